@@ -1,0 +1,121 @@
+// CPU oracle of the table-to-graph conversion -- TEST INFRASTRUCTURE ONLY.
+//
+// Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+// may load this library.  The product path never calls it and shares no code,
+// header or helper with it.
+//
+// What it computes is the plain definition of the conversion (Section 2.4,
+// "Conversion of tables to graphs"): table T with source column S and
+// destination column D gives the directed graph G = (V, E) where
+//   * V is the set of distinct values of S and D, and
+//   * every row r gives the edge (r_S, r_D);
+// and a directed graph keeps, per node, a sorted out-neighbour vector and a
+// sorted in-neighbour vector (Section 2.4; CSR layout as in Section 2.2).
+//
+// Readings taken where the paper is silent:
+//   * E is a set: repeated rows give one edge (a simple directed graph);
+//     self-loops are kept.
+//   * Nodes are listed in ascending signed 64-bit order; a neighbour is
+//     stored as its dense position in that list (a 32-bit index), so sorted
+//     by position equals sorted by identifier.
+//   * Offsets are 64-bit; the empty table gives V = 0, E = 0, offsets {0}.
+//   * V and the row count must stay below 2^31.
+//
+// The steps follow the paper's "sort-first" outline (Section 2.4): copy the
+// two columns, sort the copies, count neighbours per node, then copy the
+// neighbour lists into place.  std::sort and std::unique serve as the sort
+// and the duplicate removal; there is no blocking, packing or fusion.
+//
+// Parity: pinned by hand-worked fixtures, brute force over Python sets,
+// an independent numpy/scipy route, closed forms and invariants (tests/).
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <new>
+#include <utility>
+#include <vector>
+
+namespace {
+
+struct OracleGraph {
+  std::vector<int64_t> nodes;
+  std::vector<int64_t> out_off, in_off;
+  std::vector<int32_t> out_nbr, in_nbr;
+};
+
+// Offsets and neighbour list of one direction from (owner, neighbour) pairs
+// that are already sorted and distinct: count the neighbours of each node,
+// prefix-sum the counts, copy the neighbours.
+void build_direction(const std::vector<std::pair<int32_t, int32_t>> &pairs, int64_t V,
+                     std::vector<int64_t> &off, std::vector<int32_t> &nbr) {
+  off.assign((size_t)V + 1, 0);
+  for (const auto &p : pairs) off[(size_t)p.first + 1] += 1;
+  for (int64_t v = 0; v < V; ++v) off[(size_t)v + 1] += off[(size_t)v];
+  nbr.resize(pairs.size());
+  for (size_t i = 0; i < pairs.size(); ++i) nbr[i] = pairs[i].second;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Returns 0 on success, 1 on invalid arguments, 2 when V > 2^31 - 1,
+// 3 when host memory runs out.  On success *handle owns the result.
+int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **handle,
+                          int64_t *num_nodes, int64_t *num_edges) {
+  if (!handle || !num_nodes || !num_edges || n < 0 || n > INT32_MAX) return 1;
+  if (n > 0 && (!src || !dst)) return 1;
+  *handle = nullptr;
+  try {
+    OracleGraph *g = new OracleGraph();
+    // Node set: copy both columns, sort the copy, keep distinct values.
+    std::vector<int64_t> all;
+    all.reserve((size_t)2 * n);
+    all.insert(all.end(), src, src + n);
+    all.insert(all.end(), dst, dst + n);
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    g->nodes.swap(all);
+    const int64_t V = (int64_t)g->nodes.size();
+    if (V > INT32_MAX) {
+      delete g;
+      return 2;
+    }
+    auto index_of = [&](int64_t id) {
+      return (int32_t)(std::lower_bound(g->nodes.begin(), g->nodes.end(), id) - g->nodes.begin());
+    };
+    // Edge set: one (source index, destination index) pair per row, sorted,
+    // repeated pairs removed.
+    std::vector<std::pair<int32_t, int32_t>> e((size_t)n);
+    for (int64_t r = 0; r < n; ++r) e[(size_t)r] = {index_of(src[r]), index_of(dst[r])};
+    std::sort(e.begin(), e.end());
+    e.erase(std::unique(e.begin(), e.end()), e.end());
+    build_direction(e, V, g->out_off, g->out_nbr);
+    // In-direction: the same edges keyed by destination.
+    for (auto &p : e) std::swap(p.first, p.second);
+    std::sort(e.begin(), e.end());
+    build_direction(e, V, g->in_off, g->in_nbr);
+    *num_nodes = V;
+    *num_edges = (int64_t)e.size();
+    *handle = g;
+    return 0;
+  } catch (const std::bad_alloc &) {
+    return 3;
+  }
+}
+
+// Copies the result into caller-owned arrays of sizes V, V+1, E, V+1, E.
+void oracle_copy(const void *handle, int64_t *nodes, int64_t *out_off, int32_t *out_nbr,
+                 int64_t *in_off, int32_t *in_nbr) {
+  const OracleGraph *g = (const OracleGraph *)handle;
+  std::copy(g->nodes.begin(), g->nodes.end(), nodes);
+  std::copy(g->out_off.begin(), g->out_off.end(), out_off);
+  std::copy(g->out_nbr.begin(), g->out_nbr.end(), out_nbr);
+  std::copy(g->in_off.begin(), g->in_off.end(), in_off);
+  std::copy(g->in_nbr.begin(), g->in_nbr.end(), in_nbr);
+}
+
+void oracle_free(void *handle) { delete (OracleGraph *)handle; }
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: large inputs")
+    # Build the libraries once if nothing is built yet (CPU-only compile).
+    from paper_1503_07881_amd import build as pkg_build
+    import oracle
+    pkg_dir = os.path.dirname(pkg_build.__file__)
+    if not all(os.path.exists(os.path.join(pkg_dir, lib)) for lib in pkg_build.LIBS):
+        pkg_build.build()
+    if not os.path.exists(oracle.LIB_PATH):
+        oracle.build()
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
