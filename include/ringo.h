@@ -1,0 +1,149 @@
+/*
+ * ringo.h -- C ABI of the MI355X table-to-graph conversion library.
+ *
+ * The operation (Section 2.4, "Conversion of tables to graphs"): an edge
+ * table T with a source column S and a destination column D defines the
+ * directed graph G = (V, E) whose nodes are the distinct values found in S
+ * and D and whose edges are the pairs (r_S, r_D) of its rows.  The paper's
+ * graph keeps, for every node, a sorted out-neighbour vector and a sorted
+ * in-neighbour vector (Sections 2.2 and 2.4); this library emits the same
+ * lists in compressed-sparse-row form (the node vector plus edge vector of
+ * Section 2.2), one CSR per direction.
+ *
+ * Readings fixed by this library:
+ *   - E is a set: repeated rows give one edge; self-loops are kept.
+ *   - node_ids lists V in ascending signed 64-bit order; every 64-bit value,
+ *     INT64_MIN included, is a valid identifier.
+ *   - Neighbours are stored as 32-bit dense positions into node_ids, so each
+ *     list is strictly increasing by position and by identifier.
+ *   - The whole method runs on the GPU ("sort-first", Section 2.4): sort the
+ *     column copies, count neighbours, place the neighbour lists.
+ *
+ * Memory: unless noted otherwise, pointers named src/dst and every array in
+ * ringo_graph_t are DEVICE pointers on the current HIP device; counts and
+ * arrays of pointers passed by the caller are HOST memory.
+ *
+ * Errors: every entry point returns a ringo_status_t.  On any error the
+ * output structs are zeroed, nothing is leaked and no partial result is
+ * returned.
+ */
+#ifndef RINGO_H
+#define RINGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RINGO_OK = 0,
+  RINGO_ERR_INVALID_ARG = 1,    /* NULL pointer with rows > 0, negative or too many rows */
+  RINGO_ERR_TOO_MANY_NODES = 2, /* V > 2^31 - 1: neighbours would not fit 32 bits */
+  RINGO_ERR_OUT_OF_MEMORY = 3,  /* workspace or outputs could not be allocated */
+  RINGO_ERR_HIP = 4,            /* a HIP runtime call failed */
+  RINGO_ERR_EVICTED = 5,        /* served form: the result was evicted under the HBM budget */
+  RINGO_ERR_PENDING = 6         /* served form: the request has not finished yet */
+} ringo_status_t;
+
+/* Largest row count of one table: 2 * rows must index 32-bit slots. */
+#define RINGO_MAX_ROWS ((int64_t)2147483647)
+/* Largest node count: neighbours are 32-bit positions. */
+#define RINGO_MAX_NODES ((int64_t)2147483647)
+
+/*
+ * The converted graph (Section 2.4).  Scalars are host values, valid when
+ * the call returns; arrays are device memory owned by the library, valid
+ * once the stream passed to the call has completed, released with
+ * ringo_graph_free.
+ */
+typedef struct {
+  int64_t num_rows;     /* n: rows of the input table                          */
+  int64_t num_nodes;    /* V: distinct identifiers in src and dst              */
+  int64_t num_edges;    /* E: distinct (src, dst) pairs                        */
+  int64_t *node_ids;    /* [V]   strictly increasing, signed order             */
+  int64_t *out_offsets; /* [V+1] out_offsets[0] = 0, out_offsets[V] = E        */
+  int32_t *out_nbrs;    /* [E]   out-neighbours of v at out_offsets[v]..[v+1], */
+                        /*       strictly increasing positions into node_ids   */
+  int64_t *in_offsets;  /* [V+1] in_offsets[0] = 0, in_offsets[V] = E          */
+  int32_t *in_nbrs;     /* [E]   in-neighbours, strictly increasing            */
+  void *_alloc;         /* opaque owner of the arrays                          */
+} ringo_graph_t;
+
+/*
+ * Table-to-graph conversion of one edge table (Section 2.4).
+ *   src, dst : device arrays of num_rows int64 identifiers, caller-owned,
+ *              read-only, and valid until `stream` reaches this work.
+ *   num_rows : 0 <= num_rows <= RINGO_MAX_ROWS.  num_rows == 0 is legal:
+ *              V = E = 0, both offset arrays hold the single value 0 and
+ *              the other arrays are NULL.
+ *   out      : host struct filled on success (see ringo_graph_t).
+ *   stream   : all device work is ordered on this stream.  The call
+ *              synchronises with the stream twice to size its outputs
+ *              (after the node set and after the edge set are known) and
+ *              returns with the in-direction still enqueued.
+ * Errors: RINGO_ERR_INVALID_ARG (NULL out, NULL src/dst with rows > 0,
+ * rows out of range), RINGO_ERR_TOO_MANY_NODES, RINGO_ERR_OUT_OF_MEMORY,
+ * RINGO_ERR_HIP.
+ */
+ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int64_t num_rows,
+                                    ringo_graph_t *out, hipStream_t stream);
+
+/*
+ * Batched conversion of num_tables independent edge tables (the same
+ * operation as ringo_table_to_graph, Section 2.4, applied to each table).
+ *   src, dst : HOST arrays of num_tables DEVICE pointers.
+ *   num_rows : HOST array of num_tables row counts (each as above).
+ *   outs     : HOST array of num_tables structs, filled on success.
+ * Every phase of the pipeline runs once for the whole batch: one launch per
+ * pass covers all tables, and the batch synchronises with the stream twice
+ * in total.  outs[i] is bit-identical to ringo_table_to_graph on table i.
+ * All-or-nothing: on error every outs[i] is zeroed.
+ */
+ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,
+                                            const int64_t *const *dst, const int64_t *num_rows,
+                                            ringo_graph_t *outs, hipStream_t stream);
+
+/* Releases the arrays of a graph and zeroes *g.  Idempotent; NULL is a no-op.
+ * The caller must make sure no enqueued work still reads the arrays. */
+void ringo_graph_free(ringo_graph_t *g);
+
+/* Static, human-readable name of a status code. */
+const char *ringo_status_string(ringo_status_t s);
+
+/*
+ * Optional device allocator for workspaces and outputs (for example a
+ * framework's caching allocator).  alloc(bytes, stream, ctx) returns device
+ * memory usable in stream order on `stream`, or NULL; free_(ptr, stream, ctx)
+ * returns it.  Passing NULL for both restores the built-in allocator
+ * (stream-ordered hipMallocAsync).  Must not be changed while graphs
+ * allocated by the previous allocator are alive.
+ */
+ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stream, void *ctx),
+                                   void (*free_)(void *ptr, hipStream_t stream, void *ctx),
+                                   void *ctx);
+
+/*
+ * Tuning schedule of the radix passes: digit width (bits per pass) and
+ * items per thread of the scatter tile.  ringo_tune_get returns the schedule
+ * the library will use for a table of num_rows rows; ringo_tune_set
+ * overrides it for the size bucket holding num_rows (used by the autotuner).
+ * Valid digit widths: 8; valid items per thread: 8, 12, 16.
+ */
+typedef struct {
+  int32_t digit_bits;
+  int32_t items_per_thread;
+} ringo_schedule_t;
+ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out);
+ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched);
+
+/* Version string of the library build. */
+const char *ringo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RINGO_H */

@@ -1,0 +1,807 @@
+// gfx950 kernels of the table-to-graph conversion.
+//
+// The method is the paper's "sort-first" conversion (Section 2.4): copy the
+// source and destination columns, sort the copies, count neighbours per node
+// and place the sorted neighbour lists.  On the GPU every step is a tiled,
+// HBM-streaming pass over all tables of a batch at once:
+//
+//   node keys   2n (id ^ 2^63) keys per table, least-significant-digit radix
+//               sort, 8-bit digits (one histogram pass + 8 scatter passes)
+//   unique      head flags on the sorted keys + stream compaction -> nodes
+//   directory   bucket index over the sorted nodes for the remap lookups
+//   remap       every row's (src, dst) -> dense positions, packed into
+//               (s << b) | d with b = ceil(log2 V)
+//   edge keys   radix sort of the packed keys over their 2b low bits
+//   dedupe      adjacent compare + compaction -> unique edges, out-offsets
+//   in keys     repack to (d << 32) | s, stable radix sort on d only
+//   in-CSR      in-neighbours + in-offsets
+//
+// Each scatter pass follows the one-sweep scheme (Adinets & Merrill 2022):
+// one read and one write of the keys per pass, a tile-local stable rank
+// from 64-lane wavefront ballots, per-digit decoupled look-back (Merrill &
+// Garland 2016) across tiles for the global digit offsets, and an LDS-staged
+// write-out so that each digit run leaves the tile as one contiguous store.
+
+#include "ringo_internal.h"
+
+namespace ringo {
+
+// --------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Index s of the table whose tiles hold tile t: tmap[s] <= t < tmap[s+1].
+__device__ __forceinline__ int find_seg(const int64_t *tmap, int S, int64_t t) {
+  int lo = 0, hi = S;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tmap[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over the block; `total` receives
+// the block sum.  Every thread of the block must call it.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / 64; ++i) {
+    const uint32_t x = s_w[i];
+    off += (i < w) ? x : 0u;
+    tot += x;
+  }
+  total = tot;
+  __syncthreads();
+  return off + inc - v;
+}
+
+// ----------------------------------------------------- decoupled look-back
+//
+// Status word of (tile, digit): [63:56] launch epoch, [55:54] flag
+// (1 = tile aggregate, 2 = inclusive prefix), [53:0] value.  A word whose
+// epoch differs from the current launch's is "not yet published", so the
+// buffer is cleared once per call rather than once per pass.
+
+constexpr uint64_t ST_AGG = 1, ST_INC = 2;
+constexpr uint64_t ST_VMASK = (1ull << 54) - 1;
+
+__device__ __forceinline__ uint64_t st_pack(uint32_t epoch, uint64_t flag, uint64_t v) {
+  return ((uint64_t)epoch << 56) | (flag << 54) | v;
+}
+__device__ __forceinline__ void st_store(uint64_t *p, uint64_t w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t st_wait(const uint64_t *p, uint32_t epoch) {
+  uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while ((uint32_t)(w >> 56) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return w;
+}
+
+// First half of the look-back: publish this tile's aggregate, or its
+// inclusive prefix straight away when it opens its table or when the
+// predecessor's inclusive prefix is already visible.  Returns true with
+// *excl set when the prefix is resolved.
+__device__ __forceinline__ bool lb_publish(uint64_t *status, int64_t tile, int64_t first,
+                                           int stride, int d, uint32_t epoch, uint64_t total,
+                                           uint64_t *excl) {
+  uint64_t *own = status + tile * stride + d;
+  if (tile == first) {
+    st_store(own, st_pack(epoch, ST_INC, total));
+    *excl = 0;
+    return true;
+  }
+  const uint64_t w = __hip_atomic_load(status + (tile - 1) * stride + d, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  if ((uint32_t)(w >> 56) == epoch && ((w >> 54) & 3) == ST_INC) {
+    *excl = w & ST_VMASK;
+    st_store(own, st_pack(epoch, ST_INC, *excl + total));
+    return true;
+  }
+  st_store(own, st_pack(epoch, ST_AGG, total));
+  return false;
+}
+
+// Second half: walk back over predecessors until an inclusive prefix is
+// found (the first tile of a table always publishes one), then publish ours.
+__device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, int64_t tile, int stride, int d,
+                                               uint32_t epoch, uint64_t total) {
+  uint64_t acc = 0;
+  for (int64_t p = tile - 1;; --p) {
+    const uint64_t w = st_wait(status + p * stride + d, epoch);
+    acc += w & ST_VMASK;
+    if (((w >> 54) & 3) == ST_INC) break;
+  }
+  st_store(status + tile * stride + d, st_pack(epoch, ST_INC, acc + total));
+  return acc;
+}
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t g = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)g), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+// Tables with no rows: both offset arrays are the single value 0.
+__global__ void k_empty_offsets(const SegPlan *plan, int32_t S) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
+    if (plan[i].n == 0) {
+      plan[i].out_off[0] = 0;
+      plan[i].in_off[0] = 0;
+    }
+  }
+}
+
+hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
+  hipLaunchKernelGGL(k_empty_offsets, dim3((S + 255) / 256), dim3(256), 0, s, plan, S);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- histograms
+
+// Digit histograms of all 8 passes of the node keys, read once from the
+// input columns.  Per-wave LDS copies spread the atomics of repeated
+// identifiers; a block flushes when its tiles move to another table.
+__global__ __launch_bounds__(256) void k_hist_node(TileLaunch t, uint32_t *hist) {
+  constexpr int W = 4, H = NODE_PASSES * RADIX;
+  __shared__ uint32_t s_h[W * H];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int i = tid; i < W * H; i += 256) s_h[i] = 0;
+  __syncthreads();
+  int cur = -1;
+  auto flush = [&](int seg) {
+    __syncthreads();
+    for (int i = tid; i < H; i += 256) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        v += s_h[w * H + i];
+        s_h[w * H + i] = 0;
+      }
+      if (v) atomicAdd(&hist[(int64_t)seg * H + i], v);
+    }
+    __syncthreads();
+  };
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    if (seg != cur) {
+      if (cur >= 0) flush(cur);
+      cur = seg;
+    }
+    const SegPlan &P = t.plan[seg];
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)HIST_TILE;
+    const int64_t end = std::min<int64_t>(base + HIST_TILE, 2 * P.n);
+    uint32_t *h = s_h + wave * H;
+    for (int64_t e = base + tid; e < end; e += 256) {
+      const int64_t v = e < P.n ? P.src[e] : P.dst[e - P.n];
+      const uint64_t k = (uint64_t)v ^ SIGN_FLIP;
+#pragma unroll
+      for (int p = 0; p < NODE_PASSES; ++p)
+        atomicAdd(&h[p * RADIX + ((k >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+    }
+  }
+  if (cur >= 0) flush(cur);
+}
+
+hipError_t launch_hist_node(const TileLaunch &t, uint32_t *hist, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist_node, dim3(grid), dim3(256), 0, s, t, hist);
+  return hipGetLastError();
+}
+
+// Exclusive scan of each (table, pass) histogram into absolute positions.
+__global__ __launch_bounds__(RADIX) void k_scan_hist(const uint32_t *hist, int64_t *base,
+                                                      const SegPlan *plan, int32_t passes,
+                                                      int32_t kind) {
+  __shared__ uint32_t s_w[RADIX / 64];
+  const int seg = blockIdx.x / passes;
+  const int64_t row = (int64_t)blockIdx.x * RADIX;
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<RADIX>(hist[row + threadIdx.x], s_w, total);
+  base[row + threadIdx.x] = range_start(plan[seg], kind) + (int64_t)ex;
+}
+
+hipError_t launch_scan_hist(const uint32_t *hist, int64_t *base, const SegPlan *plan, int32_t S,
+                            int32_t passes, int32_t range_kind, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_hist, dim3(S * passes), dim3(RADIX), 0, s, hist, base, plan, passes,
+                     range_kind);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ one-sweep LSD pass
+
+template <int BLOCK, int ITEMS, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int TILE = BLOCK * ITEMS;
+  static_assert(BLOCK >= RADIX, "one thread per digit");
+  __shared__ uint64_t s_stage[TILE];
+  __shared__ uint32_t s_whist[WAVES * RADIX];
+  __shared__ uint32_t s_lstart[RADIX];
+  __shared__ int64_t s_goff[RADIX];
+  __shared__ uint32_t s_w[WAVES];
+  __shared__ int64_t s_tile;
+  __shared__ int32_t s_seg;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int shift = a.shift;
+  for (;;) {
+    if (tid == 0) {
+      const int64_t t = (int64_t)atomicAdd(a.counter, 1u);
+      s_tile = t;
+      s_seg = t < a.total_tiles ? find_seg(a.tmap, a.num_segs, t) : 0;
+    }
+    for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= a.total_tiles) break;
+    const int seg = s_seg;
+    const SegPlan &P = a.plan[seg];
+    const int64_t first = a.tmap[seg];
+    const int64_t base = (tile - first) * (int64_t)TILE;
+    const int64_t start = range_start(P, a.range_kind);
+    const int cnt = (int)std::min<int64_t>(TILE, range_count(P, a.range_kind) - base);
+
+    // Load: wave w owns the contiguous run [w * ITEMS * 64, (w + 1) * ITEMS * 64)
+    // of the tile, one coalesced 64-key row per item.
+    uint64_t keys[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+      uint64_t k = 0;
+      if (idx < cnt) {
+        const int64_t e = base + idx;
+        if (MODE == SORT_NODE_FIRST) {
+          const int64_t v = e < P.n ? P.src[e] : P.dst[e - P.n];
+          k = (uint64_t)v ^ SIGN_FLIP;
+        } else if (MODE == SORT_IN_FIRST) {
+          const uint64_t x = a.in[start + e];
+          const uint64_t d = x & ((1ull << P.b) - 1);
+          P.out_nbr[e] = (int32_t)d;  // out-neighbours, already in (s, d) order
+          k = (d << 32) | (x >> P.b);
+        } else {
+          k = a.in[start + e];
+        }
+      }
+      keys[i] = k;
+    }
+
+    // Stable rank inside the wave: lanes with an equal digit are found with
+    // RADIX_BITS ballots; the lowest such lane bumps the wave's digit count.
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const bool valid = wave * (ITEMS * 64) + i * 64 + lane < cnt;
+      const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < RADIX_BITS; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(set);
+        m &= set ? bb : ~bb;
+      }
+      const uint32_t below = lanes_below(m);
+      uint32_t r = 0;
+      if (valid) {
+        const uint32_t old = s_whist[wave * RADIX + d];
+        if (below == 0) s_whist[wave * RADIX + d] = old + (uint32_t)__popcll(m);
+        r = old + below;
+      }
+      rank[i] = r;
+    }
+    __syncthreads();
+
+    // Tile digit counts; per-wave counts become exclusive offsets.
+    uint32_t total = 0;
+    if (tid < RADIX) {
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = s_whist[w * RADIX + tid];
+        s_whist[w * RADIX + tid] = total;
+        total += c;
+      }
+    }
+    uint64_t excl = 0;
+    bool resolved = false;
+    if (tid < RADIX)
+      resolved = lb_publish(a.status, tile, first, RADIX, tid, a.epoch, total, &excl);
+    uint32_t tile_total;
+    const uint32_t lstart = block_excl_scan<BLOCK>(tid < RADIX ? total : 0u, s_w, tile_total);
+    if (tid < RADIX) s_lstart[tid] = lstart;
+    __syncthreads();
+
+    // Stage the tile in LDS in digit order.
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      if (wave * (ITEMS * 64) + i * 64 + lane < cnt) {
+        const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
+        s_stage[s_lstart[d] + s_whist[wave * RADIX + d] + rank[i]] = keys[i];
+      }
+    }
+    if (tid < RADIX) {
+      if (!resolved) excl = lb_resolve(a.status, tile, RADIX, tid, a.epoch, total);
+      s_goff[tid] = a.digit_base[(int64_t)seg * a.base_stride + a.pass * RADIX + tid] +
+                    (int64_t)excl - (int64_t)lstart;
+    }
+    __syncthreads();
+
+    // Write out: consecutive threads take consecutive staged keys, so every
+    // digit run is stored contiguously.
+    const int64_t lim = range_count(P, a.range_kind);
+    for (int p = tid; p < cnt; p += BLOCK) {
+      const uint64_t k = s_stage[p];
+      const int64_t pos = s_goff[(uint32_t)(k >> shift) & (RADIX - 1)] + p;
+      if ((uint64_t)(pos - start) < (uint64_t)lim) a.out[pos] = k;  // in range by construction
+    }
+    __syncthreads();
+  }
+}
+
+template <int BLOCK, int ITEMS>
+static hipError_t launch_sort_t(const SortLaunch &a, int mode, int grid, hipStream_t s) {
+  switch (mode) {
+    case SORT_NODE_FIRST:
+      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_NODE_FIRST>), dim3(grid), dim3(BLOCK), 0,
+                         s, a);
+      break;
+    case SORT_IN_FIRST:
+      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_IN_FIRST>), dim3(grid), dim3(BLOCK), 0, s,
+                         a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_PLAIN>), dim3(grid), dim3(BLOCK), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int sort_tile(int items) { return 256 * items; }
+
+template <int BLOCK, int ITEMS>
+static int max_grid_t(int mode) {
+  int nb = 0;
+  hipError_t e;
+  switch (mode) {
+    case SORT_NODE_FIRST:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, k_sort_pass<BLOCK, ITEMS, SORT_NODE_FIRST>, BLOCK, 0);
+      break;
+    case SORT_IN_FIRST:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, k_sort_pass<BLOCK, ITEMS, SORT_IN_FIRST>, BLOCK, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass<BLOCK, ITEMS, SORT_PLAIN>,
+                                                       BLOCK, 0);
+  }
+  if (e != hipSuccess || nb < 1) nb = 1;
+  return nb * device_cu_count();
+}
+
+int sort_max_grid(int items, int mode) {
+  switch (items) {
+    case 8: return max_grid_t<256, 8>(mode);
+    case 12: return max_grid_t<256, 12>(mode);
+    default: return max_grid_t<256, 16>(mode);
+  }
+}
+
+hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, int grid, hipStream_t s) {
+  if (a.total_tiles == 0) return hipSuccess;
+  switch (items) {
+    case 8: return launch_sort_t<256, 8>(a, mode, grid, s);
+    case 12: return launch_sort_t<256, 12>(a, mode, grid, s);
+    default: return launch_sort_t<256, 16>(a, mode, grid, s);
+  }
+}
+
+// ------------------------------------------------------ unique (node set)
+//
+// Head flags on the sorted node keys, stream compaction of the heads into
+// the node list, per-table node count.  A tile is processed as ITEMS rows
+// of BLOCK keys; the head count of each (row, wave) pair is a ballot, and
+// the pairs are scanned in index order by one wave.
+
+template <int BLOCK, int ITEMS>
+struct CompactTile {
+  static constexpr int WAVES = BLOCK / 64;
+  static constexpr int TILE = BLOCK * ITEMS;
+  static_assert(ITEMS * WAVES <= 64, "one wave scans the row counts");
+};
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_unique(TileLaunch t, const uint64_t *in,
+                                                       uint64_t *out, int64_t *seg_count,
+                                                       uint64_t *status, uint32_t *counter,
+                                                       uint32_t epoch) {
+  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
+  __shared__ uint64_t s_k[TILE];
+  __shared__ uint32_t s_cnt[64];
+  __shared__ int64_t s_tile, s_prefix, s_total;
+  __shared__ int32_t s_seg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (;;) {
+    if (tid == 0) {
+      const int64_t tt = (int64_t)atomicAdd(counter, 1u);
+      s_tile = tt;
+      s_seg = tt < t.total_tiles ? find_seg(t.tmap, t.num_segs, tt) : 0;
+    }
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= t.total_tiles) break;
+    const int seg = s_seg;
+    const SegPlan &P = t.plan[seg];
+    const int64_t first = t.tmap[seg];
+    const int64_t base = (tile - first) * (int64_t)TILE;
+    const int64_t start = range_start(P, t.range_kind);
+    const int64_t count = range_count(P, t.range_kind);
+    const int cnt = (int)std::min<int64_t>(TILE, count - base);
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      if (idx < cnt) s_k[idx] = in[start + base + idx];
+    }
+    const uint64_t before = base > 0 ? in[start + base - 1] : 0;
+    __syncthreads();
+    uint64_t heads[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      bool h = false;
+      if (idx < cnt) {
+        const uint64_t k = s_k[idx];
+        h = (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
+      }
+      heads[i] = __ballot(h);
+      if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const uint32_t v = s_cnt[lane];
+      const uint32_t inc = wave_incl_scan(v, lane);
+      s_cnt[lane] = inc - v;
+      const uint32_t tot = __shfl(inc, 63, 64);
+      if (lane == 0) {
+        uint64_t ex;
+        if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
+          ex = lb_resolve(status, tile, 1, 0, epoch, tot);
+        s_prefix = (int64_t)ex;
+        s_total = (int64_t)ex + tot;
+      }
+    }
+    __syncthreads();
+    const int64_t prefix = s_prefix;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      if ((heads[i] >> lane) & 1ull) {
+        const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
+        if (j < count) out[start + j] = s_k[idx];
+      }
+    }
+    if (tid == 0 && base + cnt == count) seg_count[seg] = s_total;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
+                         uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
+                         hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unique, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count, status,
+                     counter, epoch);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- node directory
+//
+// Bucket index over the sorted node keys of a table: bucket q holds the
+// keys whose (key - lo) >> shift equals q, and dir[q] is the position of its
+// first key, with 2^dirk buckets (about one key per bucket for spread-out
+// identifiers).  The same pass writes the node identifiers of the output.
+
+__device__ __forceinline__ int dir_shift(uint64_t lo, uint64_t hi, int dirk) {
+  const uint64_t range = hi - lo;
+  const int bits = range == 0 ? 0 : 64 - __clzll((long long)range);
+  return bits > dirk ? bits - dirk : 0;
+}
+
+__global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes, uint32_t *dir) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan &P = t.plan[seg];
+    const uint64_t *nd = nodes + 2 * P.row_off;
+    const uint64_t lo = nd[0], hi = nd[P.V - 1];
+    const int shift = dir_shift(lo, hi, P.dirk);
+    uint32_t *D = dir + P.dir_off;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)DIR_TILE;
+    const int64_t end = std::min<int64_t>(base + DIR_TILE, P.V);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
+      const uint64_t u = nd[j];
+      P.node_ids[j] = (int64_t)(u ^ SIGN_FLIP);
+      const int64_t q = (int64_t)((u - lo) >> shift);
+      const int64_t qp = j == 0 ? -1 : (int64_t)((nd[j - 1] - lo) >> shift);
+      for (int64_t x = qp + 1; x <= q; ++x) D[x] = (uint32_t)j;
+      if (j == P.V - 1) {
+        const int64_t nb = (int64_t)1 << P.dirk;
+        for (int64_t x = q + 1; x <= nb; ++x) D[x] = (uint32_t)P.V;
+      }
+    }
+  }
+}
+
+hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, uint32_t *dir, int grid,
+                      hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dir, dim3(grid), dim3(256), 0, s, t, nodes, dir);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- remap
+//
+// Dense position of every row's source and destination (merge-rank against
+// the sorted node list through the bucket directory), packed into the edge
+// key (s << b) | d; the digit histograms of the edge sort ride along.
+
+__device__ __forceinline__ uint32_t node_rank(const uint64_t *nd, const uint32_t *D, uint64_t lo,
+                                              int shift, uint64_t nbuckets, uint64_t u) {
+  uint64_t q = (u - lo) >> shift;
+  if (q >= nbuckets) q = nbuckets - 1;  // only for keys outside the table's range
+  uint32_t a = D[q], e = D[q + 1];
+  while (e - a > 1) {
+    const uint32_t m = (a + e) >> 1;
+    if (nd[m] <= u) a = m; else e = m;
+  }
+  return a;
+}
+
+__global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nodes,
+                                               const uint32_t *dir, uint64_t *ekeys,
+                                               uint32_t *hist, int32_t passes) {
+  __shared__ uint32_t s_h[MAX_PASSES * RADIX];
+  const int tid = threadIdx.x;
+  const int H = passes * RADIX;
+  for (int i = tid; i < H; i += 256) s_h[i] = 0;
+  __syncthreads();
+  int cur = -1;
+  auto flush = [&](int seg) {
+    __syncthreads();
+    for (int i = tid; i < H; i += 256) {
+      const uint32_t v = s_h[i];
+      s_h[i] = 0;
+      if (v) atomicAdd(&hist[(int64_t)seg * H + i], v);
+    }
+    __syncthreads();
+  };
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    if (seg != cur) {
+      if (cur >= 0) flush(cur);
+      cur = seg;
+    }
+    const SegPlan &P = t.plan[seg];
+    const uint64_t *nd = nodes + 2 * P.row_off;
+    const uint64_t lo = nd[0], hi = nd[P.V - 1];
+    const int shift = dir_shift(lo, hi, P.dirk);
+    const uint32_t *D = dir + P.dir_off;
+    const uint64_t nb = 1ull << P.dirk;
+    const int b = P.b;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    for (int64_t r = base + tid; r < end; r += 256) {
+      const uint64_t s = node_rank(nd, D, lo, shift, nb, (uint64_t)P.src[r] ^ SIGN_FLIP);
+      const uint64_t d = node_rank(nd, D, lo, shift, nb, (uint64_t)P.dst[r] ^ SIGN_FLIP);
+      const uint64_t k = (s << b) | d;
+      ekeys[P.row_off + r] = k;
+      for (int p = 0; p < passes; ++p)
+        atomicAdd(&s_h[p * RADIX + ((k >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+    }
+  }
+  if (cur >= 0) flush(cur);
+}
+
+hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const uint32_t *dir,
+                        uint64_t *ekeys, uint32_t *hist, int32_t passes, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys, hist, passes);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- dedupe
+//
+// Adjacent compare of the sorted edge keys, compaction of the first copy of
+// every edge, out-offsets by boundary fill (out_off[v] = position of the
+// first edge whose source is >= v), and the digit histograms of the in-sort
+// (digits of the destination) over the unique edges.
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint64_t *in,
+                                                       uint64_t *out, int64_t *seg_count,
+                                                       uint32_t *hist, int32_t passes,
+                                                       uint64_t *status, uint32_t *counter,
+                                                       uint32_t epoch) {
+  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
+  __shared__ uint64_t s_k[TILE];
+  __shared__ uint32_t s_cnt[64];
+  __shared__ uint32_t s_h[MAX_PASSES * RADIX];
+  __shared__ int64_t s_tile, s_prefix, s_total;
+  __shared__ int32_t s_seg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int H = passes * RADIX;
+  for (int i = tid; i < H; i += BLOCK) s_h[i] = 0;
+  int cur = -1;
+  for (;;) {
+    if (tid == 0) {
+      const int64_t tt = (int64_t)atomicAdd(counter, 1u);
+      s_tile = tt;
+      s_seg = tt < t.total_tiles ? find_seg(t.tmap, t.num_segs, tt) : 0;
+    }
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= t.total_tiles) break;
+    const int seg = s_seg;
+    if (seg != cur) {
+      if (cur >= 0) {
+        for (int i = tid; i < H; i += BLOCK) {
+          const uint32_t v = s_h[i];
+          s_h[i] = 0;
+          if (v) atomicAdd(&hist[(int64_t)cur * H + i], v);
+        }
+        __syncthreads();
+      }
+      cur = seg;
+    }
+    const SegPlan &P = t.plan[seg];
+    const int64_t first = t.tmap[seg];
+    const int64_t base = (tile - first) * (int64_t)TILE;
+    const int64_t start = P.row_off;
+    const int64_t count = P.n;
+    const int cnt = (int)std::min<int64_t>(TILE, count - base);
+    const int b = P.b;
+    const uint64_t dmask = (1ull << b) - 1;
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      if (idx < cnt) s_k[idx] = in[start + base + idx];
+    }
+    const uint64_t before = base > 0 ? in[start + base - 1] : 0;
+    __syncthreads();
+    uint64_t heads[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      bool h = false;
+      if (idx < cnt) {
+        const uint64_t k = s_k[idx];
+        h = (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
+        if (h) {
+          const uint64_t d = k & dmask;
+          for (int p = 0; p < passes; ++p)
+            atomicAdd(&s_h[p * RADIX + ((d >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+        }
+      }
+      heads[i] = __ballot(h);
+      if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const uint32_t v = s_cnt[lane];
+      const uint32_t inc = wave_incl_scan(v, lane);
+      s_cnt[lane] = inc - v;
+      const uint32_t tot = __shfl(inc, 63, 64);
+      if (lane == 0) {
+        uint64_t ex;
+        if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
+          ex = lb_resolve(status, tile, 1, 0, epoch, tot);
+        s_prefix = (int64_t)ex;
+        s_total = (int64_t)ex + tot;
+      }
+    }
+    __syncthreads();
+    const int64_t prefix = s_prefix;
+    const bool last_tile = base + cnt == count;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = i * BLOCK + tid;
+      if ((heads[i] >> lane) & 1ull) {
+        const uint64_t k = s_k[idx];
+        const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
+        if (j < count) out[start + j] = k;
+        const int64_t hsrc = std::min<int64_t>((int64_t)(k >> b), P.V - 1);
+        const int64_t hp =
+            (base + idx == 0) ? -1 : (int64_t)((idx > 0 ? s_k[idx - 1] : before) >> b);
+        for (int64_t v = hp + 1; v <= hsrc; ++v) P.out_off[v] = j;
+      }
+      if (last_tile && idx == cnt - 1) {
+        // the last row of the table closes the offsets
+        const int64_t E = s_total;
+        for (int64_t v = std::min<int64_t>((int64_t)(s_k[idx] >> b), P.V - 1) + 1; v <= P.V; ++v)
+          P.out_off[v] = E;
+      }
+    }
+    if (tid == 0 && last_tile) seg_count[seg] = s_total;
+    __syncthreads();
+  }
+  if (cur >= 0) {
+    for (int i = tid; i < H; i += BLOCK) {
+      const uint32_t v = s_h[i];
+      if (v) atomicAdd(&hist[(int64_t)cur * H + i], v);
+    }
+  }
+}
+
+hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
+                         int64_t *seg_count, uint32_t *hist, int32_t passes, uint64_t *status,
+                         uint32_t *counter, uint32_t epoch, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dedupe, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count, hist,
+                     passes, status, counter, epoch);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- in-CSR
+//
+// The unique edges sorted by (d, s): in-neighbours are the low words, and
+// in_off[v] is the position of the first edge whose destination is >= v.
+
+__global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan &P = t.plan[seg];
+    const uint64_t *K = in + P.row_off;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
+    const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.E);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
+      const uint64_t k = K[j];
+      P.in_nbr[j] = (int32_t)(uint32_t)k;
+      const int64_t h = std::min<int64_t>((int64_t)(k >> 32), P.V - 1);
+      const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(K[j - 1] >> 32), P.V - 1);
+      for (int64_t v = hp + 1; v <= h; ++v) P.in_off[v] = j;
+      if (j == P.E - 1)
+        for (int64_t v = h + 1; v <= P.V; ++v) P.in_off[v] = P.E;
+    }
+  }
+}
+
+hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_in_csr, dim3(grid), dim3(256), 0, s, t, in);
+  return hipGetLastError();
+}
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+}  // namespace ringo

@@ -1,0 +1,575 @@
+// Host side of libringo: the C ABI, the memory planner and the pass driver.
+//
+// One call converts S >= 1 tables.  Every phase runs once for the whole
+// batch, each kernel walking the tiles of all tables:
+//
+//   phase N  node histogram, 8 radix passes over the 2n node keys, unique
+//   sync #1  read back V of every table, size the node-sized outputs
+//   phase E  directory, remap + pack, radix passes over the packed edge
+//            keys, dedupe + out-offsets
+//   sync #2  read back E of every table, size the edge-sized outputs
+//   phase I  radix passes over the (d, s) keys (the first one also writes
+//            the out-neighbours), in-CSR
+//
+// Everything is enqueued on the caller's stream; the two synchronisations
+// exist only to size the outputs exactly ("no need to estimate the size of
+// the hash table or neighbor vectors in advance", Section 2.4).
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "ringo.h"
+#include "ringo_internal.h"
+
+using namespace ringo;
+
+namespace {
+
+// ----------------------------------------------------------- allocation
+
+struct AllocHooks {
+  void *(*alloc)(size_t, hipStream_t, void *) = nullptr;
+  void (*free_)(void *, hipStream_t, void *) = nullptr;
+  void *ctx = nullptr;
+};
+
+std::mutex g_mu;
+AllocHooks g_hooks;
+bool g_pool_ready[64] = {false};
+
+AllocHooks hooks() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_hooks;
+}
+
+void prepare_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;  // keep freed blocks cached in the pool
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  g_pool_ready[dev] = true;
+}
+
+void *dev_alloc(const AllocHooks &h, size_t bytes, hipStream_t s) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (h.alloc) return h.alloc(bytes, s, h.ctx);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(const AllocHooks &h, void *p, hipStream_t s) {
+  if (!p) return;
+  if (h.free_) h.free_(p, s, h.ctx);
+  else (void)hipFreeAsync(p, s);
+}
+
+// Owner of the output arrays of one call (shared by the graphs of a batch).
+struct Owner {
+  std::atomic<int> refs{0};
+  void *blocks[2] = {nullptr, nullptr};
+  hipStream_t stream = nullptr;
+  AllocHooks hooks;
+};
+
+void owner_release(Owner *o) {
+  if (!o) return;
+  if (o->refs.fetch_sub(1) == 1) {
+    for (void *b : o->blocks) dev_free(o->hooks, b, o->stream);
+    delete o;
+  }
+}
+
+// Pinned staging buffers for plan uploads and count read-backs.  A buffer
+// returns to the pool with an event recorded after its last copy.
+struct Pinned {
+  void *p = nullptr;
+  size_t size = 0;
+  hipEvent_t ev = nullptr;
+  bool busy = false;
+};
+std::vector<Pinned *> g_pinned;
+
+Pinned *pinned_acquire(size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Pinned *b : g_pinned)
+    if (!b->busy && b->size >= bytes && hipEventQuery(b->ev) == hipSuccess) {
+      b->busy = true;
+      return b;
+    }
+  Pinned *b = new Pinned();
+  bytes = std::max<size_t>(bytes, 1 << 16);
+  if (hipHostMalloc(&b->p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete b;
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(b->p);
+    delete b;
+    return nullptr;
+  }
+  b->size = bytes;
+  b->busy = true;
+  g_pinned.push_back(b);
+  return b;
+}
+
+void pinned_release(Pinned *b, hipStream_t s) {
+  if (!b) return;
+  (void)hipEventRecord(b->ev, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  b->busy = false;
+}
+
+// ------------------------------------------------------------- schedule
+
+// Items per thread of the scatter tile by table size (log2 buckets).
+int g_items[64];
+bool g_items_init = false;
+
+int items_for(int64_t rows) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_items_init) {
+    for (int i = 0; i < 64; ++i) g_items[i] = 16;
+    g_items_init = true;
+  }
+  return g_items[ceil_log2(std::max<int64_t>(rows, 1))];
+}
+
+// ----------------------------------------------------------- tile maps
+
+enum TileKind {
+  TM_HIST, TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR, TM_KINDS
+};
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Call {
+  int S = 0;
+  hipStream_t stream = nullptr;
+  AllocHooks hooks;
+  int items = 16;
+  int sort_tile = 4096;
+  std::vector<SegPlan> plan;
+  std::vector<int64_t> tmap;  // TM_KINDS x (S + 1)
+
+  // device workspace
+  uint64_t *A = nullptr, *B = nullptr;
+  uint64_t *status = nullptr;
+  uint32_t *hist = nullptr;
+  int64_t *base = nullptr;
+  uint32_t *counters = nullptr;
+  int64_t *results = nullptr;
+  uint8_t *meta = nullptr;
+  uint32_t *dir = nullptr;
+  size_t meta_bytes = 0;
+  Pinned *pin = nullptr;
+  int upload_slot = 0;
+  uint32_t epoch = 0;
+  Owner *owner = nullptr;
+
+  ~Call() { release_workspace(); }
+
+  void release_workspace() {
+    void *bufs[] = {A, B, status, hist, base, counters, results, meta, dir};
+    for (void *b : bufs) dev_free(hooks, b, stream);
+    A = B = nullptr;
+    status = nullptr;
+    hist = nullptr;
+    base = nullptr;
+    counters = nullptr;
+    results = nullptr;
+    meta = nullptr;
+    dir = nullptr;
+    if (pin) pinned_release(pin, stream);
+    pin = nullptr;
+  }
+
+  int64_t *tm(int kind) { return tmap.data() + (size_t)kind * (S + 1); }
+  const int64_t *tm_dev(int kind) const {
+    return (const int64_t *)(meta + align_up(sizeof(SegPlan) * S)) + (size_t)kind * (S + 1);
+  }
+  const SegPlan *plan_dev() const { return (const SegPlan *)meta; }
+
+  void set_tiles(int kind, int range, int64_t tile) {
+    int64_t *t = tm(kind);
+    t[0] = 0;
+    for (int i = 0; i < S; ++i) {
+      const int64_t c = range_count(plan[i], range);
+      t[i + 1] = t[i] + (c + tile - 1) / tile;
+    }
+  }
+  int64_t total(int kind) { return tm(kind)[S]; }
+
+  TileLaunch tiles(int kind, int range) {
+    TileLaunch t;
+    t.plan = plan_dev();
+    t.tmap = tm_dev(kind);
+    t.num_segs = S;
+    t.range_kind = range;
+    t.total_tiles = total(kind);
+    return t;
+  }
+
+  hipError_t upload() {
+    char *stage = (char *)pin->p + (size_t)upload_slot * meta_bytes;
+    ++upload_slot;
+    std::memcpy(stage, plan.data(), sizeof(SegPlan) * S);
+    std::memcpy(stage + align_up(sizeof(SegPlan) * S), tmap.data(), sizeof(int64_t) * tmap.size());
+    return hipMemcpyAsync(meta, stage, meta_bytes, hipMemcpyHostToDevice, stream);
+  }
+
+  // Read back S counts from results[off..off+S) and wait for the stream.
+  hipError_t readback(int off, std::vector<int64_t> &v) {
+    int64_t *host = (int64_t *)((char *)pin->p + 3 * meta_bytes);
+    hipError_t e = hipMemcpyAsync(host, results + off, sizeof(int64_t) * S, hipMemcpyDeviceToHost,
+                                  stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    v.assign(host, host + S);
+    return hipSuccess;
+  }
+
+  SortLaunch sort_args(const uint64_t *in, uint64_t *out, int kind, int range, int passes, int pass,
+                       int shift) {
+    SortLaunch a;
+    a.in = in;
+    a.out = out;
+    a.plan = plan_dev();
+    a.tmap = tm_dev(kind);
+    a.num_segs = S;
+    a.range_kind = range;
+    a.total_tiles = total(kind);
+    a.digit_base = base;
+    a.base_stride = passes * RADIX;
+    a.pass = pass;
+    a.shift = shift;
+    a.epoch = ++epoch;
+    a.status = status;
+    a.counter = counters + a.epoch;
+    return a;
+  }
+};
+
+int grid_for(int64_t tiles, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
+}
+
+#define HIP_TRY(x)                                  \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) return RINGO_ERR_HIP;     \
+  } while (0)
+
+ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst,
+                   const int64_t *num_rows, ringo_graph_t *outs) {
+  const int S = c.S;
+  hipStream_t st = c.stream;
+  const int cus = device_cu_count();
+
+  // ---------------------------------------------------------------- plan N
+  c.plan.assign(S, SegPlan{});
+  c.tmap.assign((size_t)TM_KINDS * (S + 1), 0);
+  int64_t N = 0, max_rows = 0;
+  for (int i = 0; i < S; ++i) {
+    SegPlan &p = c.plan[i];
+    p.src = src[i];
+    p.dst = dst[i];
+    p.n = num_rows[i];
+    p.row_off = N;
+    N += p.n;
+    max_rows = std::max(max_rows, p.n);
+  }
+  c.items = items_for(S == 1 ? max_rows : N);
+  c.sort_tile = sort_tile(c.items);
+  c.set_tiles(TM_HIST, RANGE_NODE_KEYS, HIST_TILE);
+  c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
+  c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
+
+  const int64_t status_words =
+      std::max<int64_t>(c.total(TM_NSORT) * RADIX, c.total(TM_UNIQ)) + RADIX;
+  c.meta_bytes = align_up(align_up(sizeof(SegPlan) * S) + sizeof(int64_t) * c.tmap.size());
+  c.pin = pinned_acquire(3 * c.meta_bytes + sizeof(int64_t) * S);
+  if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
+
+  const size_t hist_words = (size_t)S * MAX_PASSES * RADIX;
+  c.A = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
+  c.B = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
+  c.status = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * status_words, st);
+  c.hist = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * hist_words, st);
+  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * hist_words, st);
+  c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
+  c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * 2 * S, st);
+  c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
+  if (!c.A || !c.B || !c.status || !c.hist || !c.base || !c.counters || !c.results || !c.meta)
+    return RINGO_ERR_OUT_OF_MEMORY;
+
+  HIP_TRY(c.upload());
+  HIP_TRY(launch_fill_u64(c.status, 0, status_words, st));
+  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
+  HIP_TRY(launch_fill_u64((uint64_t *)c.counters, 0, 128, st));
+  HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
+
+  // ------------------------------------------------------------- phase N
+  HIP_TRY(launch_hist_node(c.tiles(TM_HIST, RANGE_NODE_KEYS), c.hist,
+                           grid_for(c.total(TM_HIST), cus * 4), st));
+  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, NODE_PASSES, RANGE_NODE_KEYS, st));
+  uint64_t *buf[2] = {c.A, c.B};
+  {
+    const int g0 = grid_for(c.total(TM_NSORT), sort_max_grid(c.items, SORT_NODE_FIRST));
+    const int g1 = grid_for(c.total(TM_NSORT), sort_max_grid(c.items, SORT_PLAIN));
+    for (int p = 0; p < NODE_PASSES; ++p) {
+      SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
+                                 RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
+      HIP_TRY(launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
+                               st));
+    }
+  }
+  uint64_t *sorted_nodes = buf[(NODE_PASSES - 1) & 1];
+  uint64_t *nodes_ws = buf[NODE_PASSES & 1];
+  {
+    const uint32_t ep = ++c.epoch;
+    HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), sorted_nodes, nodes_ws, c.results,
+                          c.status, c.counters + ep, ep, grid_for(c.total(TM_UNIQ), cus * 4), st));
+  }
+
+  // -------------------------------------------------------------- sync #1
+  std::vector<int64_t> V;
+  HIP_TRY(c.readback(0, V));
+  int b_max = 1;
+  int64_t dir_words = 0;
+  size_t arena1 = 0;
+  std::vector<size_t> off1(3 * (size_t)S);
+  for (int i = 0; i < S; ++i) {
+    if (V[i] > RINGO_MAX_NODES) return RINGO_ERR_TOO_MANY_NODES;
+    SegPlan &p = c.plan[i];
+    p.V = V[i];
+    p.dirk = p.V > 0 ? ceil_log2(p.V) : 0;
+    p.b = std::max(1, p.dirk);
+    b_max = std::max(b_max, p.V > 0 ? p.b : 1);
+    p.dir_off = dir_words;
+    dir_words += p.V > 0 ? ((int64_t)1 << p.dirk) + 1 : 0;
+    off1[3 * i] = arena1;
+    arena1 = align_up(arena1 + sizeof(int64_t) * p.V);
+    off1[3 * i + 1] = arena1;
+    arena1 = align_up(arena1 + sizeof(int64_t) * (p.V + 1));
+    off1[3 * i + 2] = arena1;
+    arena1 = align_up(arena1 + sizeof(int64_t) * (p.V + 1));
+  }
+  c.owner = new Owner();
+  c.owner->stream = st;
+  c.owner->hooks = c.hooks;
+  c.owner->blocks[0] = dev_alloc(c.hooks, arena1, st);
+  c.dir = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * dir_words, st);
+  if (!c.owner->blocks[0] || !c.dir) return RINGO_ERR_OUT_OF_MEMORY;
+  char *a1 = (char *)c.owner->blocks[0];
+  for (int i = 0; i < S; ++i) {
+    SegPlan &p = c.plan[i];
+    p.node_ids = (int64_t *)(a1 + off1[3 * i]);
+    p.out_off = (int64_t *)(a1 + off1[3 * i + 1]);
+    p.in_off = (int64_t *)(a1 + off1[3 * i + 2]);
+  }
+  const int P_e = (2 * b_max + RADIX_BITS - 1) / RADIX_BITS;
+  const int P_in = (b_max + RADIX_BITS - 1) / RADIX_BITS;
+  c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
+  c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
+  c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
+  c.set_tiles(TM_DEDUP, RANGE_ROWS, SCAN_TILE);
+  HIP_TRY(c.upload());
+
+  // ------------------------------------------------------------- phase E
+  HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
+  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
+  HIP_TRY(launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
+                     grid_for(c.total(TM_DIR), cus * 8), st));
+  // the sorted node keys are consumed: their buffer takes the edge keys
+  uint64_t *ebuf[2] = {sorted_nodes, nodes_ws};
+  HIP_TRY(launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0], c.hist, P_e,
+                       grid_for(c.total(TM_REMAP), cus * 8), st));
+  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_e, RANGE_ROWS, st));
+  {
+    const int g = grid_for(c.total(TM_ESORT), sort_max_grid(c.items, SORT_PLAIN));
+    for (int p = 0; p < P_e; ++p) {
+      SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
+                                 RADIX_BITS * p);
+      HIP_TRY(launch_sort_pass(a, SORT_PLAIN, c.items, g, st));
+    }
+  }
+  uint64_t *sorted_edges = ebuf[P_e & 1];
+  uint64_t *ukeys = ebuf[(P_e + 1) & 1];
+  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
+  {
+    const uint32_t ep = ++c.epoch;
+    HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, RANGE_ROWS), sorted_edges, ukeys, c.results + S,
+                          c.hist, P_in, c.status, c.counters + ep, ep,
+                          grid_for(c.total(TM_DEDUP), cus * 4), st));
+  }
+
+  // -------------------------------------------------------------- sync #2
+  std::vector<int64_t> E;
+  HIP_TRY(c.readback(S, E));
+  size_t arena2 = 0;
+  std::vector<size_t> off2(2 * (size_t)S);
+  for (int i = 0; i < S; ++i) {
+    c.plan[i].E = E[i];
+    off2[2 * i] = arena2;
+    arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
+    off2[2 * i + 1] = arena2;
+    arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
+  }
+  c.owner->blocks[1] = dev_alloc(c.hooks, arena2, st);
+  if (!c.owner->blocks[1]) return RINGO_ERR_OUT_OF_MEMORY;
+  char *a2 = (char *)c.owner->blocks[1];
+  for (int i = 0; i < S; ++i) {
+    c.plan[i].out_nbr = (int32_t *)(a2 + off2[2 * i]);
+    c.plan[i].in_nbr = (int32_t *)(a2 + off2[2 * i + 1]);
+  }
+  c.set_tiles(TM_ISORT, RANGE_EDGES, c.sort_tile);
+  c.set_tiles(TM_ICSR, RANGE_EDGES, SCAN_TILE);
+  HIP_TRY(c.upload());
+
+  // ------------------------------------------------------------- phase I
+  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_in, RANGE_EDGES, st));
+  uint64_t *ibuf[2] = {ukeys, sorted_edges};
+  {
+    const int g0 = grid_for(c.total(TM_ISORT), sort_max_grid(c.items, SORT_IN_FIRST));
+    const int g1 = grid_for(c.total(TM_ISORT), sort_max_grid(c.items, SORT_PLAIN));
+    for (int p = 0; p < P_in; ++p) {
+      SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
+                                 32 + RADIX_BITS * p);
+      HIP_TRY(launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
+                               st));
+    }
+  }
+  HIP_TRY(launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1],
+                        grid_for(c.total(TM_ICSR), cus * 8), st));
+
+  // ------------------------------------------------------------- handoff
+  c.owner->refs.store(S);
+  for (int i = 0; i < S; ++i) {
+    const SegPlan &p = c.plan[i];
+    ringo_graph_t &g = outs[i];
+    g.num_rows = p.n;
+    g.num_nodes = p.V;
+    g.num_edges = p.E;
+    g.node_ids = p.V > 0 ? p.node_ids : nullptr;
+    g.out_offsets = p.out_off;
+    g.out_nbrs = p.E > 0 ? p.out_nbr : nullptr;
+    g.in_offsets = p.in_off;
+    g.in_nbrs = p.E > 0 ? p.in_nbr : nullptr;
+    g._alloc = c.owner;
+  }
+  c.owner = nullptr;  // now owned by the graphs
+  return RINGO_OK;
+}
+
+ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *const *dst,
+                       const int64_t *num_rows, ringo_graph_t *outs, hipStream_t stream) {
+  if (S < 0 || (S > 0 && (!src || !dst || !num_rows || !outs))) return RINGO_ERR_INVALID_ARG;
+  for (int i = 0; i < S; ++i) std::memset(&outs[i], 0, sizeof(ringo_graph_t));
+  for (int i = 0; i < S; ++i) {
+    if (num_rows[i] < 0 || num_rows[i] > RINGO_MAX_ROWS) return RINGO_ERR_INVALID_ARG;
+    if (num_rows[i] > 0 && (!src[i] || !dst[i])) return RINGO_ERR_INVALID_ARG;
+  }
+  if (S == 0) return RINGO_OK;
+  (void)hipGetLastError();
+  prepare_pool();
+  Call c;
+  c.S = S;
+  c.stream = stream;
+  c.hooks = hooks();
+  ringo_status_t rc = run(c, src, dst, num_rows, outs);
+  if (rc != RINGO_OK) {
+    // drain what was enqueued before releasing anything it may touch
+    (void)hipStreamSynchronize(stream);
+    (void)hipGetLastError();
+    if (c.owner) {
+      for (void *b : c.owner->blocks) dev_free(c.hooks, b, stream);
+      delete c.owner;
+      c.owner = nullptr;
+    }
+    for (int i = 0; i < S; ++i) std::memset(&outs[i], 0, sizeof(ringo_graph_t));
+  }
+  c.release_workspace();
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int64_t num_rows,
+                                    ringo_graph_t *out, hipStream_t stream) {
+  if (!out) return RINGO_ERR_INVALID_ARG;
+  return convert(1, &src, &dst, &num_rows, out, stream);
+}
+
+ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,
+                                            const int64_t *const *dst, const int64_t *num_rows,
+                                            ringo_graph_t *outs, hipStream_t stream) {
+  return convert(num_tables, src, dst, num_rows, outs, stream);
+}
+
+void ringo_graph_free(ringo_graph_t *g) {
+  if (!g) return;
+  owner_release((Owner *)g->_alloc);
+  std::memset(g, 0, sizeof(*g));
+}
+
+const char *ringo_status_string(ringo_status_t s) {
+  switch (s) {
+    case RINGO_OK: return "ok";
+    case RINGO_ERR_INVALID_ARG: return "invalid argument";
+    case RINGO_ERR_TOO_MANY_NODES: return "too many nodes (V > 2^31 - 1)";
+    case RINGO_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RINGO_ERR_HIP: return "HIP runtime error";
+    case RINGO_ERR_EVICTED: return "result evicted";
+    case RINGO_ERR_PENDING: return "request pending";
+  }
+  return "unknown status";
+}
+
+ringo_status_t ringo_set_allocator(void *(*alloc)(size_t, hipStream_t, void *),
+                                   void (*free_)(void *, hipStream_t, void *), void *ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return RINGO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_hooks.alloc = alloc;
+  g_hooks.free_ = free_;
+  g_hooks.ctx = alloc ? ctx : nullptr;
+  return RINGO_OK;
+}
+
+ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out) {
+  if (!out || num_rows < 0) return RINGO_ERR_INVALID_ARG;
+  out->digit_bits = RADIX_BITS;
+  out->items_per_thread = items_for(num_rows);
+  return RINGO_OK;
+}
+
+ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched) {
+  if (!sched || num_rows < 0 || sched->digit_bits != RADIX_BITS) return RINGO_ERR_INVALID_ARG;
+  const int it = sched->items_per_thread;
+  if (it != 8 && it != 12 && it != 16) return RINGO_ERR_INVALID_ARG;
+  (void)items_for(0);  // initialise the table
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_items[ceil_log2(std::max<int64_t>(num_rows, 1))] = it;
+  return RINGO_OK;
+}
+
+const char *ringo_version(void) { return "ringo-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+"""Python binding of libringo (argument marshalling only).
+
+Every step of the conversion runs in the library's HIP kernels; PyTorch is
+used for device memory and streams only.  There is no fallback: if the
+library is missing, every entry point raises.
+
+    g = to_graph(src, dst)              # src, dst: int64 tensors on the GPU
+    gs = to_graph_batched(srcs, dsts)   # many tables, one batched call
+
+A `Graph` exposes the converted graph (Section 2.4) as tensors that share
+the library's device memory; the memory is released when the last of them
+(and the Graph) is gone.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libringo.so")
+
+RINGO_OK = 0
+STATUS_NAMES = {0: "RINGO_OK", 1: "RINGO_ERR_INVALID_ARG", 2: "RINGO_ERR_TOO_MANY_NODES",
+                3: "RINGO_ERR_OUT_OF_MEMORY", 4: "RINGO_ERR_HIP", 5: "RINGO_ERR_EVICTED",
+                6: "RINGO_ERR_PENDING"}
+
+# Every symbol include/ringo.h declares.
+EXPORTED_SYMBOLS = (
+    "ringo_table_to_graph", "ringo_table_to_graph_batched", "ringo_graph_free",
+    "ringo_status_string", "ringo_set_allocator", "ringo_tune_get", "ringo_tune_set",
+    "ringo_version",
+)
+
+
+class RingoError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}" if what else STATUS_NAMES.get(status, str(status)))
+
+
+class RawGraph(ctypes.Structure):
+    """ringo_graph_t"""
+    _fields_ = [
+        ("num_rows", ctypes.c_int64),
+        ("num_nodes", ctypes.c_int64),
+        ("num_edges", ctypes.c_int64),
+        ("node_ids", ctypes.c_void_p),
+        ("out_offsets", ctypes.c_void_p),
+        ("out_nbrs", ctypes.c_void_p),
+        ("in_offsets", ctypes.c_void_p),
+        ("in_nbrs", ctypes.c_void_p),
+        ("_alloc", ctypes.c_void_p),
+    ]
+
+
+class Schedule(ctypes.Structure):
+    """ringo_schedule_t"""
+    _fields_ = [("digit_bits", ctypes.c_int32), ("items_per_thread", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libringo.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.ringo_table_to_graph.argtypes = [p, p, i64, ctypes.POINTER(RawGraph), p]
+        L.ringo_table_to_graph.restype = ctypes.c_int
+        L.ringo_table_to_graph_batched.argtypes = [ctypes.c_int32, p, p, p, ctypes.POINTER(RawGraph), p]
+        L.ringo_table_to_graph_batched.restype = ctypes.c_int
+        L.ringo_graph_free.argtypes = [ctypes.POINTER(RawGraph)]
+        L.ringo_graph_free.restype = None
+        L.ringo_status_string.argtypes = [ctypes.c_int]
+        L.ringo_status_string.restype = ctypes.c_char_p
+        L.ringo_set_allocator.argtypes = [p, p, p]
+        L.ringo_set_allocator.restype = ctypes.c_int
+        L.ringo_tune_get.argtypes = [i64, ctypes.POINTER(Schedule)]
+        L.ringo_tune_get.restype = ctypes.c_int
+        L.ringo_tune_set.argtypes = [i64, ctypes.POINTER(Schedule)]
+        L.ringo_tune_set.restype = ctypes.c_int
+        L.ringo_version.argtypes = []
+        L.ringo_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != RINGO_OK:
+        raise RingoError(rc, what)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _column(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or t.dim() != 1:
+        raise TypeError(f"{name} must be a 1-D int64 tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must live on the GPU")
+    return t.contiguous()
+
+
+# ------------------------------------------------------------- raw calls
+
+def table_to_graph_raw(src_ptr: int, dst_ptr: int, num_rows: int, stream: int) -> RawGraph:
+    """ringo_table_to_graph on raw device pointers; free with graph_free."""
+    g = RawGraph()
+    _check(lib().ringo_table_to_graph(src_ptr, dst_ptr, num_rows, ctypes.byref(g), stream),
+           "ringo_table_to_graph")
+    return g
+
+
+def table_to_graph_batched_raw(src_ptrs, dst_ptrs, num_rows, stream: int) -> list[RawGraph]:
+    k = len(num_rows)
+    S = (ctypes.c_void_p * k)(*src_ptrs)
+    D = (ctypes.c_void_p * k)(*dst_ptrs)
+    N = (ctypes.c_int64 * k)(*num_rows)
+    outs = (RawGraph * k)()
+    _check(lib().ringo_table_to_graph_batched(k, S, D, N, outs, stream), "ringo_table_to_graph_batched")
+    return [outs[i] for i in range(k)]
+
+
+def graph_free(g: RawGraph) -> None:
+    lib().ringo_graph_free(ctypes.byref(g))
+
+
+def status_string(status: int) -> str:
+    return lib().ringo_status_string(status).decode()
+
+
+def version() -> str:
+    return lib().ringo_version().decode()
+
+
+def tune_get(num_rows: int) -> tuple[int, int]:
+    s = Schedule()
+    _check(lib().ringo_tune_get(num_rows, ctypes.byref(s)), "ringo_tune_get")
+    return s.digit_bits, s.items_per_thread
+
+
+def tune_set(num_rows: int, digit_bits: int, items_per_thread: int) -> None:
+    s = Schedule(digit_bits, items_per_thread)
+    _check(lib().ringo_tune_set(num_rows, ctypes.byref(s)), "ringo_tune_set")
+
+
+# ----------------------------------------------------------- tensor views
+
+class _Owner:
+    """Keeps one library graph alive while any tensor view of it exists."""
+
+    def __init__(self, raw: RawGraph):
+        self.raw = raw
+
+    def __del__(self):
+        try:
+            lib().ringo_graph_free(ctypes.byref(self.raw))
+        except Exception:
+            pass
+
+
+class _DeviceArray:
+    """__cuda_array_interface__ holder: torch.as_tensor keeps it (and the
+    owner) referenced for as long as the tensor lives."""
+
+    def __init__(self, ptr: int, n: int, typestr: str, owner: _Owner):
+        self._owner = owner
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+def _view(ptr, n: int, dtype: torch.dtype, owner: _Owner, device) -> torch.Tensor:
+    if n == 0 or not ptr:
+        return torch.empty(0, dtype=dtype, device=device)
+    typestr = {torch.int64: "<i8", torch.int32: "<i4"}[dtype]
+    return torch.as_tensor(_DeviceArray(int(ptr), n, typestr, owner), device=device)
+
+
+@dataclass
+class Graph:
+    """The converted graph: node identifiers and CSR in both directions."""
+    num_rows: int
+    num_nodes: int
+    num_edges: int
+    node_ids: torch.Tensor     # int64 [V]
+    out_offsets: torch.Tensor  # int64 [V+1]
+    out_nbrs: torch.Tensor     # int32 [E]
+    in_offsets: torch.Tensor   # int64 [V+1]
+    in_nbrs: torch.Tensor      # int32 [E]
+
+
+def _wrap(raw: RawGraph, device) -> Graph:
+    owner = _Owner(raw)
+    V, E = raw.num_nodes, raw.num_edges
+    return Graph(raw.num_rows, V, E,
+                 _view(raw.node_ids, V, torch.int64, owner, device),
+                 _view(raw.out_offsets, V + 1, torch.int64, owner, device),
+                 _view(raw.out_nbrs, E, torch.int32, owner, device),
+                 _view(raw.in_offsets, V + 1, torch.int64, owner, device),
+                 _view(raw.in_nbrs, E, torch.int32, owner, device))
+
+
+def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None) -> Graph:
+    """Table-to-graph conversion of one edge table (src, dst columns)."""
+    src = _column(src, "src")
+    dst = _column(dst, "dst")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst must have the same length")
+    if src.device != dst.device:
+        raise ValueError("src and dst must be on the same device")
+    with torch.cuda.device(src.device):
+        raw = table_to_graph_raw(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream))
+    return _wrap(raw, src.device)
+
+
+def to_graph_batched(srcs, dsts, stream=None) -> list[Graph]:
+    """Batched conversion: one library call for all tables."""
+    if len(srcs) != len(dsts):
+        raise ValueError("srcs and dsts must have the same length")
+    if len(srcs) == 0:
+        return []
+    srcs = [_column(s, "src") for s in srcs]
+    dsts = [_column(d, "dst") for d in dsts]
+    dev = srcs[0].device
+    for s, d in zip(srcs, dsts):
+        if s.numel() != d.numel():
+            raise ValueError("src and dst must have the same length")
+        if s.device != dev or d.device != dev:
+            raise ValueError("all tables must be on the same device")
+    with torch.cuda.device(dev):
+        raws = table_to_graph_batched_raw([s.data_ptr() for s in srcs], [d.data_ptr() for d in dsts],
+                                          [s.numel() for s in srcs], _stream_handle(stream))
+    return [_wrap(r, dev) for r in raws]

@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every symbol include/ringo.h declares,
+and rejects invalid arguments before touching the device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1503_07881_amd import ringo, workloads
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ringo.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ringo_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("ringo_table_to_graph", "ringo_table_to_graph_batched", "ringo_graph_free", "ringo_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(ringo.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+    assert set(declared_functions()) == set(ringo.EXPORTED_SYMBOLS)
+
+
+def test_status_strings():
+    for code in range(7):
+        assert ringo.status_string(code)
+    assert ringo.status_string(0) == "ok"
+    assert "gfx950" in ringo.version()
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = ringo.lib()
+    g = ringo.RawGraph()
+    assert L.ringo_table_to_graph(None, None, -1, ctypes.byref(g), None) == 1
+    assert L.ringo_table_to_graph(None, None, 10, ctypes.byref(g), None) == 1
+    assert L.ringo_table_to_graph(None, None, (1 << 31), ctypes.byref(g), None) == 1
+    assert L.ringo_table_to_graph(None, None, 0, None, None) == 1
+    assert g.num_nodes == 0 and g.node_ids is None
+    n = (ctypes.c_int64 * 2)(5, -1)
+    p = (ctypes.c_void_p * 2)(None, None)
+    outs = (ringo.RawGraph * 2)()
+    assert L.ringo_table_to_graph_batched(2, p, p, n, outs, None) == 1
+    assert L.ringo_table_to_graph_batched(-1, p, p, n, outs, None) == 1
+    assert L.ringo_table_to_graph_batched(0, None, None, None, None, None) == 0
+    ringo.graph_free(g)  # zeroed struct: no-op
+    L.ringo_graph_free(None)
+
+
+def test_tune_schedule_roundtrip():
+    d, it = ringo.tune_get(1000)
+    assert d == 8 and it in (8, 12, 16)
+    ringo.tune_set(1 << 20, 8, 12)
+    assert ringo.tune_get(1 << 20) == (8, 12)
+    ringo.tune_set(1 << 20, 8, 16)
+    with pytest.raises(ringo.RingoError):
+        ringo.tune_set(1000, 9, 16)
+    with pytest.raises(ringo.RingoError):
+        ringo.tune_set(1000, 8, 7)
+
+
+def test_generators_deterministic_and_shaped():
+    spec = workloads.TableSpec("uniform", 50_000, seed=9, pool=1000, ndup=500, shuffle=True)
+    a = workloads.generate_host(spec)
+    b = workloads.generate_host(spec, threads=1)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+    import numpy as np
+    assert np.unique(np.concatenate(a)).size <= 1000
+    r = workloads.generate_host(workloads.TableSpec("rmat", 100_000, seed=2, scale=10))
+    assert np.unique(np.concatenate(r)).size <= 1024
+    # R-MAT skew: the most frequent source carries far more than 1/1024 of rows
+    _, counts = np.unique(r[0], return_counts=True)
+    assert counts.max() > 20 * 100_000 / 1024
+    # the splitmix64 finaliser matches the library's
+    L = workloads.lib()
+    for x in (0, 1, 12345, (1 << 64) - 1):
+        assert L.ringo_gen_mix64(x) == workloads.mix64(x)
+
+
+def test_config4_sizes():
+    specs = workloads.config4()
+    assert len(specs) == 4096
+    ns = [s.n for s in specs]
+    assert min(ns) >= 1000 and max(ns) <= 2_000_000
+    total = sum(ns)
+    assert 0.9e9 < total < 1.25e9
+    assert all(s.kind == ("uniform" if i % 2 == 0 else "rmat") for i, s in enumerate(specs))
