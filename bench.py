@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the table-to-graph conversion (Section 2.4) on one MI355X.
+
+A step is one full conversion of the 2^26-row R-MAT scale-22 edge table
+(the LiveJournal-shaped stand-in): node-key sort, unique, remap, edge-key
+sort, dedupe, out-CSR, in-key sort, in-CSR, output allocation and both
+size read-backs.  The input columns are generated on the device and are
+resident in HBM before the timed region starts.
+
+Prints one JSON line: edges/s (input rows per second, the paper's "Edges/s"
+of Table 5), the roofline position of the dominant kernel measured with HIP
+events on the conversion's stream inside the timed region, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sort_pass_node_rmat_s22.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07881_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(rows: int):
+    import numpy as np  # noqa: F401
+    import oracle
+    from paper_1503_07881_amd import workloads
+    spec = workloads.config2()
+    sample = workloads.TableSpec("rmat", rows, seed=spec.seed, scale=spec.scale)
+    src, dst = workloads.generate_host(sample)
+    t0 = time.perf_counter()
+    oracle.table_to_graph(src, dst)
+    dt = time.perf_counter() - t0
+    return {"value": rows / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {rows:,} rows of the R-MAT scale-22 workload (rows are i.i.d., so a prefix "
+                      f"is a sample of the same distribution); single-threaded std::sort oracle, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--cpu-rows", type=int, default=1 << 24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the conversion runs on a single MI355X; see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_07881_amd import ringo, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = {1: workloads.config1, 2: workloads.config2, 3: workloads.config3}[args.config]()
+    n = spec.n
+    log(f"bench: generating {spec.kind} n={n:,} on the device")
+    src = torch.empty(n, dtype=torch.int64, device=dev)
+    dst = torch.empty(n, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    if spec.kind == "rmat" or (spec.ndup == 0 and not spec.shuffle):
+        workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
+    else:
+        hs, hd = workloads.generate_host(spec)
+        src.copy_(torch.from_numpy(hs))
+        dst.copy_(torch.from_numpy(hd))
+    torch.cuda.synchronize()
+
+    # achievable-bandwidth reference: a plain 16-byte copy of 2 GiB
+    cbytes = 1 << 31
+    ca = torch.empty(cbytes // 8, dtype=torch.int64, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(2):
+        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * cbytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del ca, cb
+    log(f"bench: copy kernel {copy_gbps:.0f} GB/s")
+
+    def step():
+        g = ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh)
+        V, E = g.num_nodes, g.num_edges
+        ringo.graph_free(g)
+        return V, E
+
+    for i in range(args.warmup):
+        V, E = step()
+        log(f"bench: warmup {i + 1}/{args.warmup} V={V:,} E={E:,}")
+    torch.cuda.synchronize()
+
+    # untraced timing (reported beside the traced one to show the overhead)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_untraced = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"bench: untraced {ms_untraced:.3f} ms/step")
+
+    # timed region, with per-kernel HIP events on the conversion's stream
+    ringo.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        V, E = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    trace = ringo.trace_read()
+    ringo.trace_enable(False)
+    log(f"bench: timed {args.steps} steps: {ms:.3f} ms/step")
+
+    kernels = {}
+    for name, t in trace.items():
+        avg_ms = t["ms"] / t["launches"]
+        bpl = t["bytes"] / t["launches"]
+        kernels[name] = {"launches_per_step": t["launches"] // args.steps,
+                         "ms_per_step": round(t["ms"] / args.steps, 4),
+                         "avg_launch_ms": round(avg_ms, 5),
+                         "GBps": round(bpl / (avg_ms / 1e3) / 1e9, 1)}
+    dom = max(trace, key=lambda k: trace[k]["ms"])
+    t = trace[dom]
+    avg_s = t["ms"] / t["launches"] / 1e3
+    bytes_per_launch = t["bytes"] / t["launches"]
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = read_traffic() if dom == "sort_pass_node" else None
+
+    out = {
+        "metric": "edges/s converted (input rows per second, table to directed simple graph, 1 GPU)",
+        "value": n / (ms / 1e3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)",
+        "config": {"workload": f"{spec.kind}_scale{spec.scale}_rows{n}" if spec.kind == "rmat"
+                   else f"uniform_rows{n}_pool{spec.pool}",
+                   "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
+                   "digit_bits": 8, "items_per_thread": ringo.tune_get(n)[1]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": round(avg_s * 1e3, 5)},
+        "ms_per_step_untraced": ms_untraced,
+        "copy_kernel_GBps": round(copy_gbps, 1),
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline and args.config == 2:
+        log(f"bench: CPU oracle on {args.cpu_rows:,} rows")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -139,6 +139,26 @@ typedef struct {
 ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out);
 ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched);
 
+/*
+ * Kernel tracing (measurement support).  While enabled, every kernel launch
+ * of every call is bracketed by two HIP events recorded on the call's
+ * stream.  ringo_trace_read waits for the recorded events and fills up to
+ * max_entries entries, one per kernel kind that ran, with the launch count,
+ * the summed event-measured duration, the algorithmic bytes the launches
+ * move (input read once, output written once, per the kernel's definition)
+ * and the processed element count.  Returns the number of entries, or -1 on
+ * a HIP error.  ringo_trace_enable(0 or 1) discards the records so far.
+ */
+typedef struct {
+  const char *kernel; /* static name: hist_node, sort_pass_node, ...     */
+  int64_t launches;
+  double total_ms;
+  double bytes;
+  int64_t units;      /* keys, rows, nodes or edges processed in total    */
+} ringo_trace_entry_t;
+void ringo_trace_enable(int on);
+int ringo_trace_read(ringo_trace_entry_t *out, int max_entries);
+
 /* Version string of the library build. */
 const char *ringo_version(void);
 

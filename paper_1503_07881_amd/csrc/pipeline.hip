@@ -265,21 +265,101 @@ struct Call {
   }
 };
 
+
+#define HIP_TRY(x)                              \
+  do {                                          \
+    hipError_t _e = (x);                        \
+    if (_e != hipSuccess) return RINGO_ERR_HIP; \
+  } while (0)
+
+// --------------------------------------------------------------- tracing
+//
+// When enabled, every kernel launch of a call is bracketed by two HIP events
+// recorded on the call's stream; ringo_trace_read reports per-kernel launch
+// counts, summed durations and the algorithmic bytes the launches move.
+
+enum TraceKind {
+  TK_HIST_NODE, TK_SORT_NODE, TK_UNIQUE, TK_DIR, TK_REMAP, TK_SORT_EDGE, TK_DEDUPE, TK_SORT_IN,
+  TK_IN_CSR, TK_AUX, TK_KINDS
+};
+const char *const kTraceNames[TK_KINDS] = {"hist_node", "sort_pass_node", "unique", "directory",
+                                           "remap_pack", "sort_pass_edge", "dedupe_out_csr",
+                                           "sort_pass_in", "in_csr", "aux"};
+
+struct TraceRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+  int64_t units;
+};
+bool g_trace_on = false;
+std::vector<TraceRec> g_trace;
+std::vector<hipEvent_t> g_evpool;
+
+hipEvent_t trace_event() {
+  if (!g_evpool.empty()) {
+    hipEvent_t e = g_evpool.back();
+    g_evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+struct TraceMark {
+  hipEvent_t a = nullptr;
+};
+
+TraceMark trace_begin(hipStream_t s) {
+  TraceMark m;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_trace_on) return m;
+  m.a = trace_event();
+  if (m.a) (void)hipEventRecord(m.a, s);
+  return m;
+}
+
+// Returns the record index (or -1) so that byte counts known only later
+// can be filled in.
+long trace_end(const TraceMark &m, int kind, int64_t units, double bytes, hipStream_t s) {
+  if (!m.a) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipEvent_t b = trace_event();
+  if (!b) return -1;
+  (void)hipEventRecord(b, s);
+  g_trace.push_back(TraceRec{kind, m.a, b, bytes, units});
+  return (long)g_trace.size() - 1;
+}
+
+void trace_set_bytes(long idx, double bytes) {
+  if (idx < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((size_t)idx < g_trace.size()) g_trace[(size_t)idx].bytes = bytes;
+}
+
+#define TRACED(kind, units, bytes, expr)                       \
+  do {                                                         \
+    TraceMark _m = trace_begin(st);                            \
+    HIP_TRY(expr);                                             \
+    (void)trace_end(_m, (kind), (units), (double)(bytes), st); \
+  } while (0)
+
 int grid_for(int64_t tiles, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
 }
 
-#define HIP_TRY(x)                                  \
-  do {                                              \
-    hipError_t _e = (x);                            \
-    if (_e != hipSuccess) return RINGO_ERR_HIP;     \
-  } while (0)
 
 ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst,
                    const int64_t *num_rows, ringo_graph_t *outs) {
   const int S = c.S;
   hipStream_t st = c.stream;
   const int cus = device_cu_count();
+  long unique_rec = -1, dedupe_rec = -1;
+  int64_t sumV = 0, sumE = 0;
 
   // ---------------------------------------------------------------- plan N
   c.plan.assign(S, SegPlan{});
@@ -325,8 +405,9 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
 
   // ------------------------------------------------------------- phase N
-  HIP_TRY(launch_hist_node(c.tiles(TM_HIST, RANGE_NODE_KEYS), c.hist,
-                           grid_for(c.total(TM_HIST), cus * 4), st));
+  TRACED(TK_HIST_NODE, 2 * N, 16.0 * N,
+         launch_hist_node(c.tiles(TM_HIST, RANGE_NODE_KEYS), c.hist,
+                          grid_for(c.total(TM_HIST), cus * 4), st));
   HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, NODE_PASSES, RANGE_NODE_KEYS, st));
   uint64_t *buf[2] = {c.A, c.B};
   {
@@ -335,16 +416,19 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < NODE_PASSES; ++p) {
       SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
                                  RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
-      HIP_TRY(launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
-                               st));
+      TRACED(TK_SORT_NODE, 2 * N, 32.0 * N,
+             launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
+                              st));
     }
   }
   uint64_t *sorted_nodes = buf[(NODE_PASSES - 1) & 1];
   uint64_t *nodes_ws = buf[NODE_PASSES & 1];
   {
     const uint32_t ep = ++c.epoch;
+    TraceMark m = trace_begin(st);
     HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), sorted_nodes, nodes_ws, c.results,
                           c.status, c.counters + ep, ep, grid_for(c.total(TM_UNIQ), cus * 4), st));
+    unique_rec = trace_end(m, TK_UNIQUE, 2 * N, 16.0 * N, st);
   }
 
   // -------------------------------------------------------------- sync #1
@@ -370,6 +454,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     off1[3 * i + 2] = arena1;
     arena1 = align_up(arena1 + sizeof(int64_t) * (p.V + 1));
   }
+  for (int i = 0; i < S; ++i) sumV += V[i];
+  trace_set_bytes(unique_rec, 16.0 * N + 8.0 * sumV);
   c.owner = new Owner();
   c.owner->stream = st;
   c.owner->hooks = c.hooks;
@@ -394,19 +480,21 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   // ------------------------------------------------------------- phase E
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
   HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
-  HIP_TRY(launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
-                     grid_for(c.total(TM_DIR), cus * 8), st));
+  TRACED(TK_DIR, sumV, 16.0 * sumV + 4.0 * dir_words,
+         launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
+                    grid_for(c.total(TM_DIR), cus * 8), st));
   // the sorted node keys are consumed: their buffer takes the edge keys
   uint64_t *ebuf[2] = {sorted_nodes, nodes_ws};
-  HIP_TRY(launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0], c.hist, P_e,
-                       grid_for(c.total(TM_REMAP), cus * 8), st));
+  TRACED(TK_REMAP, N, 24.0 * N,
+         launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0], c.hist, P_e,
+                      grid_for(c.total(TM_REMAP), cus * 8), st));
   HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_e, RANGE_ROWS, st));
   {
     const int g = grid_for(c.total(TM_ESORT), sort_max_grid(c.items, SORT_PLAIN));
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
                                  RADIX_BITS * p);
-      HIP_TRY(launch_sort_pass(a, SORT_PLAIN, c.items, g, st));
+      TRACED(TK_SORT_EDGE, N, 16.0 * N, launch_sort_pass(a, SORT_PLAIN, c.items, g, st));
     }
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
@@ -414,9 +502,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
   {
     const uint32_t ep = ++c.epoch;
+    TraceMark m = trace_begin(st);
     HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, RANGE_ROWS), sorted_edges, ukeys, c.results + S,
                           c.hist, P_in, c.status, c.counters + ep, ep,
                           grid_for(c.total(TM_DEDUP), cus * 4), st));
+    dedupe_rec = trace_end(m, TK_DEDUPE, N, 8.0 * N, st);
   }
 
   // -------------------------------------------------------------- sync #2
@@ -431,6 +521,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     off2[2 * i + 1] = arena2;
     arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
   }
+  for (int i = 0; i < S; ++i) sumE += E[i];
+  trace_set_bytes(dedupe_rec, 8.0 * N + 8.0 * sumE + 8.0 * (sumV + S));
   c.owner->blocks[1] = dev_alloc(c.hooks, arena2, st);
   if (!c.owner->blocks[1]) return RINGO_ERR_OUT_OF_MEMORY;
   char *a2 = (char *)c.owner->blocks[1];
@@ -451,12 +543,14 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + RADIX_BITS * p);
-      HIP_TRY(launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
-                               st));
+      TRACED(TK_SORT_IN, sumE, (p == 0 ? 20.0 : 16.0) * sumE,
+             launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
+                              st));
     }
   }
-  HIP_TRY(launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1],
-                        grid_for(c.total(TM_ICSR), cus * 8), st));
+  TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
+         launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1],
+                       grid_for(c.total(TM_ICSR), cus * 8), st));
 
   // ------------------------------------------------------------- handoff
   c.owner->refs.store(S);
@@ -568,6 +662,52 @@ ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_items[ceil_log2(std::max<int64_t>(num_rows, 1))] = it;
   return RINGO_OK;
+}
+
+
+void ringo_trace_enable(int on) {
+  std::vector<TraceRec> old;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_trace_on = on != 0;
+    old.swap(g_trace);
+  }
+  for (auto &r : old) {
+    (void)hipEventSynchronize(r.b);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_evpool.push_back(r.a);
+    g_evpool.push_back(r.b);
+  }
+}
+
+int ringo_trace_read(ringo_trace_entry_t *out, int max_entries) {
+  std::vector<TraceRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    recs = g_trace;
+  }
+  ringo_trace_entry_t acc[TK_KINDS];
+  for (int k = 0; k < TK_KINDS; ++k) {
+    acc[k].kernel = kTraceNames[k];
+    acc[k].launches = 0;
+    acc[k].total_ms = 0;
+    acc[k].bytes = 0;
+    acc[k].units = 0;
+  }
+  for (auto &r : recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -1;
+    ringo_trace_entry_t &e = acc[r.kind];
+    e.launches += 1;
+    e.total_ms += ms;
+    e.bytes += r.bytes;
+    e.units += r.units;
+  }
+  int n = 0;
+  for (int k = 0; k < TK_KINDS && n < max_entries; ++k)
+    if (acc[k].launches > 0) out[n++] = acc[k];
+  return n;
 }
 
 const char *ringo_version(void) { return "ringo-mi355x 0.1 (gfx950)"; }

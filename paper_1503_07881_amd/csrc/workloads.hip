@@ -175,3 +175,28 @@ int ringo_gen_uniform_device(int64_t n, int64_t pool, uint64_t s_salt, uint64_t 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ calibration
+//
+// Plain streaming copy of `words` 16-byte words: the reference kernel whose
+// bandwidth and HBM counter readings calibrate the measurements of the
+// conversion kernels.
+
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
+                                                uint4 *__restrict__ dst, int64_t words) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+    dst[i] = src[i];
+}
+
+extern "C" int ringo_gen_copy_device(void *dst, const void *src, int64_t bytes,
+                                     hipStream_t stream) {
+  if (bytes < 0 || (bytes & 15) != 0 || ((uintptr_t)dst & 15) != 0 || ((uintptr_t)src & 15) != 0)
+    return -1;
+  const int64_t words = bytes / 16;
+  if (words == 0) return 0;
+  int64_t g = std::min<int64_t>((words + 255) / 256, 256 * 16);
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)g), dim3(256), 0, stream, (const uint4 *)src,
+                     (uint4 *)dst, words);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "RINGO_OK", 1: "RINGO_ERR_INVALID_ARG", 2: "RINGO_ERR_TOO_MAN
 EXPORTED_SYMBOLS = (
     "ringo_table_to_graph", "ringo_table_to_graph_batched", "ringo_graph_free",
     "ringo_status_string", "ringo_set_allocator", "ringo_tune_get", "ringo_tune_set",
-    "ringo_version",
+    "ringo_version", "ringo_trace_enable", "ringo_trace_read",
 )
 
 
@@ -54,6 +54,12 @@ class RawGraph(ctypes.Structure):
         ("in_nbrs", ctypes.c_void_p),
         ("_alloc", ctypes.c_void_p),
     ]
+
+
+class TraceEntry(ctypes.Structure):
+    """ringo_trace_entry_t"""
+    _fields_ = [("kernel", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("units", ctypes.c_int64)]
 
 
 class Schedule(ctypes.Structure):
@@ -85,6 +91,10 @@ def lib() -> ctypes.CDLL:
         L.ringo_tune_get.restype = ctypes.c_int
         L.ringo_tune_set.argtypes = [i64, ctypes.POINTER(Schedule)]
         L.ringo_tune_set.restype = ctypes.c_int
+        L.ringo_trace_enable.argtypes = [ctypes.c_int]
+        L.ringo_trace_enable.restype = None
+        L.ringo_trace_read.argtypes = [ctypes.POINTER(TraceEntry), ctypes.c_int]
+        L.ringo_trace_read.restype = ctypes.c_int
         L.ringo_version.argtypes = []
         L.ringo_version.restype = ctypes.c_char_p
         _lib = L
@@ -151,6 +161,20 @@ def tune_get(num_rows: int) -> tuple[int, int]:
 def tune_set(num_rows: int, digit_bits: int, items_per_thread: int) -> None:
     s = Schedule(digit_bits, items_per_thread)
     _check(lib().ringo_tune_set(num_rows, ctypes.byref(s)), "ringo_tune_set")
+
+
+def trace_enable(on: bool) -> None:
+    lib().ringo_trace_enable(1 if on else 0)
+
+
+def trace_read() -> dict:
+    """Per-kernel launches, summed event time (ms), algorithmic bytes, units."""
+    buf = (TraceEntry * 16)()
+    n = lib().ringo_trace_read(buf, 16)
+    if n < 0:
+        raise RingoError(4, "ringo_trace_read")
+    return {buf[i].kernel.decode(): {"launches": buf[i].launches, "ms": buf[i].total_ms, "bytes": buf[i].bytes,
+                                     "units": buf[i].units} for i in range(n)}
 
 
 # ----------------------------------------------------------- tensor views

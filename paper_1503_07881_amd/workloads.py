@@ -69,6 +69,8 @@ def lib():
         L.ringo_gen_rmat_device.restype = ctypes.c_int
         L.ringo_gen_uniform_device.argtypes = [i64, i64, u64, u64, u64, p64, p64, p64]
         L.ringo_gen_uniform_device.restype = ctypes.c_int
+        L.ringo_gen_copy_device.argtypes = [p64, p64, i64, p64]
+        L.ringo_gen_copy_device.restype = ctypes.c_int
         L.ringo_gen_mix64.argtypes = [u64]
         L.ringo_gen_mix64.restype = u64
         _lib = L
@@ -133,6 +135,12 @@ def generate_device(spec: TableSpec, src_ptr: int, dst_ptr: int, stream_handle: 
         raise ValueError(f"no device generator for {spec}")
     if rc != 0:
         raise RuntimeError(f"device generator failed ({rc}) for {spec}")
+
+
+def copy_device(dst_ptr: int, src_ptr: int, nbytes: int, stream_handle: int = 0):
+    """Plain streaming copy (bandwidth and counter calibration)."""
+    if lib().ringo_gen_copy_device(dst_ptr, src_ptr, nbytes, stream_handle) != 0:
+        raise RuntimeError("copy kernel rejected its arguments")
 
 
 # ------------------------------------------------------------------ the workloads
