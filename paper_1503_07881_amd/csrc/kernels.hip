@@ -28,6 +28,14 @@ namespace ringo {
 
 // --------------------------------------------------------------- helpers
 
+// Pointers read from the plan are generic to the compiler; G() marks them as
+// global-memory pointers so that accesses compile to global (not flat)
+// instructions, which keep LDS waits independent of outstanding loads.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *G(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -88,10 +96,13 @@ __device__ __forceinline__ uint64_t st_pack(uint32_t epoch, uint64_t flag, uint6
 __device__ __forceinline__ void st_store(uint64_t *p, uint64_t w) {
   __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+#ifndef RINGO_SPIN_SLEEP
+#define RINGO_SPIN_SLEEP 1
+#endif
 __device__ __forceinline__ uint64_t st_wait(const uint64_t *p, uint32_t epoch) {
   uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   while ((uint32_t)(w >> 56) != epoch) {
-    __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_s_sleep(RINGO_SPIN_SLEEP);
     w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return w;
@@ -123,13 +134,34 @@ __device__ __forceinline__ bool lb_publish(uint64_t *status, int64_t tile, int64
 
 // Second half: walk back over predecessors until an inclusive prefix is
 // found (the first tile of a table always publishes one), then publish ours.
-__device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, int64_t tile, int stride, int d,
-                                               uint32_t epoch, uint64_t total) {
+// The status words of LB_WINDOW predecessors are requested together, so a
+// walk over k published aggregates costs k / LB_WINDOW dependent round trips.
+#ifndef RINGO_LB_WINDOW
+#define RINGO_LB_WINDOW 8
+#endif
+constexpr int LB_WINDOW = RINGO_LB_WINDOW;
+
+__device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, int64_t tile, int64_t first,
+                                               int stride, int d, uint32_t epoch, uint64_t total) {
   uint64_t acc = 0;
-  for (int64_t p = tile - 1;; --p) {
-    const uint64_t w = st_wait(status + p * stride + d, epoch);
-    acc += w & ST_VMASK;
-    if (((w >> 54) & 3) == ST_INC) break;
+  bool done = false;
+  for (int64_t p = tile - 1; !done; p -= LB_WINDOW) {
+    uint64_t w[LB_WINDOW];
+#pragma unroll
+    for (int k = 0; k < LB_WINDOW; ++k)
+      w[k] = p - k >= first ? __hip_atomic_load(status + (p - k) * stride + d, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : 0;
+#pragma unroll
+    for (int k = 0; k < LB_WINDOW; ++k) {
+      if (done) break;
+      uint64_t x = w[k];
+      // the walk ends at the table's first tile at the latest, which always
+      // publishes an inclusive prefix, so p - k >= first here
+      if ((uint32_t)(x >> 56) != epoch) x = st_wait(status + (p - k) * stride + d, epoch);
+      acc += x & ST_VMASK;
+      done = ((x >> 54) & 3) == ST_INC;
+    }
   }
   st_store(status + tile * stride + d, st_pack(epoch, ST_INC, acc + total));
   return acc;
@@ -195,16 +227,27 @@ __global__ __launch_bounds__(256) void k_hist_node(TileLaunch t, uint32_t *hist)
       if (cur >= 0) flush(cur);
       cur = seg;
     }
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)HIST_TILE;
     const int64_t end = std::min<int64_t>(base + HIST_TILE, 2 * P.n);
     uint32_t *h = s_h + wave * H;
-    for (int64_t e = base + tid; e < end; e += 256) {
-      const int64_t v = e < P.n ? P.src[e] : P.dst[e - P.n];
-      const uint64_t k = (uint64_t)v ^ SIGN_FLIP;
+    const __attribute__((address_space(1))) int64_t *src = G(P.src), *dst = G(P.dst);
+    for (int64_t e0 = base + tid; e0 < end; e0 += 4 * 256) {
+      uint64_t k[4];
 #pragma unroll
-      for (int p = 0; p < NODE_PASSES; ++p)
-        atomicAdd(&h[p * RADIX + ((k >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+      for (int j = 0; j < 4; ++j) {
+        const int64_t e = std::min<int64_t>(e0 + j * 256, end - 1);  // in range; counted once below
+        const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? src + e : dst + (e - P.n);
+        k[j] = (uint64_t)*ptr ^ SIGN_FLIP;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (e0 + j * 256 < end) {
+#pragma unroll
+          for (int p = 0; p < NODE_PASSES; ++p)
+            atomicAdd(&h[p * RADIX + ((k[j] >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+        }
+      }
     }
   }
   if (cur >= 0) flush(cur);
@@ -235,10 +278,138 @@ hipError_t launch_scan_hist(const uint32_t *hist, int64_t *base, const SegPlan *
   return hipGetLastError();
 }
 
-// ------------------------------------------------------ one-sweep LSD pass
+// ------------------------------------------------------------ LSD pass
+//
+// One stable counting-sort pass on RADIX_BITS digits, reduce-then-scan at
+// tile granularity, with every kernel walking the tiles in global order:
+//   upsweep      digit counts of every tile (and of every run of UP_TILES
+//                consecutive tiles)
+//   block scan   exclusive prefix of the run counts, per digit
+//   tile prefix  exclusive prefix of the tile counts, per digit: the
+//                position of a tile's first key of each digit, relative to
+//                the first tile of its table
+//   downsweep    wave-ballot stable rank inside the tile, LDS staging in
+//                digit order, contiguous write-out of every digit run
+// No block waits on another.  Tiles in flight are always neighbours in
+// the input, so the runs they write land next to each other in every
+// digit's output range.  Prefixes are 32-bit and wrap: only differences
+// inside one table (fewer than 2^32 keys) are used.
+
+constexpr int UP_TILES = 32;  // tiles per upsweep block
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The key of element e of a table's range, as the pass sorts it.
+template <int MODE>
+__device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan &P, int64_t start,
+                                             int64_t e) {
+  if (MODE == SORT_NODE_FIRST) {
+    // one load from a selected pointer: no branch, so loads stay in flight
+    const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? G(P.src) + e : G(P.dst) + (e - P.n);
+    return (uint64_t)*ptr ^ SIGN_FLIP;
+  } else if (MODE == SORT_IN_FIRST) {
+    const uint64_t x = G(a.in)[start + e];
+    const uint64_t d = x & ((1ull << P.b) - 1);
+    return (d << 32) | (x >> P.b);
+  }
+  return G(a.in)[start + e];
+}
+
+// Header of the table holding a tile; tiles only move forward in a block.
+struct TileHeader {
+  int seg = -1;
+  int64_t first = 0, end = 0, start = 0, count = 0;
+  SegPlan P;
+  __device__ __forceinline__ void at(const SortLaunch &a, int64_t tile) {
+    if (tile < end) return;
+    seg = find_seg(a.tmap, a.num_segs, tile);
+    P = a.plan[seg];
+    first = a.tmap[seg];
+    end = a.tmap[seg + 1];
+    start = range_start(P, a.range_kind);
+    count = range_count(P, a.range_kind);
+  }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys) {
+  constexpr int W = 4;
+  __shared__ uint32_t s_h[W * RADIX];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int shift = a.shift;
+  const int64_t t0 = (int64_t)blockIdx.x * UP_TILES;
+  const int64_t t1 = std::min<int64_t>(t0 + UP_TILES, a.total_tiles);
+  TileHeader H;
+  uint32_t run_sum = 0;
+  uint32_t *h = s_h + wave * RADIX;
+  for (int64_t t = t0; t < t1; ++t) {
+    for (int i = tid; i < W * RADIX; i += 256) s_h[i] = 0;
+    H.at(a, t);
+    __syncthreads();
+    const int64_t k0 = (t - H.first) * tile_keys;
+    const int64_t k1 = std::min<int64_t>(k0 + tile_keys, H.count);
+    for (int64_t e0 = k0 + tid; e0 < k1; e0 += 4 * 256) {
+      uint64_t k[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) k[j] = pass_key<MODE>(a, H.P, H.start, std::min<int64_t>(e0 + j * 256, k1 - 1));
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (e0 + j * 256 < k1) atomicAdd(&h[(k[j] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t v = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) v += s_h[w * RADIX + tid];
+    a.counts[t * RADIX + tid] = v;
+    run_sum += v;
+    __syncthreads();
+  }
+  a.bsum[(int64_t)blockIdx.x * RADIX + tid] = run_sum;
+}
+
+// Exclusive scan of the run counts over all runs, one block per digit.
+__global__ __launch_bounds__(1024) void k_block_scan(SortLaunch a, int64_t runs) {
+  __shared__ uint32_t s_w[16];
+  const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < runs; b0 += 1024) {
+    const int64_t b = b0 + tid;
+    const uint32_t v = b < runs ? a.bsum[b * RADIX + d] : 0u;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t x = s_w[i];
+      off += (i < w) ? x : 0u;
+      tot += x;
+    }
+    if (b < runs) a.bsum[b * RADIX + d] = carry + off + inc - v;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+// Tile counts become exclusive prefixes, in place; one block per run.
+__global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a) {
+  const int d = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * UP_TILES;
+  const int64_t t1 = std::min<int64_t>(t0 + UP_TILES, a.total_tiles);
+  uint32_t run = a.bsum[(int64_t)blockIdx.x * RADIX + d];
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = a.counts[t * RADIX + d];
+    a.counts[t * RADIX + d] = run;
+    run += v;
+  }
+}
 
 template <int BLOCK, int ITEMS, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
+__global__ __launch_bounds__(BLOCK) void k_downsweep(SortLaunch a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(BLOCK >= RADIX, "one thread per digit");
@@ -247,51 +418,43 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
   __shared__ uint32_t s_lstart[RADIX];
   __shared__ int64_t s_goff[RADIX];
   __shared__ uint32_t s_w[WAVES];
-  __shared__ int64_t s_tile;
-  __shared__ int32_t s_seg;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
-  for (;;) {
-    if (tid == 0) {
-      const int64_t t = (int64_t)atomicAdd(a.counter, 1u);
-      s_tile = t;
-      s_seg = t < a.total_tiles ? find_seg(a.tmap, a.num_segs, t) : 0;
-    }
-    for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
-    __syncthreads();
-    const int64_t tile = s_tile;
-    if (tile >= a.total_tiles) break;
-    const int seg = s_seg;
-    const SegPlan &P = a.plan[seg];
-    const int64_t first = a.tmap[seg];
-    const int64_t base = (tile - first) * (int64_t)TILE;
-    const int64_t start = range_start(P, a.range_kind);
-    const int cnt = (int)std::min<int64_t>(TILE, range_count(P, a.range_kind) - base);
+  TileHeader H;
+  int64_t dbase = 0;     // this thread's digit: first output position in the table
+  uint32_t pfirst = 0;   // prefix of the table's first tile
+  for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
+  __syncthreads();
 
-    // Load: wave w owns the contiguous run [w * ITEMS * 64, (w + 1) * ITEMS * 64)
-    // of the tile, one coalesced 64-key row per item.
+  for (int64_t tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
+    if (tile >= H.end) {
+      H.at(a, tile);
+      if (tid < RADIX) {
+        dbase = a.digit_base[(int64_t)H.seg * a.base_stride + a.pass * RADIX + tid];
+        pfirst = a.counts[H.first * RADIX + tid];
+      }
+    }
+    const int64_t base = (tile - H.first) * (int64_t)TILE;
+    const int cnt = (int)std::min<int64_t>(TILE, H.count - base);
+
+    // Wave w owns the contiguous run [w * ITEMS * 64, (w + 1) * ITEMS * 64)
+    // of the tile, one coalesced 64-key row per item.  Lanes past the end
+    // load the tile's first key and are masked out of the rank; the loads
+    // are unconditional so that all of them are in flight before the first
+    // wait.
     uint64_t keys[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
-      uint64_t k = 0;
-      if (idx < cnt) {
-        const int64_t e = base + idx;
-        if (MODE == SORT_NODE_FIRST) {
-          const int64_t v = e < P.n ? P.src[e] : P.dst[e - P.n];
-          k = (uint64_t)v ^ SIGN_FLIP;
-        } else if (MODE == SORT_IN_FIRST) {
-          const uint64_t x = a.in[start + e];
-          const uint64_t d = x & ((1ull << P.b) - 1);
-          P.out_nbr[e] = (int32_t)d;  // out-neighbours, already in (s, d) order
-          k = (d << 32) | (x >> P.b);
-        } else {
-          k = a.in[start + e];
-        }
-      }
+      const bool valid = idx < cnt;
+      const int64_t e = base + (valid ? idx : 0);
+      const uint64_t k = pass_key<MODE>(a, H.P, H.start, e);
+      if (MODE == SORT_IN_FIRST && valid)  // out-neighbours, already in (s, d) order
+        G(H.P.out_nbr)[e] = (int32_t)(uint32_t)(k >> 32);
       keys[i] = k;
     }
+    const uint32_t tprefix = tid < RADIX ? a.counts[tile * RADIX + tid] : 0u;
 
     // Stable rank inside the wave: lanes with an equal digit are found with
     // RADIX_BITS ballots; the lowest such lane bumps the wave's digit count.
@@ -308,13 +471,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
         m &= set ? bb : ~bb;
       }
       const uint32_t below = lanes_below(m);
-      uint32_t r = 0;
+      uint32_t rk = 0;
       if (valid) {
         const uint32_t old = s_whist[wave * RADIX + d];
         if (below == 0) s_whist[wave * RADIX + d] = old + (uint32_t)__popcll(m);
-        r = old + below;
+        rk = old + below;
       }
-      rank[i] = r;
+      rank[i] = rk;
     }
     __syncthreads();
 
@@ -328,13 +491,12 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
         total += c;
       }
     }
-    uint64_t excl = 0;
-    bool resolved = false;
-    if (tid < RADIX)
-      resolved = lb_publish(a.status, tile, first, RADIX, tid, a.epoch, total, &excl);
     uint32_t tile_total;
     const uint32_t lstart = block_excl_scan<BLOCK>(tid < RADIX ? total : 0u, s_w, tile_total);
-    if (tid < RADIX) s_lstart[tid] = lstart;
+    if (tid < RADIX) {
+      s_lstart[tid] = lstart;
+      s_goff[tid] = dbase + (int64_t)(uint32_t)(tprefix - pfirst) - (int64_t)lstart;
+    }
     __syncthreads();
 
     // Stage the tile in LDS in digit order.
@@ -345,79 +507,73 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(SortLaunch a) {
         s_stage[s_lstart[d] + s_whist[wave * RADIX + d] + rank[i]] = keys[i];
       }
     }
-    if (tid < RADIX) {
-      if (!resolved) excl = lb_resolve(a.status, tile, RADIX, tid, a.epoch, total);
-      s_goff[tid] = a.digit_base[(int64_t)seg * a.base_stride + a.pass * RADIX + tid] +
-                    (int64_t)excl - (int64_t)lstart;
-    }
     __syncthreads();
 
     // Write out: consecutive threads take consecutive staged keys, so every
     // digit run is stored contiguously.
-    const int64_t lim = range_count(P, a.range_kind);
-    for (int p = tid; p < cnt; p += BLOCK) {
-      const uint64_t k = s_stage[p];
-      const int64_t pos = s_goff[(uint32_t)(k >> shift) & (RADIX - 1)] + p;
-      if ((uint64_t)(pos - start) < (uint64_t)lim) a.out[pos] = k;  // in range by construction
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int p = i * BLOCK + tid;
+      if (p < cnt) {
+        const uint64_t k = s_stage[p];
+        const int64_t pos = s_goff[(uint32_t)(k >> shift) & (RADIX - 1)] + p;
+        if ((uint64_t)(pos - H.start) < (uint64_t)H.count) G(a.out)[pos] = k;  // in range by construction
+      }
     }
+    for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
     __syncthreads();
   }
 }
 
-template <int BLOCK, int ITEMS>
-static hipError_t launch_sort_t(const SortLaunch &a, int mode, int grid, hipStream_t s) {
-  switch (mode) {
-    case SORT_NODE_FIRST:
-      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_NODE_FIRST>), dim3(grid), dim3(BLOCK), 0,
-                         s, a);
-      break;
-    case SORT_IN_FIRST:
-      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_IN_FIRST>), dim3(grid), dim3(BLOCK), 0, s,
-                         a);
-      break;
-    default:
-      hipLaunchKernelGGL((k_sort_pass<BLOCK, ITEMS, SORT_PLAIN>), dim3(grid), dim3(BLOCK), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
 int sort_tile(int items) { return 256 * items; }
 
-template <int BLOCK, int ITEMS>
-static int max_grid_t(int mode) {
+int64_t sort_runs(int64_t tiles) { return (tiles + UP_TILES - 1) / UP_TILES; }
+
+// Blocks of the downsweep that fit on the device at once.
+template <int ITEMS>
+static int resident_t() {
   int nb = 0;
-  hipError_t e;
-  switch (mode) {
-    case SORT_NODE_FIRST:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, k_sort_pass<BLOCK, ITEMS, SORT_NODE_FIRST>, BLOCK, 0);
-      break;
-    case SORT_IN_FIRST:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, k_sort_pass<BLOCK, ITEMS, SORT_IN_FIRST>, BLOCK, 0);
-      break;
-    default:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass<BLOCK, ITEMS, SORT_PLAIN>,
-                                                       BLOCK, 0);
-  }
-  if (e != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_downsweep<256, ITEMS, SORT_PLAIN>, 256,
+                                                   0) != hipSuccess ||
+      nb < 1)
+    nb = 1;
   return nb * device_cu_count();
 }
 
-int sort_max_grid(int items, int mode) {
+int sort_resident_blocks(int items) {
   switch (items) {
-    case 8: return max_grid_t<256, 8>(mode);
-    case 12: return max_grid_t<256, 12>(mode);
-    default: return max_grid_t<256, 16>(mode);
+    case 8: return resident_t<8>();
+    case 12: return resident_t<12>();
+    default: return resident_t<16>();
   }
 }
 
-hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, int grid, hipStream_t s) {
+template <int ITEMS, int MODE>
+static hipError_t launch_pass_t(const SortLaunch &a, hipStream_t s) {
+  const int64_t runs = sort_runs(a.total_tiles);
+  hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS);
+  hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
+  hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a);
+  const int64_t g = std::min<int64_t>(a.total_tiles, resident_t<ITEMS>());
+  hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int ITEMS>
+static hipError_t launch_pass_items(const SortLaunch &a, int mode, hipStream_t s) {
+  switch (mode) {
+    case SORT_NODE_FIRST: return launch_pass_t<ITEMS, SORT_NODE_FIRST>(a, s);
+    case SORT_IN_FIRST: return launch_pass_t<ITEMS, SORT_IN_FIRST>(a, s);
+    default: return launch_pass_t<ITEMS, SORT_PLAIN>(a, s);
+  }
+}
+
+hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s) {
   if (a.total_tiles == 0) return hipSuccess;
   switch (items) {
-    case 8: return launch_sort_t<256, 8>(a, mode, grid, s);
-    case 12: return launch_sort_t<256, 12>(a, mode, grid, s);
-    default: return launch_sort_t<256, 16>(a, mode, grid, s);
+    case 8: return launch_pass_items<8>(a, mode, s);
+    case 12: return launch_pass_items<12>(a, mode, s);
+    default: return launch_pass_items<16>(a, mode, s);
   }
 }
 
@@ -455,7 +611,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_unique(TileLaunch t, const uint6
     const int64_t tile = s_tile;
     if (tile >= t.total_tiles) break;
     const int seg = s_seg;
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const int64_t first = t.tmap[seg];
     const int64_t base = (tile - first) * (int64_t)TILE;
     const int64_t start = range_start(P, t.range_kind);
@@ -488,7 +644,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_unique(TileLaunch t, const uint6
       if (lane == 0) {
         uint64_t ex;
         if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
-          ex = lb_resolve(status, tile, 1, 0, epoch, tot);
+          ex = lb_resolve(status, tile, first, 1, 0, epoch, tot);
         s_prefix = (int64_t)ex;
         s_total = (int64_t)ex + tot;
       }
@@ -533,7 +689,7 @@ __device__ __forceinline__ int dir_shift(uint64_t lo, uint64_t hi, int dirk) {
 __global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes, uint32_t *dir) {
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const uint64_t *nd = nodes + 2 * P.row_off;
     const uint64_t lo = nd[0], hi = nd[P.V - 1];
     const int shift = dir_shift(lo, hi, P.dirk);
@@ -542,7 +698,7 @@ __global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes
     const int64_t end = std::min<int64_t>(base + DIR_TILE, P.V);
     for (int64_t j = base + threadIdx.x; j < end; j += 256) {
       const uint64_t u = nd[j];
-      P.node_ids[j] = (int64_t)(u ^ SIGN_FLIP);
+      G(P.node_ids)[j] = (int64_t)(u ^ SIGN_FLIP);
       const int64_t q = (int64_t)((u - lo) >> shift);
       const int64_t qp = j == 0 ? -1 : (int64_t)((nd[j - 1] - lo) >> shift);
       for (int64_t x = qp + 1; x <= q; ++x) D[x] = (uint32_t)j;
@@ -603,7 +759,7 @@ __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nod
       if (cur >= 0) flush(cur);
       cur = seg;
     }
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const uint64_t *nd = nodes + 2 * P.row_off;
     const uint64_t lo = nd[0], hi = nd[P.V - 1];
     const int shift = dir_shift(lo, hi, P.dirk);
@@ -613,8 +769,8 @@ __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nod
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
     for (int64_t r = base + tid; r < end; r += 256) {
-      const uint64_t s = node_rank(nd, D, lo, shift, nb, (uint64_t)P.src[r] ^ SIGN_FLIP);
-      const uint64_t d = node_rank(nd, D, lo, shift, nb, (uint64_t)P.dst[r] ^ SIGN_FLIP);
+      const uint64_t s = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.src)[r] ^ SIGN_FLIP);
+      const uint64_t d = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.dst)[r] ^ SIGN_FLIP);
       const uint64_t k = (s << b) | d;
       ekeys[P.row_off + r] = k;
       for (int p = 0; p < passes; ++p)
@@ -674,7 +830,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
       }
       cur = seg;
     }
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const int64_t first = t.tmap[seg];
     const int64_t base = (tile - first) * (int64_t)TILE;
     const int64_t start = P.row_off;
@@ -714,7 +870,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
       if (lane == 0) {
         uint64_t ex;
         if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
-          ex = lb_resolve(status, tile, 1, 0, epoch, tot);
+          ex = lb_resolve(status, tile, first, 1, 0, epoch, tot);
         s_prefix = (int64_t)ex;
         s_total = (int64_t)ex + tot;
       }
@@ -732,13 +888,13 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
         const int64_t hsrc = std::min<int64_t>((int64_t)(k >> b), P.V - 1);
         const int64_t hp =
             (base + idx == 0) ? -1 : (int64_t)((idx > 0 ? s_k[idx - 1] : before) >> b);
-        for (int64_t v = hp + 1; v <= hsrc; ++v) P.out_off[v] = j;
+        for (int64_t v = hp + 1; v <= hsrc; ++v) G(P.out_off)[v] = j;
       }
       if (last_tile && idx == cnt - 1) {
         // the last row of the table closes the offsets
         const int64_t E = s_total;
         for (int64_t v = std::min<int64_t>((int64_t)(s_k[idx] >> b), P.V - 1) + 1; v <= P.V; ++v)
-          P.out_off[v] = E;
+          G(P.out_off)[v] = E;
       }
     }
     if (tid == 0 && last_tile) seg_count[seg] = s_total;
@@ -769,18 +925,18 @@ hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
 __global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in) {
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
-    const SegPlan &P = t.plan[seg];
+    const SegPlan P = t.plan[seg];
     const uint64_t *K = in + P.row_off;
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
     const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.E);
     for (int64_t j = base + threadIdx.x; j < end; j += 256) {
       const uint64_t k = K[j];
-      P.in_nbr[j] = (int32_t)(uint32_t)k;
+      G(P.in_nbr)[j] = (int32_t)(uint32_t)k;
       const int64_t h = std::min<int64_t>((int64_t)(k >> 32), P.V - 1);
       const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(K[j - 1] >> 32), P.V - 1);
-      for (int64_t v = hp + 1; v <= h; ++v) P.in_off[v] = j;
+      for (int64_t v = hp + 1; v <= h; ++v) G(P.in_off)[v] = j;
       if (j == P.E - 1)
-        for (int64_t v = h + 1; v <= P.V; ++v) P.in_off[v] = P.E;
+        for (int64_t v = h + 1; v <= P.V; ++v) G(P.in_off)[v] = P.E;
     }
   }
 }

@@ -175,6 +175,8 @@ struct Call {
   int64_t *results = nullptr;
   uint8_t *meta = nullptr;
   uint32_t *dir = nullptr;
+  uint32_t *counts = nullptr;
+  uint32_t *bsum = nullptr;
   size_t meta_bytes = 0;
   Pinned *pin = nullptr;
   int upload_slot = 0;
@@ -184,7 +186,7 @@ struct Call {
   ~Call() { release_workspace(); }
 
   void release_workspace() {
-    void *bufs[] = {A, B, status, hist, base, counters, results, meta, dir};
+    void *bufs[] = {A, B, status, hist, base, counters, results, meta, dir, counts, bsum};
     for (void *b : bufs) dev_free(hooks, b, stream);
     A = B = nullptr;
     status = nullptr;
@@ -194,6 +196,8 @@ struct Call {
     results = nullptr;
     meta = nullptr;
     dir = nullptr;
+    counts = nullptr;
+    bsum = nullptr;
     if (pin) pinned_release(pin, stream);
     pin = nullptr;
   }
@@ -254,13 +258,12 @@ struct Call {
     a.num_segs = S;
     a.range_kind = range;
     a.total_tiles = total(kind);
+    a.shift = shift;
+    a.pass = pass;
     a.digit_base = base;
     a.base_stride = passes * RADIX;
-    a.pass = pass;
-    a.shift = shift;
-    a.epoch = ++epoch;
-    a.status = status;
-    a.counter = counters + a.epoch;
+    a.counts = counts;
+    a.bsum = bsum;
     return a;
   }
 };
@@ -380,8 +383,10 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
   c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
 
-  const int64_t status_words =
-      std::max<int64_t>(c.total(TM_NSORT) * RADIX, c.total(TM_UNIQ)) + RADIX;
+  const int64_t status_words = c.total(TM_UNIQ) + RADIX;  // one word per unique/dedupe tile
+  // the node pass has the most tiles: 2n keys per table
+  const int64_t max_tiles = c.total(TM_NSORT) + 1;
+  const int64_t max_runs = sort_runs(max_tiles) + 1;
   c.meta_bytes = align_up(align_up(sizeof(SegPlan) * S) + sizeof(int64_t) * c.tmap.size());
   c.pin = pinned_acquire(3 * c.meta_bytes + sizeof(int64_t) * S);
   if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
@@ -395,7 +400,10 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
   c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * 2 * S, st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
-  if (!c.A || !c.B || !c.status || !c.hist || !c.base || !c.counters || !c.results || !c.meta)
+  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
+  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_runs, st);
+  if (!c.A || !c.B || !c.status || !c.hist || !c.base || !c.counters || !c.results || !c.meta ||
+      !c.counts || !c.bsum)
     return RINGO_ERR_OUT_OF_MEMORY;
 
   HIP_TRY(c.upload());
@@ -411,14 +419,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, NODE_PASSES, RANGE_NODE_KEYS, st));
   uint64_t *buf[2] = {c.A, c.B};
   {
-    const int g0 = grid_for(c.total(TM_NSORT), sort_max_grid(c.items, SORT_NODE_FIRST));
-    const int g1 = grid_for(c.total(TM_NSORT), sort_max_grid(c.items, SORT_PLAIN));
     for (int p = 0; p < NODE_PASSES; ++p) {
       SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
                                  RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
       TRACED(TK_SORT_NODE, 2 * N, 32.0 * N,
-             launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
-                              st));
+             launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, st));
     }
   }
   uint64_t *sorted_nodes = buf[(NODE_PASSES - 1) & 1];
@@ -490,11 +495,10 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                       grid_for(c.total(TM_REMAP), cus * 8), st));
   HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_e, RANGE_ROWS, st));
   {
-    const int g = grid_for(c.total(TM_ESORT), sort_max_grid(c.items, SORT_PLAIN));
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
                                  RADIX_BITS * p);
-      TRACED(TK_SORT_EDGE, N, 16.0 * N, launch_sort_pass(a, SORT_PLAIN, c.items, g, st));
+      TRACED(TK_SORT_EDGE, N, 16.0 * N, launch_sort_pass(a, SORT_PLAIN, c.items, st));
     }
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
@@ -538,14 +542,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_in, RANGE_EDGES, st));
   uint64_t *ibuf[2] = {ukeys, sorted_edges};
   {
-    const int g0 = grid_for(c.total(TM_ISORT), sort_max_grid(c.items, SORT_IN_FIRST));
-    const int g1 = grid_for(c.total(TM_ISORT), sort_max_grid(c.items, SORT_PLAIN));
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + RADIX_BITS * p);
       TRACED(TK_SORT_IN, sumE, (p == 0 ? 20.0 : 16.0) * sumE,
-             launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, p == 0 ? g0 : g1,
-                              st));
+             launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, st));
     }
   }
   TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),

@@ -73,17 +73,16 @@ struct SortLaunch {
   const uint64_t *in;
   uint64_t *out;
   const SegPlan *plan;
-  const int64_t *tmap;      // [S+1] first tile of each table
+  const int64_t *tmap;        // [S+1] first tile of each table
   int32_t num_segs;
   int32_t range_kind;
   int64_t total_tiles;
+  int32_t shift;
+  int32_t pass;
   const int64_t *digit_base;  // [S][passes][RADIX], absolute output positions
   int32_t base_stride;        // passes * RADIX
-  int32_t pass;
-  int32_t shift;
-  uint32_t epoch;
-  uint64_t *status;
-  uint32_t *counter;
+  uint32_t *counts;           // [tiles][RADIX] digit counts, then their prefixes
+  uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
 };
 
 enum SortMode : int { SORT_PLAIN = 0, SORT_NODE_FIRST = 1, SORT_IN_FIRST = 2 };
@@ -101,9 +100,10 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s
 hipError_t launch_hist_node(const TileLaunch &t, uint32_t *hist, int grid, hipStream_t s);
 hipError_t launch_scan_hist(const uint32_t *hist, int64_t *base, const SegPlan *plan, int32_t S,
                             int32_t passes, int32_t range_kind, hipStream_t s);
-hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, int grid, hipStream_t s);
+hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s);
 int sort_tile(int items);
-int sort_max_grid(int items, int mode);
+int sort_resident_blocks(int items);
+int64_t sort_runs(int64_t tiles);
 hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
                          uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
                          hipStream_t s);
