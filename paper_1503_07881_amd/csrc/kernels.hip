@@ -196,88 +196,6 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------- histograms
-
-// Digit histograms of all 8 passes of the node keys, read once from the
-// input columns.  Per-wave LDS copies spread the atomics of repeated
-// identifiers; a block flushes when its tiles move to another table.
-__global__ __launch_bounds__(256) void k_hist_node(TileLaunch t, uint32_t *hist) {
-  constexpr int W = 4, H = NODE_PASSES * RADIX;
-  __shared__ uint32_t s_h[W * H];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  for (int i = tid; i < W * H; i += 256) s_h[i] = 0;
-  __syncthreads();
-  int cur = -1;
-  auto flush = [&](int seg) {
-    __syncthreads();
-    for (int i = tid; i < H; i += 256) {
-      uint32_t v = 0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        v += s_h[w * H + i];
-        s_h[w * H + i] = 0;
-      }
-      if (v) atomicAdd(&hist[(int64_t)seg * H + i], v);
-    }
-    __syncthreads();
-  };
-  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
-    const int seg = find_seg(t.tmap, t.num_segs, tile);
-    if (seg != cur) {
-      if (cur >= 0) flush(cur);
-      cur = seg;
-    }
-    const SegPlan P = t.plan[seg];
-    const int64_t base = (tile - t.tmap[seg]) * (int64_t)HIST_TILE;
-    const int64_t end = std::min<int64_t>(base + HIST_TILE, 2 * P.n);
-    uint32_t *h = s_h + wave * H;
-    const __attribute__((address_space(1))) int64_t *src = G(P.src), *dst = G(P.dst);
-    for (int64_t e0 = base + tid; e0 < end; e0 += 4 * 256) {
-      uint64_t k[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t e = std::min<int64_t>(e0 + j * 256, end - 1);  // in range; counted once below
-        const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? src + e : dst + (e - P.n);
-        k[j] = (uint64_t)*ptr ^ SIGN_FLIP;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (e0 + j * 256 < end) {
-#pragma unroll
-          for (int p = 0; p < NODE_PASSES; ++p)
-            atomicAdd(&h[p * RADIX + ((k[j] >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
-        }
-      }
-    }
-  }
-  if (cur >= 0) flush(cur);
-}
-
-hipError_t launch_hist_node(const TileLaunch &t, uint32_t *hist, int grid, hipStream_t s) {
-  if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hist_node, dim3(grid), dim3(256), 0, s, t, hist);
-  return hipGetLastError();
-}
-
-// Exclusive scan of each (table, pass) histogram into absolute positions.
-__global__ __launch_bounds__(RADIX) void k_scan_hist(const uint32_t *hist, int64_t *base,
-                                                      const SegPlan *plan, int32_t passes,
-                                                      int32_t kind) {
-  __shared__ uint32_t s_w[RADIX / 64];
-  const int seg = blockIdx.x / passes;
-  const int64_t row = (int64_t)blockIdx.x * RADIX;
-  uint32_t total;
-  const uint32_t ex = block_excl_scan<RADIX>(hist[row + threadIdx.x], s_w, total);
-  base[row + threadIdx.x] = range_start(plan[seg], kind) + (int64_t)ex;
-}
-
-hipError_t launch_scan_hist(const uint32_t *hist, int64_t *base, const SegPlan *plan, int32_t S,
-                            int32_t passes, int32_t range_kind, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_hist, dim3(S * passes), dim3(RADIX), 0, s, hist, base, plan, passes,
-                     range_kind);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------ LSD pass
 //
 // One stable counting-sort pass on RADIX_BITS digits, reduce-then-scan at
@@ -393,6 +311,8 @@ __global__ __launch_bounds__(1024) void k_block_scan(SortLaunch a, int64_t runs)
     carry += tot;
     __syncthreads();
   }
+  // sentinel row: prefix one past the last tile
+  if (tid == 0) a.counts[a.total_tiles * RADIX + d] = carry;
 }
 
 // Tile counts become exclusive prefixes, in place; one block per run.
@@ -406,6 +326,19 @@ __global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a) {
     a.counts[t * RADIX + d] = run;
     run += v;
   }
+}
+
+// Digit bases of every table for this pass: the table's digit totals are
+// differences of tile prefixes across its tiles; their exclusive scan over
+// digits, plus the table's range start, is where each digit's run begins.
+__global__ __launch_bounds__(RADIX) void k_seg_base(SortLaunch a) {
+  __shared__ uint32_t s_w[RADIX / 64];
+  const int seg = blockIdx.x, d = threadIdx.x;
+  const int64_t f = a.tmap[seg], l = a.tmap[seg + 1];
+  const uint32_t tot = l > f ? a.counts[l * RADIX + d] - a.counts[f * RADIX + d] : 0u;
+  uint32_t all;
+  const uint32_t ex = block_excl_scan<RADIX>(tot, s_w, all);
+  a.digit_base[(int64_t)seg * RADIX + d] = range_start(a.plan[seg], a.range_kind) + (int64_t)ex;
 }
 
 template <int BLOCK, int ITEMS, int MODE>
@@ -431,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void k_downsweep(SortLaunch a) {
     if (tile >= H.end) {
       H.at(a, tile);
       if (tid < RADIX) {
-        dbase = a.digit_base[(int64_t)H.seg * a.base_stride + a.pass * RADIX + tid];
+        dbase = a.digit_base[(int64_t)H.seg * RADIX + tid];
         pfirst = a.counts[H.first * RADIX + tid];
       }
     }
@@ -554,6 +487,7 @@ static hipError_t launch_pass_t(const SortLaunch &a, hipStream_t s) {
   hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS);
   hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
   hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a);
+  hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
   const int64_t g = std::min<int64_t>(a.total_tiles, resident_t<ITEMS>());
   hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -736,29 +670,10 @@ __device__ __forceinline__ uint32_t node_rank(const uint64_t *nd, const uint32_t
 }
 
 __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nodes,
-                                               const uint32_t *dir, uint64_t *ekeys,
-                                               uint32_t *hist, int32_t passes) {
-  __shared__ uint32_t s_h[MAX_PASSES * RADIX];
+                                               const uint32_t *dir, uint64_t *ekeys) {
   const int tid = threadIdx.x;
-  const int H = passes * RADIX;
-  for (int i = tid; i < H; i += 256) s_h[i] = 0;
-  __syncthreads();
-  int cur = -1;
-  auto flush = [&](int seg) {
-    __syncthreads();
-    for (int i = tid; i < H; i += 256) {
-      const uint32_t v = s_h[i];
-      s_h[i] = 0;
-      if (v) atomicAdd(&hist[(int64_t)seg * H + i], v);
-    }
-    __syncthreads();
-  };
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
-    if (seg != cur) {
-      if (cur >= 0) flush(cur);
-      cur = seg;
-    }
     const SegPlan P = t.plan[seg];
     const uint64_t *nd = nodes + 2 * P.row_off;
     const uint64_t lo = nd[0], hi = nd[P.V - 1];
@@ -771,44 +686,34 @@ __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nod
     for (int64_t r = base + tid; r < end; r += 256) {
       const uint64_t s = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.src)[r] ^ SIGN_FLIP);
       const uint64_t d = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.dst)[r] ^ SIGN_FLIP);
-      const uint64_t k = (s << b) | d;
-      ekeys[P.row_off + r] = k;
-      for (int p = 0; p < passes; ++p)
-        atomicAdd(&s_h[p * RADIX + ((k >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
+      G(ekeys)[P.row_off + r] = (s << b) | d;
     }
   }
-  if (cur >= 0) flush(cur);
 }
 
 hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const uint32_t *dir,
-                        uint64_t *ekeys, uint32_t *hist, int32_t passes, int grid, hipStream_t s) {
+                        uint64_t *ekeys, int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys, hist, passes);
+  hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys);
   return hipGetLastError();
 }
 
 // --------------------------------------------------------------- dedupe
 //
 // Adjacent compare of the sorted edge keys, compaction of the first copy of
-// every edge, out-offsets by boundary fill (out_off[v] = position of the
-// first edge whose source is >= v), and the digit histograms of the in-sort
-// (digits of the destination) over the unique edges.
+// every edge, and out-offsets by boundary fill (out_off[v] = position of
+// the first edge whose source is >= v).
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint64_t *in,
                                                        uint64_t *out, int64_t *seg_count,
-                                                       uint32_t *hist, int32_t passes,
                                                        uint64_t *status, uint32_t *counter,
                                                        uint32_t epoch) {
   constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
   __shared__ uint64_t s_k[TILE];
   __shared__ uint32_t s_cnt[64];
-  __shared__ uint32_t s_h[MAX_PASSES * RADIX];
   __shared__ int64_t s_tile, s_prefix, s_total;
   __shared__ int32_t s_seg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int H = passes * RADIX;
-  for (int i = tid; i < H; i += BLOCK) s_h[i] = 0;
-  int cur = -1;
   for (;;) {
     if (tid == 0) {
       const int64_t tt = (int64_t)atomicAdd(counter, 1u);
@@ -819,17 +724,6 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
     const int64_t tile = s_tile;
     if (tile >= t.total_tiles) break;
     const int seg = s_seg;
-    if (seg != cur) {
-      if (cur >= 0) {
-        for (int i = tid; i < H; i += BLOCK) {
-          const uint32_t v = s_h[i];
-          s_h[i] = 0;
-          if (v) atomicAdd(&hist[(int64_t)cur * H + i], v);
-        }
-        __syncthreads();
-      }
-      cur = seg;
-    }
     const SegPlan P = t.plan[seg];
     const int64_t first = t.tmap[seg];
     const int64_t base = (tile - first) * (int64_t)TILE;
@@ -837,7 +731,6 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
     const int64_t count = P.n;
     const int cnt = (int)std::min<int64_t>(TILE, count - base);
     const int b = P.b;
-    const uint64_t dmask = (1ull << b) - 1;
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = i * BLOCK + tid;
       if (idx < cnt) s_k[idx] = in[start + base + idx];
@@ -852,11 +745,6 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
       if (idx < cnt) {
         const uint64_t k = s_k[idx];
         h = (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
-        if (h) {
-          const uint64_t d = k & dmask;
-          for (int p = 0; p < passes; ++p)
-            atomicAdd(&s_h[p * RADIX + ((d >> (RADIX_BITS * p)) & (RADIX - 1))], 1u);
-        }
       }
       heads[i] = __ballot(h);
       if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
@@ -900,20 +788,14 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
     if (tid == 0 && last_tile) seg_count[seg] = s_total;
     __syncthreads();
   }
-  if (cur >= 0) {
-    for (int i = tid; i < H; i += BLOCK) {
-      const uint32_t v = s_h[i];
-      if (v) atomicAdd(&hist[(int64_t)cur * H + i], v);
-    }
-  }
 }
 
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
-                         int64_t *seg_count, uint32_t *hist, int32_t passes, uint64_t *status,
-                         uint32_t *counter, uint32_t epoch, int grid, hipStream_t s) {
+                         int64_t *seg_count, uint64_t *status, uint32_t *counter,
+                         uint32_t epoch, int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dedupe, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count, hist,
-                     passes, status, counter, epoch);
+  hipLaunchKernelGGL(k_dedupe, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count,
+                     status, counter, epoch);
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 // One call converts S >= 1 tables.  Every phase runs once for the whole
 // batch, each kernel walking the tiles of all tables:
 //
-//   phase N  node histogram, 8 radix passes over the 2n node keys, unique
+//   phase N  8 radix passes over the 2n node keys, unique
 //   sync #1  read back V of every table, size the node-sized outputs
 //   phase E  directory, remap + pack, radix passes over the packed edge
 //            keys, dedupe + out-offsets
@@ -152,7 +152,7 @@ int items_for(int64_t rows) {
 // ----------------------------------------------------------- tile maps
 
 enum TileKind {
-  TM_HIST, TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR, TM_KINDS
+  TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR, TM_KINDS
 };
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -169,7 +169,6 @@ struct Call {
   // device workspace
   uint64_t *A = nullptr, *B = nullptr;
   uint64_t *status = nullptr;
-  uint32_t *hist = nullptr;
   int64_t *base = nullptr;
   uint32_t *counters = nullptr;
   int64_t *results = nullptr;
@@ -186,11 +185,10 @@ struct Call {
   ~Call() { release_workspace(); }
 
   void release_workspace() {
-    void *bufs[] = {A, B, status, hist, base, counters, results, meta, dir, counts, bsum};
+    void *bufs[] = {A, B, status, base, counters, results, meta, dir, counts, bsum};
     for (void *b : bufs) dev_free(hooks, b, stream);
     A = B = nullptr;
     status = nullptr;
-    hist = nullptr;
     base = nullptr;
     counters = nullptr;
     results = nullptr;
@@ -259,9 +257,7 @@ struct Call {
     a.range_kind = range;
     a.total_tiles = total(kind);
     a.shift = shift;
-    a.pass = pass;
     a.digit_base = base;
-    a.base_stride = passes * RADIX;
     a.counts = counts;
     a.bsum = bsum;
     return a;
@@ -282,10 +278,10 @@ struct Call {
 // counts, summed durations and the algorithmic bytes the launches move.
 
 enum TraceKind {
-  TK_HIST_NODE, TK_SORT_NODE, TK_UNIQUE, TK_DIR, TK_REMAP, TK_SORT_EDGE, TK_DEDUPE, TK_SORT_IN,
+  TK_SORT_NODE, TK_UNIQUE, TK_DIR, TK_REMAP, TK_SORT_EDGE, TK_DEDUPE, TK_SORT_IN,
   TK_IN_CSR, TK_AUX, TK_KINDS
 };
-const char *const kTraceNames[TK_KINDS] = {"hist_node", "sort_pass_node", "unique", "directory",
+const char *const kTraceNames[TK_KINDS] = {"sort_pass_node", "unique", "directory",
                                            "remap_pack", "sort_pass_edge", "dedupe_out_csr",
                                            "sort_pass_in", "in_csr", "aux"};
 
@@ -379,7 +375,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   c.items = items_for(S == 1 ? max_rows : N);
   c.sort_tile = sort_tile(c.items);
-  c.set_tiles(TM_HIST, RANGE_NODE_KEYS, HIST_TILE);
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
   c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
 
@@ -391,32 +386,26 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.pin = pinned_acquire(3 * c.meta_bytes + sizeof(int64_t) * S);
   if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
 
-  const size_t hist_words = (size_t)S * MAX_PASSES * RADIX;
+  const size_t base_words = (size_t)S * RADIX;
   c.A = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
   c.B = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
   c.status = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * status_words, st);
-  c.hist = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * hist_words, st);
-  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * hist_words, st);
+  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * base_words, st);
   c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
   c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * 2 * S, st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
   c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
   c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_runs, st);
-  if (!c.A || !c.B || !c.status || !c.hist || !c.base || !c.counters || !c.results || !c.meta ||
+  if (!c.A || !c.B || !c.status || !c.base || !c.counters || !c.results || !c.meta ||
       !c.counts || !c.bsum)
     return RINGO_ERR_OUT_OF_MEMORY;
 
   HIP_TRY(c.upload());
   HIP_TRY(launch_fill_u64(c.status, 0, status_words, st));
-  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
   HIP_TRY(launch_fill_u64((uint64_t *)c.counters, 0, 128, st));
   HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
 
   // ------------------------------------------------------------- phase N
-  TRACED(TK_HIST_NODE, 2 * N, 16.0 * N,
-         launch_hist_node(c.tiles(TM_HIST, RANGE_NODE_KEYS), c.hist,
-                          grid_for(c.total(TM_HIST), cus * 4), st));
-  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, NODE_PASSES, RANGE_NODE_KEYS, st));
   uint64_t *buf[2] = {c.A, c.B};
   {
     for (int p = 0; p < NODE_PASSES; ++p) {
@@ -484,16 +473,14 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
 
   // ------------------------------------------------------------- phase E
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
-  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
   TRACED(TK_DIR, sumV, 16.0 * sumV + 4.0 * dir_words,
          launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
                     grid_for(c.total(TM_DIR), cus * 8), st));
   // the sorted node keys are consumed: their buffer takes the edge keys
   uint64_t *ebuf[2] = {sorted_nodes, nodes_ws};
   TRACED(TK_REMAP, N, 24.0 * N,
-         launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0], c.hist, P_e,
+         launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0],
                       grid_for(c.total(TM_REMAP), cus * 8), st));
-  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_e, RANGE_ROWS, st));
   {
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
@@ -503,12 +490,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
   uint64_t *ukeys = ebuf[(P_e + 1) & 1];
-  HIP_TRY(launch_fill_u64((uint64_t *)c.hist, 0, (int64_t)hist_words / 2, st));
   {
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
     HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, RANGE_ROWS), sorted_edges, ukeys, c.results + S,
-                          c.hist, P_in, c.status, c.counters + ep, ep,
+                          c.status, c.counters + ep, ep,
                           grid_for(c.total(TM_DEDUP), cus * 4), st));
     dedupe_rec = trace_end(m, TK_DEDUPE, N, 8.0 * N, st);
   }
@@ -539,7 +525,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(c.upload());
 
   // ------------------------------------------------------------- phase I
-  HIP_TRY(launch_scan_hist(c.hist, c.base, c.plan_dev(), S, P_in, RANGE_EDGES, st));
   uint64_t *ibuf[2] = {ukeys, sorted_edges};
   {
     for (int p = 0; p < P_in; ++p) {

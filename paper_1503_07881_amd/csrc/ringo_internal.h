@@ -9,14 +9,12 @@ namespace ringo {
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int NODE_PASSES = 64 / RADIX_BITS;    // node identifiers are 64-bit keys
-constexpr int MAX_PASSES = 8;
 constexpr uint64_t SIGN_FLIP = 0x8000000000000000ull;  // unsigned order == signed order
 
 // Tile sizes (elements per tile) of the non-sorting kernels.
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;   // unique / dedupe / in-CSR
-constexpr int HIST_TILE = 256 * 128;                 // node histogram chunk
 constexpr int REMAP_TILE = 256 * 32;                 // rows per remap tile
 constexpr int DIR_TILE = 256 * 16;                   // nodes per directory tile
 
@@ -78,10 +76,8 @@ struct SortLaunch {
   int32_t range_kind;
   int64_t total_tiles;
   int32_t shift;
-  int32_t pass;
-  const int64_t *digit_base;  // [S][passes][RADIX], absolute output positions
-  int32_t base_stride;        // passes * RADIX
-  uint32_t *counts;           // [tiles][RADIX] digit counts, then their prefixes
+  int64_t *digit_base;        // [S][RADIX] first output position of each digit's run
+  uint32_t *counts;           // [tiles + 1][RADIX] digit counts, then their prefixes
   uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
 };
 
@@ -97,9 +93,6 @@ struct TileLaunch {
 
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
-hipError_t launch_hist_node(const TileLaunch &t, uint32_t *hist, int grid, hipStream_t s);
-hipError_t launch_scan_hist(const uint32_t *hist, int64_t *base, const SegPlan *plan, int32_t S,
-                            int32_t passes, int32_t range_kind, hipStream_t s);
 hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s);
 int sort_tile(int items);
 int sort_resident_blocks(int items);
@@ -110,10 +103,10 @@ hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out,
 hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, uint32_t *dir, int grid,
                       hipStream_t s);
 hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const uint32_t *dir,
-                        uint64_t *ekeys, uint32_t *hist, int32_t passes, int grid, hipStream_t s);
+                        uint64_t *ekeys, int grid, hipStream_t s);
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
-                         int64_t *seg_count, uint32_t *hist, int32_t passes, uint64_t *status,
-                         uint32_t *counter, uint32_t epoch, int grid, hipStream_t s);
+                         int64_t *seg_count, uint64_t *status, uint32_t *counter,
+                         uint32_t epoch, int grid, hipStream_t s);
 hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s);
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
 int device_cu_count();
