@@ -72,12 +72,84 @@ def cpu_baseline(rows: int):
                       f"{dt:.2f} s"}
 
 
+def bench_batched(args):
+    """4096 tables, rows log-uniform in [1e3, 2e6]: one batched call against
+    one call per table, same GPU, outputs compared bit for bit."""
+    import torch
+    from paper_1503_07881_amd import ringo, workloads
+    dev = torch.device("cuda:0")
+    specs = workloads.config4()
+    total = sum(s.n for s in specs)
+    log(f"bench: batched workload, {len(specs)} tables, {total:,} rows")
+    src = torch.empty(total, dtype=torch.int64, device=dev)
+    dst = torch.empty(total, dtype=torch.int64, device=dev)
+    sh = torch.cuda.current_stream().cuda_stream
+    offs, off = [], 0
+    for s in specs:
+        workloads.generate_device(s, src.data_ptr() + 8 * off, dst.data_ptr() + 8 * off, sh)
+        offs.append((off, s.n))
+        off += s.n
+    torch.cuda.synchronize()
+    sp = [src.data_ptr() + 8 * o for o, _ in offs]
+    dp = [dst.data_ptr() + 8 * o for o, _ in offs]
+    ns = [n for _, n in offs]
+
+    def batched():
+        return ringo.table_to_graph_batched_raw(sp, dp, ns, sh)
+
+    def singles():
+        out = []
+        for s_, d_, n_ in zip(sp, dp, ns):
+            out.append(ringo.table_to_graph_raw(s_, d_, n_, sh))
+        return out
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gs = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            for g in gs:
+                ringo.graph_free(g)
+        return sorted(ts)[len(ts) // 2]
+
+    for g in batched():
+        ringo.graph_free(g)
+    for g in singles():
+        ringo.graph_free(g)
+    t_b = timed(batched, max(1, args.steps))
+    log(f"bench: batched {t_b * 1e3:.1f} ms")
+    t_s = timed(singles, max(1, min(args.steps, 3)))
+    log(f"bench: one call per table {t_s * 1e3:.1f} ms")
+    # identical output, table by table, on the device
+    gb = [ringo._wrap(r, dev) for r in batched()]
+    mismatches = 0
+    for i, (s_, d_, n_) in enumerate(zip(sp, dp, ns)):
+        g1 = ringo._wrap(ringo.table_to_graph_raw(s_, d_, n_, sh), dev)
+        for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs"):
+            if not torch.equal(getattr(gb[i], f), getattr(g1, f)):
+                mismatches += 1
+                break
+    out = {
+        "metric": "batched speedup: one batched call vs one call per table (same GPU, identical output)",
+        "value": t_s / t_b, "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_b * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic (seeded uniform and R-MAT tables generated on the device)",
+        "config": {"workload": "batch_4096_tables_rows_1e3_to_2e6", "tables": len(specs), "rows": total},
+        "batched_edges_per_s": total / t_b, "single_calls_edges_per_s": total / t_s,
+        "single_calls_ms": t_s * 1e3, "tables_differing": mismatches,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3))
+    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4))
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -86,6 +158,10 @@ def main():
               f"(the conversion runs on a single MI355X; see DESIGN.md for how it would shard).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == 4:
+        bench_batched(args)
+        return
 
     import torch
     from paper_1503_07881_amd import ringo, workloads

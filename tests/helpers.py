@@ -135,7 +135,8 @@ def check_invariants_torch(g, src, dst):
     assert bool((pos_s < V).all()) and bool((pos_d < V).all())
     assert bool((nodes[pos_s] == src).all()) and bool((nodes[pos_d] == dst).all())
     del pos_s, pos_d
-    uniq_v = torch.unique(torch.cat([src, dst])).numel()
+    # (torch.unique takes fewer than 2^31 elements: unique each column first)
+    uniq_v = torch.unique(torch.cat([torch.unique(src), torch.unique(dst)])).numel()
     assert V == uniq_v, f"V {V} != distinct identifiers {uniq_v}"
     ar = torch.arange(V, device=nodes.device, dtype=torch.int64)
     osrc = torch.repeat_interleave(ar, oo[1:] - oo[:-1])

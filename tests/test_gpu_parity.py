@@ -153,3 +153,78 @@ def test_config2_full_size(cuda):
     say("config 2: V", g.num_nodes, "E", g.num_edges)
     check_invariants_torch(g, src, dst)
     check_sampled(g, src, dst, num_samples=200)
+
+
+def _device_tables(specs, dev):
+    """Generate every table of `specs` on the device, back to back in two
+    buffers; returns the buffers and per-table (offset, rows)."""
+    import torch
+    total = sum(s.n for s in specs)
+    src = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    dst = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    sh = torch.cuda.current_stream().cuda_stream
+    offs = []
+    off = 0
+    for s in specs:
+        if s.n:
+            workloads.generate_device(s, src.data_ptr() + 8 * off, dst.data_ptr() + 8 * off, sh)
+        offs.append((off, s.n))
+        off += s.n
+    torch.cuda.synchronize()
+    return src, dst, offs
+
+
+def _same_on_device(g1, g2):
+    import torch
+    for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs"):
+        a, b = getattr(g1, f), getattr(g2, f)
+        if a.shape != b.shape or not torch.equal(a, b):
+            return f
+    return None
+
+
+@pytest.mark.slow
+def test_config4_batched_full(cuda):
+    """All 4096 tables of the batched workload: the batched call equals one
+    call per table bit for bit, and a spread of tables equals the oracle."""
+    import torch
+    specs = workloads.config4()
+    say("config 4: 4096 tables, rows", sum(s.n for s in specs))
+    src, dst, offs = _device_tables(specs, cuda)
+    sh = torch.cuda.current_stream().cuda_stream
+    raws = ringo.table_to_graph_batched_raw([src.data_ptr() + 8 * o for o, _ in offs],
+                                            [dst.data_ptr() + 8 * o for o, _ in offs],
+                                            [n for _, n in offs], sh)
+    gb = [ringo._wrap(r, cuda) for r in raws]
+    torch.cuda.synchronize()
+    for i, (o, n) in enumerate(offs):
+        g1 = ringo._wrap(ringo.table_to_graph_raw(src.data_ptr() + 8 * o, dst.data_ptr() + 8 * o, n, sh), cuda)
+        bad = _same_on_device(gb[i], g1)
+        assert bad is None, f"table {i} ({specs[i]}): batched {bad} differs from the single call"
+        assert gb[i].num_nodes == g1.num_nodes and gb[i].num_edges == g1.num_edges
+    order = sorted(range(len(specs)), key=lambda i: specs[i].n)
+    for i in order[::170]:
+        o, n = offs[i]
+        say("config 4: oracle check of table", i, "rows", n)
+        hs, hd = src[o:o + n].cpu().numpy(), dst[o:o + n].cpu().numpy()
+        assert_same(gb[i], oracle.table_to_graph(hs, hd), f"table {i}: ")
+
+
+@pytest.mark.slow
+def test_config3_full_size(cuda):
+    """The 1.5e9-row R-MAT scale-26 workload at full size: complete
+    invariants with torch on the device and exact lists of sampled nodes."""
+    import torch
+    spec = workloads.config3()
+    say("config 3: 1.5e9 rows, device generation")
+    src = torch.empty(spec.n, dtype=torch.int64, device=cuda)
+    dst = torch.empty(spec.n, dtype=torch.int64, device=cuda)
+    workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    hs, hd = workloads.generate_host(workloads.TableSpec("rmat", 50_000, seed=spec.seed, scale=spec.scale))
+    assert np.array_equal(src[:50_000].cpu().numpy(), hs) and np.array_equal(dst[:50_000].cpu().numpy(), hd)
+    g = ringo.to_graph(src, dst)
+    torch.cuda.synchronize()
+    say("config 3: V", g.num_nodes, "E", g.num_edges)
+    check_sampled(g, src, dst, num_samples=64)
+    say("config 3: sampled lists match; invariants")
+    check_invariants_torch(g, src, dst)
