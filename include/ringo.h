@@ -159,6 +159,55 @@ typedef struct {
 void ringo_trace_enable(int on);
 int ringo_trace_read(ringo_trace_entry_t *out, int max_entries);
 
+/*
+ * Served form: an interactive request loop that keeps built graphs resident
+ * on the device (the paper's interactive-use goal, Sections 1 and 2.4).
+ * Requests are host edge tables; worker threads, each with its own stream,
+ * take every queued request that fits into one batch and convert it with
+ * ringo_table_to_graph_batched, so batches started by different workers
+ * overlap on the device.  A request is admitted only while the HBM budget
+ * holds its estimated footprint on top of the resident graphs; the least
+ * recently used resident graph is evicted when it does not.  Each result is
+ * bit-identical to ringo_table_to_graph on the same table.
+ */
+typedef struct ringo_server ringo_server_t;
+typedef struct {
+  int64_t budget_bytes;     /* device bytes for resident graphs and in-flight work  */
+  int32_t num_streams;      /* worker threads / streams, 1..16                       */
+  int32_t max_batch_tables; /* requests per batch, >= 1                              */
+  int64_t max_batch_rows;   /* rows per batch (a larger single request still runs)   */
+} ringo_server_config_t;
+typedef struct {
+  int64_t submitted, completed, failed, evicted, queued;
+  int64_t batches, max_concurrent_batches;
+  int64_t rows_completed;
+  int64_t resident_bytes, peak_reserved_bytes;
+} ringo_server_stats_t;
+
+/* Starts the workers on the current HIP device.  RINGO_ERR_INVALID_ARG on a
+ * bad configuration, RINGO_ERR_HIP if no device is current. */
+ringo_status_t ringo_server_create(const ringo_server_config_t *cfg, ringo_server_t **out);
+/* Queues a conversion of the HOST arrays src[num_rows], dst[num_rows]
+ * (pinned memory for full copy speed).  They must stay valid and unchanged
+ * until the request leaves RINGO_ERR_PENDING.  *req_id identifies it. */
+ringo_status_t ringo_server_submit(ringo_server_t *s, const int64_t *src, const int64_t *dst,
+                                   int64_t num_rows, int64_t *req_id);
+/* RINGO_OK with *out set to a view of the resident graph (the server keeps
+ * ownership: out->_alloc is NULL; the view is valid until the request is
+ * released or evicted), RINGO_ERR_PENDING, RINGO_ERR_EVICTED, or the
+ * conversion's error.  *latency_s (may be NULL) receives the time from
+ * submission to the graph being resident once the request has finished.
+ * Polling a resident graph marks it as recently used. */
+ringo_status_t ringo_server_poll(ringo_server_t *s, int64_t req_id, ringo_graph_t *out,
+                                 double *latency_s);
+/* Frees a finished request and its resident graph; RINGO_ERR_PENDING while
+ * it is still queued or running. */
+ringo_status_t ringo_server_release(ringo_server_t *s, int64_t req_id);
+ringo_status_t ringo_server_stats(ringo_server_t *s, ringo_server_stats_t *out);
+/* Finishes the queued requests, frees every resident graph, joins the
+ * workers.  NULL is a no-op. */
+void ringo_server_destroy(ringo_server_t *s);
+
 /* Version string of the library build. */
 const char *ringo_version(void);
 

@@ -23,6 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libringo.so")
 
 RINGO_OK = 0
+STATUS_EVICTED = 5
+STATUS_PENDING = 6
 STATUS_NAMES = {0: "RINGO_OK", 1: "RINGO_ERR_INVALID_ARG", 2: "RINGO_ERR_TOO_MANY_NODES",
                 3: "RINGO_ERR_OUT_OF_MEMORY", 4: "RINGO_ERR_HIP", 5: "RINGO_ERR_EVICTED",
                 6: "RINGO_ERR_PENDING"}
@@ -32,6 +34,8 @@ EXPORTED_SYMBOLS = (
     "ringo_table_to_graph", "ringo_table_to_graph_batched", "ringo_graph_free",
     "ringo_status_string", "ringo_set_allocator", "ringo_tune_get", "ringo_tune_set",
     "ringo_version", "ringo_trace_enable", "ringo_trace_read",
+    "ringo_server_create", "ringo_server_submit", "ringo_server_poll", "ringo_server_release",
+    "ringo_server_stats", "ringo_server_destroy",
 )
 
 
@@ -231,6 +235,18 @@ def _wrap(raw: RawGraph, device) -> Graph:
                  _view(raw.out_nbrs, E, torch.int32, owner, device),
                  _view(raw.in_offsets, V + 1, torch.int64, owner, device),
                  _view(raw.in_nbrs, E, torch.int32, owner, device))
+
+
+def view_graph(raw: RawGraph, device) -> Graph:
+    """Tensor views of a graph owned elsewhere (for example by the server);
+    valid only while the owner keeps it."""
+    V, E = raw.num_nodes, raw.num_edges
+    return Graph(raw.num_rows, V, E,
+                 _view(raw.node_ids, V, torch.int64, None, device),
+                 _view(raw.out_offsets, V + 1, torch.int64, None, device),
+                 _view(raw.out_nbrs, E, torch.int32, None, device),
+                 _view(raw.in_offsets, V + 1, torch.int64, None, device),
+                 _view(raw.in_nbrs, E, torch.int32, None, device))
 
 
 def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None) -> Graph:
