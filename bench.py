@@ -210,7 +210,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the conversion runs on a single MI355X; see DESIGN.md for how it would shard).",
+              f"(the conversion runs on a single MI355X).",
               file=sys.stderr)
         sys.exit(2)
 

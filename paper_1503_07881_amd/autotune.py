@@ -1,0 +1,109 @@
+"""Autotuner of the radix-pass schedule.
+
+For every table-size bucket (powers of two of rows), the conversion is timed
+on the device with each supported tile shape (items per thread of the
+scatter tile; digit width is 8 bits) and the fastest is kept.  Results are
+cached as JSON (RINGO_TUNE_CACHE, else the in-tree tuned_schedules.json
+measured on an MI355X) and applied to the library through ringo_tune_set.
+The schedule changes only the tiling: the output is the same bit for bit
+whichever schedule runs.
+
+    python -m paper_1503_07881_amd.autotune            # tune and save
+    from paper_1503_07881_amd import autotune; autotune.apply()   # load and apply
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import ringo, workloads
+
+ITEMS = (8, 12, 16)
+DIGIT_BITS = 8
+
+
+def cache_path() -> str:
+    return os.environ.get("RINGO_TUNE_CACHE",
+                          os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_schedules.json"))
+
+
+def _device_name() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).name if torch.cuda.is_available() else "none"
+
+
+def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> dict:
+    """Times every schedule for R-MAT tables of 2^k rows; returns
+    {"device": ..., "buckets": {str(rows): {"items": best, "ms": {...}}}}."""
+    import torch
+    dev = torch.device("cuda:0")
+    sh = torch.cuda.current_stream().cuda_stream
+    out = {"device": _device_name(), "digit_bits": DIGIT_BITS, "buckets": {}}
+    for k in log2_sizes:
+        n = 1 << k
+        spec = workloads.TableSpec("rmat", n, seed=99, table=k, scale=workloads.rmat_scale_for(n))
+        src = torch.empty(n, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
+        times = {}
+        for items in ITEMS:
+            ringo.tune_set(n, DIGIT_BITS, items)
+            ringo.tune_set(2 * n, DIGIT_BITS, items)
+            ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            times[items] = sorted(ts)[len(ts) // 2] * 1e3
+        best = min(times, key=times.get)
+        out["buckets"][str(n)] = {"items": best, "ms": {str(i): round(t, 4) for i, t in times.items()}}
+        if verbose:
+            print(f"rows 2^{k}: best items {best}  {times}", flush=True)
+        del src, dst
+    apply(out)
+    return out
+
+
+def save(cache: dict, path: str | None = None) -> str:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return path
+
+
+def load(path: str | None = None) -> dict | None:
+    path = path or cache_path()
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply(cache: dict | None = None) -> int:
+    """Sets the library's schedule for every cached bucket; buckets between
+    two tuned sizes take the schedule of the nearest tuned size below."""
+    cache = cache if cache is not None else load()
+    if not cache or cache.get("digit_bits", DIGIT_BITS) != DIGIT_BITS:
+        return 0
+    buckets = sorted((int(k), v["items"]) for k, v in cache.get("buckets", {}).items()
+                     if v.get("items") in ITEMS)
+    if not buckets:
+        return 0
+    applied = 0
+    for e in range(0, 63):
+        rows = 1 << e
+        below = [it for n, it in buckets if n <= rows]
+        items = below[-1] if below else buckets[0][1]
+        ringo.tune_set(rows, DIGIT_BITS, items)
+        applied += 1
+    return applied
+
+
+if __name__ == "__main__":
+    c = tune(verbose=True)
+    print("saved", save(c))

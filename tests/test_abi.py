@@ -93,3 +93,18 @@ def test_config4_sizes():
     total = sum(ns)
     assert 0.9e9 < total < 1.25e9
     assert all(s.kind == ("uniform" if i % 2 == 0 else "rmat") for i, s in enumerate(specs))
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    from paper_1503_07881_amd import autotune
+    cache = {"device": "test", "digit_bits": 8,
+             "buckets": {str(1 << 10): {"items": 8}, str(1 << 20): {"items": 12}, str(1 << 24): {"items": 16}}}
+    path = autotune.save(cache, str(tmp_path / "tune.json"))
+    assert autotune.load(path) == cache
+    assert autotune.apply(autotune.load(path)) == 63
+    assert ringo.tune_get(1 << 5)[1] == 8      # below the first tuned size: nearest
+    assert ringo.tune_get(1 << 15)[1] == 8
+    assert ringo.tune_get(1 << 21)[1] == 12
+    assert ringo.tune_get(1 << 30)[1] == 16
+    assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
+    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 16}}})  # restore the default
