@@ -214,6 +214,9 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
 // inside one table (fewer than 2^32 keys) are used.
 
 constexpr int UP_TILES = 32;  // tiles per upsweep block
+constexpr int NUM_XCD = 8;    // accelerator complex dies of the MI355X
+// s_waitcnt immediate: lgkmcnt(0), vmcnt and expcnt left at their maxima
+constexpr int LGKMCNT_0 = 0xC07F;
 
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
@@ -253,40 +256,69 @@ struct TileHeader {
   }
 };
 
+// Each wave counts whole tiles on its own, in a wave-private LDS histogram;
+// the block only meets once, to add up the four waves' sums over its run of
+// UP_TILES tiles.  LDS atomics of a wave are not ordered with its later LDS
+// reads and writes, so the wave waits for its LDS operations to complete
+// (lgkmcnt(0)) between clearing, counting and reading the histogram.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys) {
-  constexpr int W = 4;
+  constexpr int W = 4, U = 8;
   __shared__ uint32_t s_h[W * RADIX];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
   const int64_t t0 = (int64_t)blockIdx.x * UP_TILES;
   const int64_t t1 = std::min<int64_t>(t0 + UP_TILES, a.total_tiles);
   TileHeader H;
-  uint32_t run_sum = 0;
+  uint32_t run_sum[RADIX / 64] = {0, 0, 0, 0};
   uint32_t *h = s_h + wave * RADIX;
-  for (int64_t t = t0; t < t1; ++t) {
-    for (int i = tid; i < W * RADIX; i += 256) s_h[i] = 0;
+  for (int64_t t = t0 + wave; t < t1; t += W) {
+#pragma unroll
+    for (int j = 0; j < RADIX / 64; ++j) h[lane + 64 * j] = 0;
+    __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
+    __builtin_amdgcn_wave_barrier();
     H.at(a, t);
-    __syncthreads();
     const int64_t k0 = (t - H.first) * tile_keys;
     const int64_t k1 = std::min<int64_t>(k0 + tile_keys, H.count);
-    for (int64_t e0 = k0 + tid; e0 < k1; e0 += 4 * 256) {
-      uint64_t k[4];
+    for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
+      uint64_t k[U];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) k[j] = pass_key<MODE>(a, H.P, H.start, std::min<int64_t>(e0 + j * 256, k1 - 1));
+      for (int j = 0; j < U; ++j)
+        k[j] = pass_key<MODE>(a, H.P, H.start, std::min<int64_t>(e0 + j * 64, k1 - 1));
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (e0 + j * 256 < k1) atomicAdd(&h[(k[j] >> shift) & (RADIX - 1)], 1u);
+      for (int j = 0; j < U; ++j) {
+        // Lanes hold consecutive keys: a run of equal digits over
+        // neighbouring lanes (clustered identifiers after the first passes)
+        // is added once, by the lane that starts it.
+        const bool valid = e0 + j * 64 < k1;
+        const uint32_t d = (uint32_t)(k[j] >> shift) & (RADIX - 1);
+        const uint32_t dp = __shfl_up(d, 1, 64);
+        const uint64_t heads = __ballot(valid && (lane == 0 || d != dp));
+        const uint64_t vmask = __ballot(valid);
+        if ((heads >> lane) & 1ull) {
+          const uint64_t after = lane < 63 ? heads & ~((2ull << lane) - 1) : 0ull;  // heads above
+          const int end = after ? __builtin_ctzll(after) : 64 - __builtin_clzll(vmask);
+          atomicAdd(&h[d], (uint32_t)(end - lane));
+        }
+      }
     }
-    __syncthreads();
-    uint32_t v = 0;
+    __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int w = 0; w < W; ++w) v += s_h[w * RADIX + tid];
-    a.counts[t * RADIX + tid] = v;
-    run_sum += v;
-    __syncthreads();
+    for (int j = 0; j < RADIX / 64; ++j) {
+      const uint32_t v = h[lane + 64 * j];
+      a.counts[t * RADIX + lane + 64 * j] = v;
+      run_sum[j] += v;
+    }
   }
-  a.bsum[(int64_t)blockIdx.x * RADIX + tid] = run_sum;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RADIX / 64; ++j) h[lane + 64 * j] = run_sum[j];
+  __syncthreads();
+  uint32_t v = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) v += s_h[w * RADIX + tid];
+  a.bsum[(int64_t)blockIdx.x * RADIX + tid] = v;
 }
 
 // Exclusive scan of the run counts over all runs, one block per digit.
@@ -341,8 +373,12 @@ __global__ __launch_bounds__(RADIX) void k_seg_base(SortLaunch a) {
   a.digit_base[(int64_t)seg * RADIX + d] = range_start(a.plan[seg], a.range_kind) + (int64_t)ex;
 }
 
+// Waves per SIMD the downsweep is compiled for: the register budget that
+// still holds a tile of 8 or 12 keys per thread without spilling.
+constexpr int ds_waves(int items) { return items <= 8 ? 5 : items <= 12 ? 4 : 3; }
+
 template <int BLOCK, int ITEMS, int MODE>
-__global__ __launch_bounds__(BLOCK) void k_downsweep(SortLaunch a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(ITEMS), 8))) void k_downsweep(SortLaunch a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
   static_assert(BLOCK >= RADIX, "one thread per digit");
@@ -360,7 +396,15 @@ __global__ __launch_bounds__(BLOCK) void k_downsweep(SortLaunch a) {
   for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
   __syncthreads();
 
-  for (int64_t tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
+  // Tiles in contiguous ranges per XCD (blocks go to the XCDs round-robin,
+  // and the grid is a multiple of their count): tiles that run together on
+  // one XCD are neighbours, so the partial cache lines shared by their digit
+  // runs meet in the same L2.  Any mapping is correct; this one is faster.
+  const int xcd = blockIdx.x % NUM_XCD;
+  const int64_t per = gridDim.x / NUM_XCD;
+  const int64_t t_hi = a.total_tiles * (xcd + 1) / NUM_XCD;
+  for (int64_t tile = a.total_tiles * xcd / NUM_XCD + blockIdx.x / NUM_XCD; tile < t_hi;
+       tile += per) {
     if (tile >= H.end) {
       H.at(a, tile);
       if (tid < RADIX) {
@@ -380,12 +424,16 @@ __global__ __launch_bounds__(BLOCK) void k_downsweep(SortLaunch a) {
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
-      const bool valid = idx < cnt;
-      const int64_t e = base + (valid ? idx : 0);
-      const uint64_t k = pass_key<MODE>(a, H.P, H.start, e);
-      if (MODE == SORT_IN_FIRST && valid)  // out-neighbours, already in (s, d) order
-        G(H.P.out_nbr)[e] = (int32_t)(uint32_t)(k >> 32);
-      keys[i] = k;
+      keys[i] = pass_key<MODE>(a, H.P, H.start, base + (idx < cnt ? idx : 0));
+    }
+    if (MODE == SORT_IN_FIRST) {
+      // out-neighbours, already in (s, d) order; stored after all loads are
+      // issued so that no load waits for another
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+        if (idx < cnt) G(H.P.out_nbr)[base + idx] = (int32_t)(uint32_t)(keys[i] >> 32);
+      }
     }
     const uint32_t tprefix = tid < RADIX ? a.counts[tile * RADIX + tid] : 0u;
 
@@ -488,7 +536,8 @@ static hipError_t launch_pass_t(const SortLaunch &a, hipStream_t s) {
   hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
   hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a);
   hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
-  const int64_t g = std::min<int64_t>(a.total_tiles, resident_t<ITEMS>());
+  const int64_t g = std::max<int64_t>(
+      NUM_XCD, std::min<int64_t>(a.total_tiles, resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);
   hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -610,9 +659,11 @@ hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out,
 // ------------------------------------------------------- node directory
 //
 // Bucket index over the sorted node keys of a table: bucket q holds the
-// keys whose (key - lo) >> shift equals q, and dir[q] is the position of its
-// first key, with 2^dirk buckets (about one key per bucket for spread-out
-// identifiers).  The same pass writes the node identifiers of the output.
+// keys whose (key - lo) >> shift equals q, with 2^dirk buckets (about one
+// key per bucket for spread-out identifiers).  Entry q holds the bucket's
+// first key and its position range [start, next), so a lookup whose key is
+// the first of its bucket costs one 16-byte read.  The same pass writes the
+// node identifiers of the output.
 
 __device__ __forceinline__ int dir_shift(uint64_t lo, uint64_t hi, int dirk) {
   const uint64_t range = hi - lo;
@@ -620,14 +671,14 @@ __device__ __forceinline__ int dir_shift(uint64_t lo, uint64_t hi, int dirk) {
   return bits > dirk ? bits - dirk : 0;
 }
 
-__global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes, uint32_t *dir) {
+__global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes, DirEntry *dir) {
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
     const uint64_t *nd = nodes + 2 * P.row_off;
     const uint64_t lo = nd[0], hi = nd[P.V - 1];
     const int shift = dir_shift(lo, hi, P.dirk);
-    uint32_t *D = dir + P.dir_off;
+    __attribute__((address_space(1))) DirEntry *D = G(dir + P.dir_off);
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)DIR_TILE;
     const int64_t end = std::min<int64_t>(base + DIR_TILE, P.V);
     for (int64_t j = base + threadIdx.x; j < end; j += 256) {
@@ -635,16 +686,32 @@ __global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes
       G(P.node_ids)[j] = (int64_t)(u ^ SIGN_FLIP);
       const int64_t q = (int64_t)((u - lo) >> shift);
       const int64_t qp = j == 0 ? -1 : (int64_t)((nd[j - 1] - lo) >> shift);
-      for (int64_t x = qp + 1; x <= q; ++x) D[x] = (uint32_t)j;
-      if (j == P.V - 1) {
-        const int64_t nb = (int64_t)1 << P.dirk;
-        for (int64_t x = q + 1; x <= nb; ++x) D[x] = (uint32_t)P.V;
+      const int64_t qn = j == P.V - 1 ? ((int64_t)1 << P.dirk) + 1 : (int64_t)((nd[j + 1] - lo) >> shift);
+      if (q != qp) {  // first key of bucket q; the buckets skipped before it are empty
+        for (int64_t x = qp + 1; x < q; ++x) {
+          D[x].key = 0;
+          D[x].start = (uint32_t)j;
+          D[x].next = (uint32_t)j;
+        }
+        D[q].key = u;
+        D[q].start = (uint32_t)j;
+      }
+      if (q != qn) {  // last key of bucket q
+        D[q].next = (uint32_t)(j + 1);
+        if (j == P.V - 1) {
+          const int64_t nb = (int64_t)1 << P.dirk;
+          for (int64_t x = q + 1; x <= nb; ++x) {
+            D[x].key = 0;
+            D[x].start = (uint32_t)P.V;
+            D[x].next = (uint32_t)P.V;
+          }
+        }
       }
     }
   }
 }
 
-hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, uint32_t *dir, int grid,
+hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, DirEntry *dir, int grid,
                       hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_dir, dim3(grid), dim3(256), 0, s, t, nodes, dir);
@@ -655,22 +722,51 @@ hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, uint32_t *dir,
 //
 // Dense position of every row's source and destination (merge-rank against
 // the sorted node list through the bucket directory), packed into the edge
-// key (s << b) | d; the digit histograms of the edge sort ride along.
+// key (s << b) | d.  Keys that open their bucket are found by the directory
+// read alone; the others by a binary search inside the bucket.  All keys of
+// a thread advance together so that their loads overlap.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint32_t node_rank(const uint64_t *nd, const uint32_t *D, uint64_t lo,
-                                              int shift, uint64_t nbuckets, uint64_t u) {
-  uint64_t q = (u - lo) >> shift;
-  if (q >= nbuckets) q = nbuckets - 1;  // only for keys outside the table's range
-  uint32_t a = D[q], e = D[q + 1];
-  while (e - a > 1) {
-    const uint32_t m = (a + e) >> 1;
-    if (nd[m] <= u) a = m; else e = m;
+template <int K>
+__device__ __forceinline__ void node_rank_n(const uint64_t *nd, const DirEntry *D, uint64_t lo,
+                                            int shift, uint64_t nbuckets, const uint64_t *u,
+                                            uint32_t *rank) {
+  uint32_t a[K], e[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    uint64_t q = (u[j] - lo) >> shift;
+    if (q >= nbuckets) q = nbuckets - 1;  // only for keys outside the table's range
+    // one 16-byte load: {key, start | next << 32}
+    const u64x2 de = G((const u64x2 *)(D + q))[0];
+    const uint32_t start = (uint32_t)de.y, next = (uint32_t)(de.y >> 32);
+    a[j] = start;
+    e[j] = de.x == u[j] ? start + 1 : next;
   }
-  return a;
+  bool more = true;
+  while (more) {
+    more = false;
+    uint32_t m[K];
+    uint64_t x[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      m[j] = (a[j] + e[j]) >> 1;
+      // unconditional load (finished searches read node 0, always present)
+      x[j] = G(nd)[e[j] - a[j] > 1 ? m[j] : 0u];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (e[j] - a[j] > 1) {
+        if (x[j] <= u[j]) a[j] = m[j]; else e[j] = m[j];
+        more |= e[j] - a[j] > 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) rank[j] = a[j];
 }
 
 __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nodes,
-                                               const uint32_t *dir, uint64_t *ekeys) {
+                                               const DirEntry *dir, uint64_t *ekeys) {
   const int tid = threadIdx.x;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
@@ -678,20 +774,31 @@ __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nod
     const uint64_t *nd = nodes + 2 * P.row_off;
     const uint64_t lo = nd[0], hi = nd[P.V - 1];
     const int shift = dir_shift(lo, hi, P.dirk);
-    const uint32_t *D = dir + P.dir_off;
+    const DirEntry *D = dir + P.dir_off;
     const uint64_t nb = 1ull << P.dirk;
     const int b = P.b;
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
-    for (int64_t r = base + tid; r < end; r += 256) {
-      const uint64_t s = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.src)[r] ^ SIGN_FLIP);
-      const uint64_t d = node_rank(nd, D, lo, shift, nb, (uint64_t)G(P.dst)[r] ^ SIGN_FLIP);
-      G(ekeys)[P.row_off + r] = (s << b) | d;
+    constexpr int U = 4;  // rows per thread in flight
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t u[2 * U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
+        u[j] = (uint64_t)G(P.src)[r] ^ SIGN_FLIP;
+        u[U + j] = (uint64_t)G(P.dst)[r] ^ SIGN_FLIP;
+      }
+      uint32_t rk[2 * U];
+      node_rank_n<2 * U>(nd, D, lo, shift, nb, u, rk);
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end)
+          G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rk[j] << b) | rk[U + j];
     }
   }
 }
 
-hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const uint32_t *dir,
+hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEntry *dir,
                         uint64_t *ekeys, int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys);

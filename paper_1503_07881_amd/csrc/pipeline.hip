@@ -173,7 +173,7 @@ struct Call {
   uint32_t *counters = nullptr;
   int64_t *results = nullptr;
   uint8_t *meta = nullptr;
-  uint32_t *dir = nullptr;
+  DirEntry *dir = nullptr;
   uint32_t *counts = nullptr;
   uint32_t *bsum = nullptr;
   size_t meta_bytes = 0;
@@ -454,7 +454,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.owner->stream = st;
   c.owner->hooks = c.hooks;
   c.owner->blocks[0] = dev_alloc(c.hooks, arena1, st);
-  c.dir = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * dir_words, st);
+  c.dir = (DirEntry *)dev_alloc(c.hooks, sizeof(DirEntry) * dir_words, st);
   if (!c.owner->blocks[0] || !c.dir) return RINGO_ERR_OUT_OF_MEMORY;
   char *a1 = (char *)c.owner->blocks[0];
   for (int i = 0; i < S; ++i) {
@@ -473,7 +473,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
 
   // ------------------------------------------------------------- phase E
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
-  TRACED(TK_DIR, sumV, 16.0 * sumV + 4.0 * dir_words,
+  TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
          launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
                     grid_for(c.total(TM_DIR), cus * 8), st));
   // the sorted node keys are consumed: their buffer takes the edge keys

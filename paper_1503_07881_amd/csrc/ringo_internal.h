@@ -100,9 +100,16 @@ int64_t sort_runs(int64_t tiles);
 hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
                          uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
                          hipStream_t s);
-hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, uint32_t *dir, int grid,
+// Node directory entry: the bucket's first key and its position range.
+struct alignas(16) DirEntry {
+  uint64_t key;
+  uint32_t start;
+  uint32_t next;
+};
+
+hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, DirEntry *dir, int grid,
                       hipStream_t s);
-hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const uint32_t *dir,
+hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEntry *dir,
                         uint64_t *ekeys, int grid, hipStream_t s);
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
