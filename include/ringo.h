@@ -126,15 +126,30 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
                                    void *ctx);
 
 /*
- * Tuning schedule of the radix passes: digit width (bits per pass) and
- * items per thread of the scatter tile.  ringo_tune_get returns the schedule
- * the library will use for a table of num_rows rows; ringo_tune_set
- * overrides it for the size bucket holding num_rows (used by the autotuner).
+ * Tuning schedule: digit width (bits per radix pass), items per thread of
+ * the scatter tile, and the node-numbering method.  ringo_tune_get returns
+ * the schedule the library will use for a table of num_rows rows (for a
+ * batch: of the batch's total rows); ringo_tune_set overrides it for the
+ * size bucket holding num_rows (powers of two; used by the autotuner).
  * Valid digit widths: 8; valid items per thread: 8, 12, 16.
+ *
+ * Node numbering (both give the same graph, bit for bit):
+ *   RINGO_NODES_SORT  radix sort of all 2n identifiers, then unique.
+ *   RINGO_NODES_HASH  the paper's node hash table (open addressing, linear
+ *                     probing; Section 2.5): insert the 2n identifiers, sort
+ *                     only the V distinct ones.  One more stream
+ *                     synchronisation per call (a distinct-count estimate
+ *                     sizes the table).  Should a probe sequence exceed its
+ *                     bound (an estimate far too low), the call falls back to
+ *                     RINGO_NODES_SORT by itself.
+ * Built-in default: RINGO_NODES_HASH from 2^20 rows, RINGO_NODES_SORT below.
  */
+#define RINGO_NODES_SORT 0
+#define RINGO_NODES_HASH 1
 typedef struct {
   int32_t digit_bits;
   int32_t items_per_thread;
+  int32_t node_method;
 } ringo_schedule_t;
 ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out);
 ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched);

@@ -2,7 +2,8 @@
 
 For every table-size bucket (powers of two of rows), the conversion is timed
 on the device with each supported tile shape (items per thread of the
-scatter tile; digit width is 8 bits) and the fastest is kept.  Results are
+scatter tile; digit width is 8 bits) and each node-numbering method (radix
+sort of all identifiers, or the node hash table), and the fastest is kept.  Results are
 cached as JSON (RINGO_TUNE_CACHE, else the in-tree tuned_schedules.json
 measured on an MI355X) and applied to the library through ringo_tune_set.
 The schedule changes only the tiling: the output is the same bit for bit
@@ -20,6 +21,7 @@ import time
 from . import ringo, workloads
 
 ITEMS = (8, 12, 16)
+METHODS = (ringo.NODES_SORT, ringo.NODES_HASH)
 DIGIT_BITS = 8
 
 
@@ -35,7 +37,7 @@ def _device_name() -> str:
 
 def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> dict:
     """Times every schedule for R-MAT tables of 2^k rows; returns
-    {"device": ..., "buckets": {str(rows): {"items": best, "ms": {...}}}}."""
+    {"device": ..., "buckets": {str(rows): {"items": i, "node_method": m, "ms": {...}}}}."""
     import torch
     dev = torch.device("cuda:0")
     sh = torch.cuda.current_stream().cuda_stream
@@ -47,22 +49,25 @@ def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> d
         dst = torch.empty_like(src)
         workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
         times = {}
-        for items in ITEMS:
-            ringo.tune_set(n, DIGIT_BITS, items)
-            ringo.tune_set(2 * n, DIGIT_BITS, items)
-            ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                t0 = time.perf_counter()
+        for method in METHODS:
+            for items in ITEMS:
+                ringo.tune_set(n, DIGIT_BITS, items, method)
                 ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
                 torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            times[items] = sorted(ts)[len(ts) // 2] * 1e3
-        best = min(times, key=times.get)
-        out["buckets"][str(n)] = {"items": best, "ms": {str(i): round(t, 4) for i, t in times.items()}}
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                times[(method, items)] = sorted(ts)[len(ts) // 2] * 1e3
+        method, items = min(times, key=times.get)
+        out["buckets"][str(n)] = {"items": items, "node_method": method,
+                                  "ms": {f"{'hash' if m else 'sort'}/{i}": round(v, 4)
+                                         for (m, i), v in times.items()}}
         if verbose:
-            print(f"rows 2^{k}: best items {best}  {times}", flush=True)
+            print(f"rows 2^{k}: best {'hash' if method else 'sort'}/{items}  "
+                  f"{out['buckets'][str(n)]['ms']}", flush=True)
         del src, dst
     apply(out)
     return out
@@ -85,21 +90,24 @@ def load(path: str | None = None) -> dict | None:
 
 
 def apply(cache: dict | None = None) -> int:
-    """Sets the library's schedule for every cached bucket; buckets between
-    two tuned sizes take the schedule of the nearest tuned size below."""
+    """Sets the library's schedule for every size bucket from the cache;
+    buckets between two tuned sizes take the schedule of the nearest tuned
+    size below (the smallest tuned size for buckets below it).  A cached
+    bucket without a node method keeps the library's."""
     cache = cache if cache is not None else load()
     if not cache or cache.get("digit_bits", DIGIT_BITS) != DIGIT_BITS:
         return 0
-    buckets = sorted((int(k), v["items"]) for k, v in cache.get("buckets", {}).items()
-                     if v.get("items") in ITEMS)
+    buckets = sorted((int(k), v["items"], v.get("node_method"))
+                     for k, v in cache.get("buckets", {}).items()
+                     if v.get("items") in ITEMS and v.get("node_method", 0) in METHODS)
     if not buckets:
         return 0
     applied = 0
     for e in range(0, 63):
         rows = 1 << e
-        below = [it for n, it in buckets if n <= rows]
-        items = below[-1] if below else buckets[0][1]
-        ringo.tune_set(rows, DIGIT_BITS, items)
+        below = [(it, m) for n, it, m in buckets if n <= rows]
+        items, method = below[-1] if below else buckets[0][1:]
+        ringo.tune_set(rows, DIGIT_BITS, items, method)
         applied += 1
     return applied
 

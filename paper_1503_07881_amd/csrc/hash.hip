@@ -1,0 +1,375 @@
+// Node numbering through a node hash table.
+//
+// The paper keeps a graph's nodes in an open-addressing hash table with
+// linear probing (Ringo Implementation, "Concurrent hash tables and vectors",
+// Section 2.5) and inserts both identifiers of every row into it (the
+// Twitter2010 walk-through of Section 3).  Here that table replaces the
+// 2n-key radix sort of the node keys: only the V distinct keys are sorted,
+// which is what fixes the dense positions, so the output is identical to
+// the sort-based numbering.
+//
+//   estimate   HyperLogLog count of the distinct keys of each table
+//              (Flajolet, Fusy, Gandouet & Meunier 2007), 2^10 registers;
+//              the host sizes each table's slots from it (load <= 1/2)
+//   insert     every row's two keys, lock-free compare-and-swap into the
+//              first free slot of the probe sequence; the slot of every
+//              key is written out (32-bit, src then dst per table)
+//   compact    occupied slots -> the table's distinct keys (unordered)
+//   (sort)     the V keys, with the radix passes of kernels.hip
+//   rank       position of every sorted key, stored beside its slot; node ids
+//   remap      every row's (src, dst) slots -> positions (a gather from the
+//              rank array), packed (s << b) | d
+//
+// The slots hold keys only (8 bytes) and the ranks live in their own 4-byte
+// array, so the probe phase walks a table half the size, and the remap reads
+// only the rank array, a quarter of it.
+//
+// Keys are uint64(id) ^ 2^63 as in the sort-based path.  The key ~0 marks a
+// free slot; a table holding that key sets a flag instead (its elements get
+// the slot index NO_SLOT), and since ~0 is the largest key its position is
+// always V - 1.  A probe sequence longer than min(capacity, MAX_PROBES) sets
+// an overflow flag and stops; the host then converts that call with the
+// sort-based numbering instead.
+
+#include "device_common.h"
+#include "ringo_internal.h"
+
+namespace ringo {
+
+constexpr uint32_t MAX_PROBES = 4096;
+constexpr uint32_t NO_SLOT = 0xffffffffu;
+
+// MurmurHash3's 64-bit finaliser (Appleby): a bijection with full avalanche.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// ------------------------------------------------------------- estimate
+
+__device__ __forceinline__ void hll_add(uint32_t *R, uint64_t key) {
+  const uint64_t h = fmix64(key);
+  const uint32_t idx = (uint32_t)(h >> (64 - HLL_BITS));
+  const uint64_t w = h << HLL_BITS;
+  const uint32_t rho = w == 0 ? 64 - HLL_BITS + 1 : (uint32_t)__clzll((long long)w) + 1;
+  if (R[idx] < rho) atomicMax(&R[idx], rho);  // the read only skips redundant atomics
+}
+
+__global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs) {
+  __shared__ uint32_t R[HLL_M];
+  const int tid = threadIdx.x;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    for (int i = tid; i < HLL_M; i += 256) R[i] = 0;
+    __syncthreads();
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)HLL_TILE;
+    const int64_t end = std::min<int64_t>(base + HLL_TILE, P.n);
+    constexpr int U = 4;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t s[U], d[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
+        s[j] = (uint64_t)G(P.src)[r] ^ SIGN_FLIP;
+        d[j] = (uint64_t)G(P.dst)[r] ^ SIGN_FLIP;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end) {
+          hll_add(R, s[j]);
+          hll_add(R, d[j]);
+        }
+    }
+    __syncthreads();
+    uint32_t *g = regs + (int64_t)seg * HLL_M;
+    for (int i = tid; i < HLL_M; i += 256) {
+      const uint32_t v = R[i];
+      if (v > G(g)[i]) atomicMax(&g[i], v);
+    }
+    __syncthreads();
+  }
+}
+
+// One block per table: the bias-corrected harmonic-mean estimate, with
+// linear counting while it is below 2.5 m and registers are still zero.
+__global__ __launch_bounds__(256) void k_hll_estimate(const SegPlan *plan, int S,
+                                                      const uint32_t *regs, int64_t *est) {
+  __shared__ double s_sum[4];
+  __shared__ int s_zero[4];
+  const int seg = blockIdx.x;
+  if (seg >= S) return;
+  const uint32_t *g = regs + (int64_t)seg * HLL_M;
+  double sum = 0;
+  int zeros = 0;
+  for (int i = threadIdx.x; i < HLL_M; i += 256) {
+    const uint32_t v = g[i];
+    sum += ldexp(1.0, -(int)v);
+    zeros += v == 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_down(sum, o, 64);
+    zeros += __shfl_down(zeros, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_sum[w] = sum;
+    s_zero[w] = zeros;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sum = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+    zeros = s_zero[0] + s_zero[1] + s_zero[2] + s_zero[3];
+    const double m = HLL_M;
+    const double alpha = 0.7213 / (1.0 + 1.079 / m);
+    double e = alpha * m * m / sum;
+    if (e <= 2.5 * m && zeros > 0) e = m * log(m / zeros);
+    est[seg] = plan[seg].n == 0 ? 0 : (int64_t)ceil(e);
+  }
+}
+
+hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, int grid,
+                      hipStream_t s) {
+  if (rows.total_tiles > 0) hipLaunchKernelGGL(k_hll, dim3(grid), dim3(256), 0, s, rows, regs);
+  hipLaunchKernelGGL(k_hll_estimate, dim3(rows.num_segs), dim3(256), 0, s, rows.plan,
+                     rows.num_segs, regs, est);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- insert
+//
+// Each thread carries the keys of U rows through their probe sequences at
+// once so that their loads overlap.  A slot goes from free to its key exactly
+// once, so a plain load that still sees it free is corrected by the
+// compare-and-swap, and a plain load that sees a key sees the final value.
+
+__global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hkeys,
+                                                     uint32_t *slots, uint32_t *flags) {
+  const int tid = threadIdx.x;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    uint64_t *T = hkeys + P.tab_off;
+    uint32_t *sl = slots + 2 * P.row_off;
+    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t max_probes = (uint32_t)std::min<int64_t>(P.tab_cap, MAX_PROBES);
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    uint32_t flag = 0;
+    constexpr int U = 4;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t u[2 * U], pos[2 * U];
+      uint32_t left[2 * U];
+      bool act[2 * U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
+        u[j] = (uint64_t)G(P.src)[r] ^ SIGN_FLIP;
+        u[U + j] = (uint64_t)G(P.dst)[r] ^ SIGN_FLIP;
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * U; ++j) {
+        const bool valid = r0 + (j % U) * 256 < end;
+        if (valid && u[j] == EMPTY_KEY) flag |= HFLAG_MAX_KEY;
+        act[j] = valid && u[j] != EMPTY_KEY;
+        pos[j] = fmix64(u[j]) & mask;
+        left[j] = max_probes;
+      }
+      // First probe of every key unconditionally (all loads in flight at
+      // once); later probes only for the keys still walking, so that lanes
+      // that are done add no memory traffic.
+      bool more = true;
+      bool first = true;
+      while (more) {
+        uint64_t k[2 * U];
+        if (first) {
+#pragma unroll
+          for (int j = 0; j < 2 * U; ++j) k[j] = G(T)[pos[j]];
+          first = false;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 2 * U; ++j) k[j] = act[j] ? G(T)[pos[j]] : 0ull;
+        }
+        more = false;
+#pragma unroll
+        for (int j = 0; j < 2 * U; ++j) {
+          if (!act[j]) continue;
+          uint64_t seen = k[j];
+          if (seen == EMPTY_KEY) seen = atomicCAS((unsigned long long *)&T[pos[j]],
+                                                  (unsigned long long)EMPTY_KEY,
+                                                  (unsigned long long)u[j]);
+          if (seen == EMPTY_KEY || seen == u[j]) {
+            act[j] = false;
+          } else if (--left[j] == 0) {
+            flag |= HFLAG_OVERFLOW;
+            act[j] = false;
+          } else {
+            pos[j] = (pos[j] + 1) & mask;
+            more = true;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end) {
+          G(sl)[r0 + j * 256] = u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j];
+          G(sl)[P.n + r0 + j * 256] = u[U + j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[U + j];
+        }
+    }
+    if (flag) atomicOr(&flags[seg], flag);
+  }
+}
+
+hipError_t launch_hash_insert(const TileLaunch &rows, uint64_t *hkeys, uint32_t *slots,
+                              uint32_t *flags, int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_insert, dim3(grid), dim3(256), 0, s, rows, hkeys, slots, flags);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- compact
+
+constexpr int CMP_ITEMS = 16;
+constexpr int CMP_TILE = 256 * CMP_ITEMS;
+
+__global__ __launch_bounds__(256) void k_hash_compact(TileLaunch t, const uint64_t *hkeys,
+                                                      uint64_t *nodes, uint64_t *count) {
+  __shared__ uint32_t s_w[4];
+  __shared__ uint64_t s_base;
+  const int tid = threadIdx.x;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint64_t *T = hkeys + P.tab_off;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)CMP_TILE;
+    const int64_t cnt = std::min<int64_t>(CMP_TILE, P.tab_cap - base);
+    uint64_t k[CMP_ITEMS];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < CMP_ITEMS; ++i) {
+      const int idx = i * 256 + tid;
+      k[i] = G(T)[base + (idx < cnt ? idx : 0)];
+      if (idx >= cnt) k[i] = EMPTY_KEY;
+      mine += k[i] != EMPTY_KEY;
+    }
+    uint32_t total;
+    const uint32_t off = block_excl_scan<256>(mine, s_w, total);
+    if (tid == 0) s_base = total ? atomicAdd((unsigned long long *)&count[seg],
+                                             (unsigned long long)total) : 0;
+    __syncthreads();
+    uint64_t *out = nodes + 2 * P.row_off + s_base + off;
+    uint32_t o = 0;
+#pragma unroll
+    for (int i = 0; i < CMP_ITEMS; ++i)
+      if (k[i] != EMPTY_KEY) G(out)[o++] = k[i];
+    __syncthreads();
+  }
+}
+
+// One thread per table: the key ~0 goes after the others, and the count (or
+// -1 after an overflow) becomes the table's V.
+__global__ void k_hash_finish(const SegPlan *plan, int S, uint64_t *nodes, const uint64_t *count,
+                              const uint32_t *flags, int64_t *seg_V) {
+  const int seg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= S) return;
+  const uint32_t f = flags[seg];
+  int64_t v = (int64_t)count[seg];
+  if (f & HFLAG_OVERFLOW) {
+    v = -1;
+  } else if (f & HFLAG_MAX_KEY) {
+    nodes[2 * plan[seg].row_off + v] = EMPTY_KEY;
+    ++v;
+  }
+  seg_V[seg] = v;
+}
+
+hipError_t launch_hash_compact(const TileLaunch &slots, const uint64_t *hkeys, uint64_t *nodes,
+                               uint64_t *count, const uint32_t *flags, int64_t *seg_V, int grid,
+                               hipStream_t s) {
+  if (slots.total_tiles > 0)
+    hipLaunchKernelGGL(k_hash_compact, dim3(grid), dim3(256), 0, s, slots, hkeys, nodes, count);
+  const int S = slots.num_segs;
+  hipLaunchKernelGGL(k_hash_finish, dim3((S + 255) / 256), dim3(256), 0, s, slots.plan, S, nodes,
+                     count, flags, seg_V);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- rank
+
+__global__ __launch_bounds__(256) void k_hash_rank(TileLaunch t, const uint64_t *sorted,
+                                                   const uint64_t *hkeys, uint32_t *hrank) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint64_t *nd = sorted + 2 * P.row_off;
+    const uint64_t *T = hkeys + P.tab_off;
+    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)DIR_TILE;
+    const int64_t end = std::min<int64_t>(base + DIR_TILE, P.V);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
+      const uint64_t u = G(nd)[j];
+      G(P.node_ids)[j] = (int64_t)(u ^ SIGN_FLIP);
+      if (u == EMPTY_KEY) continue;
+      uint64_t pos = fmix64(u) & mask;
+      // the key is in the table (no overflow): the walk ends within tab_cap slots
+      for (int64_t left = P.tab_cap; left > 0 && G(T)[pos] != u; --left) pos = (pos + 1) & mask;
+      G(hrank)[P.tab_off + pos] = (uint32_t)j;
+    }
+  }
+}
+
+hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
+                            const uint64_t *hkeys, uint32_t *hrank, int grid, hipStream_t s) {
+  if (nodes_t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_rank, dim3(grid), dim3(256), 0, s, nodes_t, sorted, hkeys, hrank);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- remap
+
+__global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t *slots,
+                                                    const uint32_t *hrank, uint64_t *ekeys) {
+  const int tid = threadIdx.x;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint32_t *sl = slots + 2 * P.row_off;
+    const uint32_t *R = hrank + P.tab_off;
+    const uint32_t last = (uint32_t)(P.V - 1);
+    const int b = P.b;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    constexpr int U = 8;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint32_t q[2 * U], rk[2 * U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
+        q[j] = G(sl)[r];
+        q[U + j] = G(sl)[P.n + r];
+      }
+#pragma unroll
+      for (int j = 0; j < 2 * U; ++j) rk[j] = G(R)[q[j] == NO_SLOT ? 0u : q[j]];
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end) {
+          const uint32_t rs = q[j] == NO_SLOT ? last : rk[j];
+          const uint32_t rd = q[U + j] == NO_SLOT ? last : rk[U + j];
+          G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+        }
+    }
+  }
+}
+
+hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
+                             uint64_t *ekeys, int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_remap, dim3(grid), dim3(256), 0, s, rows, slots, hrank, ekeys);
+  return hipGetLastError();
+}
+
+}  // namespace ringo

@@ -1,12 +1,13 @@
 // gfx950 kernels of the table-to-graph conversion.
 //
-// The method is the paper's "sort-first" conversion (Section 2.4): copy the
-// source and destination columns, sort the copies, count neighbours per node
-// and place the sorted neighbour lists.  On the GPU every step is a tiled,
-// HBM-streaming pass over all tables of a batch at once:
+// The method is the paper's "sort-first" conversion (Converting Between
+// Tables and Graphs, Section 2.4): copy the source and destination columns,
+// sort the copies, count neighbours per node and place the sorted neighbour
+// lists.  On the GPU every step is a tiled, HBM-streaming pass over all
+// tables of a batch at once:
 //
 //   node keys   2n (id ^ 2^63) keys per table, least-significant-digit radix
-//               sort, 8-bit digits (one histogram pass + 8 scatter passes)
+//               sort, 8-bit digits, 8 passes
 //   unique      head flags on the sorted keys + stream compaction -> nodes
 //   directory   bucket index over the sorted nodes for the remap lookups
 //   remap       every row's (src, dst) -> dense positions, packed into
@@ -16,69 +17,19 @@
 //   in keys     repack to (d << 32) | s, stable radix sort on d only
 //   in-CSR      in-neighbours + in-offsets
 //
-// Each scatter pass follows the one-sweep scheme (Adinets & Merrill 2022):
-// one read and one write of the keys per pass, a tile-local stable rank
-// from 64-lane wavefront ballots, per-digit decoupled look-back (Merrill &
-// Garland 2016) across tiles for the global digit offsets, and an LDS-staged
-// write-out so that each digit run leaves the tile as one contiguous store.
+// (hash.hip holds the alternative node numbering through a node hash table.)
+//
+// Each radix pass is a tile-granular reduce-then-scan: an upsweep counts the
+// digits of every tile, a scan over tiles turns the counts into per-tile
+// digit offsets, and a downsweep ranks every key stably inside its tile with
+// 64-lane wavefront ballots and writes each digit run of the tile as one
+// contiguous LDS-staged store.  Stream compaction (unique, dedupe) uses a
+// single pass with decoupled look-back (Merrill & Garland 2016).
 
+#include "device_common.h"
 #include "ringo_internal.h"
 
 namespace ringo {
-
-// --------------------------------------------------------------- helpers
-
-// Pointers read from the plan are generic to the compiler; G() marks them as
-// global-memory pointers so that accesses compile to global (not flat)
-// instructions, which keep LDS waits independent of outstanding loads.
-template <class T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *G(T *p) {
-  return (__attribute__((address_space(1))) T *)p;
-}
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Index s of the table whose tiles hold tile t: tmap[s] <= t < tmap[s+1].
-__device__ __forceinline__ int find_seg(const int64_t *tmap, int S, int64_t t) {
-  int lo = 0, hi = S;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (tmap[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-// Exclusive scan of one value per thread over the block; `total` receives
-// the block sum.  Every thread of the block must call it.
-template <int BLOCK>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t &total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t inc = wave_incl_scan(v, lane);
-  if (lane == 63) s_w[w] = inc;
-  __syncthreads();
-  uint32_t off = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < BLOCK / 64; ++i) {
-    const uint32_t x = s_w[i];
-    off += (i < w) ? x : 0u;
-    tot += x;
-  }
-  total = tot;
-  __syncthreads();
-  return off + inc - v;
-}
 
 // ----------------------------------------------------- decoupled look-back
 //
@@ -200,8 +151,8 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
 //
 // One stable counting-sort pass on RADIX_BITS digits, reduce-then-scan at
 // tile granularity, with every kernel walking the tiles in global order:
-//   upsweep      digit counts of every tile (and of every run of UP_TILES
-//                consecutive tiles)
+//   upsweep      digit counts of every tile (and of every run of
+//                run_tiles consecutive tiles)
 //   block scan   exclusive prefix of the run counts, per digit
 //   tile prefix  exclusive prefix of the tile counts, per digit: the
 //                position of a tile's first key of each digit, relative to
@@ -213,7 +164,6 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
 // digit's output range.  Prefixes are 32-bit and wrap: only differences
 // inside one table (fewer than 2^32 keys) are used.
 
-constexpr int UP_TILES = 32;  // tiles per upsweep block
 constexpr int NUM_XCD = 8;    // accelerator complex dies of the MI355X
 // s_waitcnt immediate: lgkmcnt(0), vmcnt and expcnt left at their maxima
 constexpr int LGKMCNT_0 = 0xC07F;
@@ -258,17 +208,17 @@ struct TileHeader {
 
 // Each wave counts whole tiles on its own, in a wave-private LDS histogram;
 // the block only meets once, to add up the four waves' sums over its run of
-// UP_TILES tiles.  LDS atomics of a wave are not ordered with its later LDS
+// run_tiles tiles.  LDS atomics of a wave are not ordered with its later LDS
 // reads and writes, so the wave waits for its LDS operations to complete
 // (lgkmcnt(0)) between clearing, counting and reading the histogram.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys) {
+__global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, int run_tiles) {
   constexpr int W = 4, U = 8;
   __shared__ uint32_t s_h[W * RADIX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
-  const int64_t t0 = (int64_t)blockIdx.x * UP_TILES;
-  const int64_t t1 = std::min<int64_t>(t0 + UP_TILES, a.total_tiles);
+  const int64_t t0 = (int64_t)blockIdx.x * run_tiles;
+  const int64_t t1 = std::min<int64_t>(t0 + run_tiles, a.total_tiles);
   TileHeader H;
   uint32_t run_sum[RADIX / 64] = {0, 0, 0, 0};
   uint32_t *h = s_h + wave * RADIX;
@@ -348,10 +298,10 @@ __global__ __launch_bounds__(1024) void k_block_scan(SortLaunch a, int64_t runs)
 }
 
 // Tile counts become exclusive prefixes, in place; one block per run.
-__global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a) {
+__global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a, int run_tiles) {
   const int d = threadIdx.x;
-  const int64_t t0 = (int64_t)blockIdx.x * UP_TILES;
-  const int64_t t1 = std::min<int64_t>(t0 + UP_TILES, a.total_tiles);
+  const int64_t t0 = (int64_t)blockIdx.x * run_tiles;
+  const int64_t t1 = std::min<int64_t>(t0 + run_tiles, a.total_tiles);
   uint32_t run = a.bsum[(int64_t)blockIdx.x * RADIX + d];
   for (int64_t t = t0; t < t1; ++t) {
     const uint32_t v = a.counts[t * RADIX + d];
@@ -508,7 +458,25 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
 
 int sort_tile(int items) { return 256 * items; }
 
-int64_t sort_runs(int64_t tiles) { return (tiles + UP_TILES - 1) / UP_TILES; }
+// Tiles per upsweep run: the power of two in [4, 32] that gives about 2048
+// runs (blocks), so that small inputs still spread over the device.
+static int run_tiles_for(int64_t tiles) {
+  const int64_t r = tiles / 2048;
+  int rt = 4;
+  while (rt < 32 && 2 * rt <= r) rt *= 2;
+  return rt;
+}
+
+int64_t sort_runs(int64_t tiles) {
+  const int rt = run_tiles_for(tiles);
+  return (tiles + rt - 1) / rt;
+}
+
+// Upper bound of sort_runs(t) over t <= max_tiles: below 2^16 tiles there
+// are at most 4096 runs, above it every run holds 32 tiles.
+int64_t sort_runs_bound(int64_t max_tiles) {
+  return std::max<int64_t>(4096, (max_tiles + 31) / 32) + 1;
+}
 
 // Blocks of the downsweep that fit on the device at once.
 template <int ITEMS>
@@ -531,10 +499,11 @@ int sort_resident_blocks(int items) {
 
 template <int ITEMS, int MODE>
 static hipError_t launch_pass_t(const SortLaunch &a, hipStream_t s) {
-  const int64_t runs = sort_runs(a.total_tiles);
-  hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS);
+  const int rt = run_tiles_for(a.total_tiles);
+  const int64_t runs = (a.total_tiles + rt - 1) / rt;
+  hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS, rt);
   hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
-  hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a);
+  hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
   hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
   const int64_t g = std::max<int64_t>(
       NUM_XCD, std::min<int64_t>(a.total_tiles, resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);

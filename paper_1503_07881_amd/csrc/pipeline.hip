@@ -3,20 +3,26 @@
 // One call converts S >= 1 tables.  Every phase runs once for the whole
 // batch, each kernel walking the tiles of all tables:
 //
-//   phase N  8 radix passes over the 2n node keys, unique
+//   phase N  node numbering, by one of two methods (same result):
+//            sort   8 radix passes over the 2n node keys, unique
+//            hash   distinct-count estimate (sync #0 sizes the tables),
+//                   node hash table insert, compaction of the V keys
 //   sync #1  read back V of every table, size the node-sized outputs
-//   phase E  directory, remap + pack, radix passes over the packed edge
-//            keys, dedupe + out-offsets
+//   phase E  sort: directory + remap; hash: radix passes over the V keys,
+//            rank + remap; then radix passes over the packed edge keys,
+//            dedupe + out-offsets
 //   sync #2  read back E of every table, size the edge-sized outputs
 //   phase I  radix passes over the (d, s) keys (the first one also writes
 //            the out-neighbours), in-CSR
 //
-// Everything is enqueued on the caller's stream; the two synchronisations
-// exist only to size the outputs exactly ("no need to estimate the size of
-// the hash table or neighbor vectors in advance", Section 2.4).
+// Everything is enqueued on the caller's stream.  The synchronisations exist
+// only to size buffers and outputs exactly: like the paper's conversion
+// (Section 2.4), which counts neighbours before it places them, nothing is
+// sized by a guess that could fall short.
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -136,23 +142,56 @@ void pinned_release(Pinned *b, hipStream_t s) {
 
 // ------------------------------------------------------------- schedule
 
-// Items per thread of the scatter tile by table size (log2 buckets).
+// Items per thread of the scatter tile and node-numbering method by table
+// size (log2 buckets).  Built-in default: the hash numbering from 2^20 rows.
 int g_items[64];
+int g_method[64];
 bool g_items_init = false;
+constexpr int HASH_DEFAULT_LOG2 = 20;
+
+void schedule_init_locked() {
+  if (g_items_init) return;
+  for (int i = 0; i < 64; ++i) {
+    g_items[i] = 16;
+    g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
+  }
+  g_items_init = true;
+}
 
 int items_for(int64_t rows) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_items_init) {
-    for (int i = 0; i < 64; ++i) g_items[i] = 16;
-    g_items_init = true;
-  }
+  schedule_init_locked();
   return g_items[ceil_log2(std::max<int64_t>(rows, 1))];
+}
+
+int method_for(int64_t rows) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  schedule_init_locked();
+  return g_method[ceil_log2(std::max<int64_t>(rows, 1))];
+}
+
+// Slots of a table's node hash table: the smallest power of two holding
+// twice the estimated distinct keys (load <= 1/2 while the estimate holds),
+// never more than a load of 1/2 at V = 2n needs, never fewer than 64, at
+// most 2^31.
+// RINGO_HASH_TEST_CAPACITY (test support) caps it, to exercise the overflow
+// fallback.
+int64_t table_capacity(int64_t est, int64_t rows) {
+  int64_t want = std::max<int64_t>(64, 2 * est);
+  want = std::min<int64_t>(want, 4 * std::max<int64_t>(rows, 16));
+  want = std::min<int64_t>(want, (int64_t)1 << 31);  // slot indices stay below 2^32 - 1
+  int64_t cap = (int64_t)1 << ceil_log2(want);
+  const char *env = std::getenv("RINGO_HASH_TEST_CAPACITY");
+  const int64_t test_cap = env ? std::max<int64_t>(1, std::atoll(env)) : 0;
+  if (test_cap > 0 && cap > test_cap) cap = (int64_t)1 << (63 - __builtin_clzll((uint64_t)test_cap));
+  return cap;
 }
 
 // ----------------------------------------------------------- tile maps
 
 enum TileKind {
-  TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR, TM_KINDS
+  TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR,
+  TM_HLL, TM_HCMP, TM_VSORT, TM_KINDS
 };
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -174,6 +213,9 @@ struct Call {
   int64_t *results = nullptr;
   uint8_t *meta = nullptr;
   DirEntry *dir = nullptr;
+  void *tab = nullptr;    // node hash tables: keys, then ranks
+  uint32_t *hslots = nullptr;  // slot of every node key
+  void *hmeta = nullptr;  // estimate registers, slot counts and flags of the hash tables
   uint32_t *counts = nullptr;
   uint32_t *bsum = nullptr;
   size_t meta_bytes = 0;
@@ -185,8 +227,12 @@ struct Call {
   ~Call() { release_workspace(); }
 
   void release_workspace() {
-    void *bufs[] = {A, B, status, base, counters, results, meta, dir, counts, bsum};
+    void *bufs[] = {A, B, status, base, counters, results, meta, dir, tab, hslots, hmeta, counts,
+                    bsum};
     for (void *b : bufs) dev_free(hooks, b, stream);
+    tab = nullptr;
+    hslots = nullptr;
+    hmeta = nullptr;
     A = B = nullptr;
     status = nullptr;
     base = nullptr;
@@ -226,6 +272,8 @@ struct Call {
     return t;
   }
 
+  static constexpr int kUploadSlots = 6;  // at most 5 uploads per call
+
   hipError_t upload() {
     char *stage = (char *)pin->p + (size_t)upload_slot * meta_bytes;
     ++upload_slot;
@@ -236,7 +284,7 @@ struct Call {
 
   // Read back S counts from results[off..off+S) and wait for the stream.
   hipError_t readback(int off, std::vector<int64_t> &v) {
-    int64_t *host = (int64_t *)((char *)pin->p + 3 * meta_bytes);
+    int64_t *host = (int64_t *)((char *)pin->p + kUploadSlots * meta_bytes);
     hipError_t e = hipMemcpyAsync(host, results + off, sizeof(int64_t) * S, hipMemcpyDeviceToHost,
                                   stream);
     if (e != hipSuccess) return e;
@@ -279,11 +327,14 @@ struct Call {
 
 enum TraceKind {
   TK_SORT_NODE, TK_UNIQUE, TK_DIR, TK_REMAP, TK_SORT_EDGE, TK_DEDUPE, TK_SORT_IN,
-  TK_IN_CSR, TK_AUX, TK_KINDS
+  TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT, TK_SORT_VNODE, TK_HRANK, TK_HREMAP,
+  TK_KINDS
 };
-const char *const kTraceNames[TK_KINDS] = {"sort_pass_node", "unique", "directory",
-                                           "remap_pack", "sort_pass_edge", "dedupe_out_csr",
-                                           "sort_pass_in", "in_csr", "aux"};
+const char *const kTraceNames[TK_KINDS] = {
+    "sort_pass_node", "unique",         "directory",       "remap_pack",
+    "sort_pass_edge", "dedupe_out_csr", "sort_pass_in",    "in_csr",
+    "aux",            "hash_estimate",  "hash_insert",     "hash_compact",
+    "sort_pass_vnode", "hash_rank",     "hash_remap_pack"};
 
 struct TraceRec {
   int kind;
@@ -374,16 +425,19 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     max_rows = std::max(max_rows, p.n);
   }
   c.items = items_for(S == 1 ? max_rows : N);
+  const bool want_hash = method_for(S == 1 ? max_rows : N) == RINGO_NODES_HASH;
   c.sort_tile = sort_tile(c.items);
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
   c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
+  c.set_tiles(TM_HLL, RANGE_ROWS, HLL_TILE);
+  c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
 
   const int64_t status_words = c.total(TM_UNIQ) + RADIX;  // one word per unique/dedupe tile
   // the node pass has the most tiles: 2n keys per table
   const int64_t max_tiles = c.total(TM_NSORT) + 1;
-  const int64_t max_runs = sort_runs(max_tiles) + 1;
+  const int64_t max_runs = sort_runs_bound(max_tiles);
   c.meta_bytes = align_up(align_up(sizeof(SegPlan) * S) + sizeof(int64_t) * c.tmap.size());
-  c.pin = pinned_acquire(3 * c.meta_bytes + sizeof(int64_t) * S);
+  c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t) * S);
   if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
 
   const size_t base_words = (size_t)S * RADIX;
@@ -406,28 +460,84 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
 
   // ------------------------------------------------------------- phase N
+  // Both methods leave V in results[0, S); the sort method leaves the
+  // sorted distinct keys in A, the hash method leaves them unordered in A.
+  std::vector<int64_t> V;
+  bool hashed = false;
+  int64_t slots = 0;
+  uint64_t *hkeys = nullptr;
+  uint32_t *hrank = nullptr;
+  long hcompact_rec = -1;
+  if (want_hash) {
+    const size_t reg_bytes = align_up(sizeof(uint32_t) * HLL_M * S);
+    const size_t cnt_bytes = align_up(sizeof(uint64_t) * S);
+    const size_t hm_bytes = reg_bytes + cnt_bytes + align_up(sizeof(uint32_t) * S);
+    c.hmeta = dev_alloc(c.hooks, hm_bytes, st);
+    if (!c.hmeta) return RINGO_ERR_OUT_OF_MEMORY;
+    uint32_t *regs = (uint32_t *)c.hmeta;
+    uint64_t *hcount = (uint64_t *)((char *)c.hmeta + reg_bytes);
+    uint32_t *hflags = (uint32_t *)((char *)c.hmeta + reg_bytes + cnt_bytes);
+    HIP_TRY(launch_fill_u64((uint64_t *)c.hmeta, 0, (int64_t)(hm_bytes / 8), st));
+    TRACED(TK_HLL, 2 * N, 16.0 * N,
+           launch_hll(c.tiles(TM_HLL, RANGE_ROWS), regs, c.results,
+                      grid_for(c.total(TM_HLL), cus * 4), st));
+    // sync #0: size every table's node hash table from its estimate
+    std::vector<int64_t> est;
+    HIP_TRY(c.readback(0, est));
+    for (int i = 0; i < S; ++i) {
+      SegPlan &p = c.plan[i];
+      p.tab_off = slots;
+      p.tab_cap = p.n > 0 ? table_capacity(est[i], p.n) : 0;
+      slots += p.tab_cap;
+    }
+    const size_t key_bytes = align_up(sizeof(uint64_t) * std::max<int64_t>(slots, 1));
+    c.tab = dev_alloc(c.hooks, key_bytes + sizeof(uint32_t) * std::max<int64_t>(slots, 1), st);
+    c.hslots = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 2 * std::max<int64_t>(N, 1), st);
+    if (!c.tab || !c.hslots) return RINGO_ERR_OUT_OF_MEMORY;
+    hkeys = (uint64_t *)c.tab;
+    hrank = (uint32_t *)((char *)c.tab + key_bytes);
+    c.set_tiles(TM_HCMP, RANGE_SLOTS, SCAN_TILE);
+    HIP_TRY(c.upload());
+    HIP_TRY(launch_fill_u64(hkeys, EMPTY_KEY, slots, st));
+    TRACED(TK_HINSERT, 2 * N, 24.0 * N,
+           launch_hash_insert(c.tiles(TM_REMAP, RANGE_ROWS), hkeys, c.hslots, hflags,
+                              grid_for(c.total(TM_REMAP), cus * 8), st));
+    {
+      TraceMark m = trace_begin(st);
+      HIP_TRY(launch_hash_compact(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, c.A, hcount, hflags,
+                                  c.results, grid_for(c.total(TM_HCMP), cus * 8), st));
+      hcompact_rec = trace_end(m, TK_HCOMPACT, slots, 8.0 * slots, st);
+    }
+    HIP_TRY(c.readback(0, V));  // sync #1
+    hashed = true;
+    for (int i = 0; i < S; ++i) hashed = hashed && V[i] >= 0;
+    if (!hashed) {
+      // a table overflowed its probe bound: number the nodes by sorting
+      dev_free(c.hooks, c.tab, st);
+      dev_free(c.hooks, c.hslots, st);
+      c.tab = nullptr;
+      c.hslots = nullptr;
+      HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
+    }
+  }
   uint64_t *buf[2] = {c.A, c.B};
-  {
+  if (!hashed) {
     for (int p = 0; p < NODE_PASSES; ++p) {
       SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
                                  RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
       TRACED(TK_SORT_NODE, 2 * N, 32.0 * N,
              launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, st));
     }
-  }
-  uint64_t *sorted_nodes = buf[(NODE_PASSES - 1) & 1];
-  uint64_t *nodes_ws = buf[NODE_PASSES & 1];
-  {
+    // 8 passes end in B; the distinct keys go to A
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), sorted_nodes, nodes_ws, c.results,
-                          c.status, c.counters + ep, ep, grid_for(c.total(TM_UNIQ), cus * 4), st));
+    HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.status,
+                          c.counters + ep, ep, grid_for(c.total(TM_UNIQ), cus * 4), st));
     unique_rec = trace_end(m, TK_UNIQUE, 2 * N, 16.0 * N, st);
+    HIP_TRY(c.readback(0, V));  // sync #1
   }
 
   // -------------------------------------------------------------- sync #1
-  std::vector<int64_t> V;
-  HIP_TRY(c.readback(0, V));
   int b_max = 1;
   int64_t dir_words = 0;
   size_t arena1 = 0;
@@ -440,7 +550,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     p.b = std::max(1, p.dirk);
     b_max = std::max(b_max, p.V > 0 ? p.b : 1);
     p.dir_off = dir_words;
-    dir_words += p.V > 0 ? ((int64_t)1 << p.dirk) + 1 : 0;
+    if (!hashed) dir_words += p.V > 0 ? ((int64_t)1 << p.dirk) + 1 : 0;
     off1[3 * i] = arena1;
     arena1 = align_up(arena1 + sizeof(int64_t) * p.V);
     off1[3 * i + 1] = arena1;
@@ -450,12 +560,16 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   for (int i = 0; i < S; ++i) sumV += V[i];
   trace_set_bytes(unique_rec, 16.0 * N + 8.0 * sumV);
+  trace_set_bytes(hcompact_rec, 8.0 * slots + 8.0 * sumV);
   c.owner = new Owner();
   c.owner->stream = st;
   c.owner->hooks = c.hooks;
   c.owner->blocks[0] = dev_alloc(c.hooks, arena1, st);
-  c.dir = (DirEntry *)dev_alloc(c.hooks, sizeof(DirEntry) * dir_words, st);
-  if (!c.owner->blocks[0] || !c.dir) return RINGO_ERR_OUT_OF_MEMORY;
+  if (!c.owner->blocks[0]) return RINGO_ERR_OUT_OF_MEMORY;
+  if (!hashed) {
+    c.dir = (DirEntry *)dev_alloc(c.hooks, sizeof(DirEntry) * std::max<int64_t>(dir_words, 1), st);
+    if (!c.dir) return RINGO_ERR_OUT_OF_MEMORY;
+  }
   char *a1 = (char *)c.owner->blocks[0];
   for (int i = 0; i < S; ++i) {
     SegPlan &p = c.plan[i];
@@ -466,21 +580,35 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   const int P_e = (2 * b_max + RADIX_BITS - 1) / RADIX_BITS;
   const int P_in = (b_max + RADIX_BITS - 1) / RADIX_BITS;
   c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
-  c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
+  c.set_tiles(TM_VSORT, RANGE_NODES, c.sort_tile);
   c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
   c.set_tiles(TM_DEDUP, RANGE_ROWS, SCAN_TILE);
   HIP_TRY(c.upload());
 
   // ------------------------------------------------------------- phase E
+  // Both methods write the packed edge keys to B; A is free afterwards.
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
-  TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
-         launch_dir(c.tiles(TM_DIR, RANGE_NODES), nodes_ws, c.dir,
-                    grid_for(c.total(TM_DIR), cus * 8), st));
-  // the sorted node keys are consumed: their buffer takes the edge keys
-  uint64_t *ebuf[2] = {sorted_nodes, nodes_ws};
-  TRACED(TK_REMAP, N, 24.0 * N,
-         launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), nodes_ws, c.dir, ebuf[0],
-                      grid_for(c.total(TM_REMAP), cus * 8), st));
+  if (hashed) {
+    for (int p = 0; p < NODE_PASSES; ++p) {  // 8 passes: A -> B -> ... -> A
+      SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES,
+                                 NODE_PASSES, p, RADIX_BITS * p);
+      TRACED(TK_SORT_VNODE, sumV, 16.0 * sumV, launch_sort_pass(a, SORT_PLAIN, c.items, st));
+    }
+    TRACED(TK_HRANK, sumV, 20.0 * sumV,
+           launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), c.A, hkeys, hrank,
+                            grid_for(c.total(TM_DIR), cus * 8), st));
+    TRACED(TK_HREMAP, N, 16.0 * N,
+           launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B,
+                             grid_for(c.total(TM_REMAP), cus * 8), st));
+  } else {
+    TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
+           launch_dir(c.tiles(TM_DIR, RANGE_NODES), c.A, c.dir,
+                      grid_for(c.total(TM_DIR), cus * 8), st));
+    TRACED(TK_REMAP, N, 24.0 * N,
+           launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B,
+                        grid_for(c.total(TM_REMAP), cus * 8), st));
+  }
+  uint64_t *ebuf[2] = {c.B, c.A};
   {
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
@@ -637,6 +765,7 @@ ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out) {
   if (!out || num_rows < 0) return RINGO_ERR_INVALID_ARG;
   out->digit_bits = RADIX_BITS;
   out->items_per_thread = items_for(num_rows);
+  out->node_method = method_for(num_rows);
   return RINGO_OK;
 }
 
@@ -644,9 +773,13 @@ ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched) {
   if (!sched || num_rows < 0 || sched->digit_bits != RADIX_BITS) return RINGO_ERR_INVALID_ARG;
   const int it = sched->items_per_thread;
   if (it != 8 && it != 12 && it != 16) return RINGO_ERR_INVALID_ARG;
-  (void)items_for(0);  // initialise the table
+  const int m = sched->node_method;
+  if (m != RINGO_NODES_SORT && m != RINGO_NODES_HASH) return RINGO_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_items[ceil_log2(std::max<int64_t>(num_rows, 1))] = it;
+  schedule_init_locked();
+  const int k = ceil_log2(std::max<int64_t>(num_rows, 1));
+  g_items[k] = it;
+  g_method[k] = m;
   return RINGO_OK;
 }
 

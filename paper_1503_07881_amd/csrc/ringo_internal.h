@@ -24,6 +24,7 @@ enum RangeKind : int32_t {
   RANGE_ROWS = 1,       // n edge keys at row_off
   RANGE_EDGES = 2,      // E unique edges at row_off
   RANGE_NODES = 3,      // V unique nodes at 2 * row_off
+  RANGE_SLOTS = 4,      // tab_cap node hash table slots at tab_off
 };
 
 // Per-table plan, written by the host before each phase.
@@ -37,6 +38,8 @@ struct SegPlan {
   int32_t b;        // bits of a dense node index, max(1, ceil(log2 V))
   int32_t dirk;     // log2 of the directory bucket count, ceil(log2 V)
   int64_t dir_off;  // first directory entry of this table
+  int64_t tab_off;  // first node hash table slot of this table
+  int64_t tab_cap;  // node hash table slots (a power of two, or 0)
   int64_t *node_ids;
   int64_t *out_off;
   int32_t *out_nbr;
@@ -45,6 +48,7 @@ struct SegPlan {
 };
 
 __host__ __device__ inline int64_t range_start(const SegPlan &p, int kind) {
+  if (kind == RANGE_SLOTS) return p.tab_off;
   return (kind == RANGE_NODE_KEYS || kind == RANGE_NODES) ? 2 * p.row_off : p.row_off;
 }
 __host__ __device__ inline int64_t range_count(const SegPlan &p, int kind) {
@@ -52,6 +56,7 @@ __host__ __device__ inline int64_t range_count(const SegPlan &p, int kind) {
     case RANGE_NODE_KEYS: return 2 * p.n;
     case RANGE_ROWS: return p.n;
     case RANGE_EDGES: return p.E;
+    case RANGE_SLOTS: return p.tab_cap;
     default: return p.V;
   }
 }
@@ -97,6 +102,7 @@ hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_
 int sort_tile(int items);
 int sort_resident_blocks(int items);
 int64_t sort_runs(int64_t tiles);
+int64_t sort_runs_bound(int64_t max_tiles);  // >= sort_runs(t) for every t <= max_tiles
 hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
                          uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
                          hipStream_t s);
@@ -111,6 +117,38 @@ hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, DirEntry *dir,
                       hipStream_t s);
 hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEntry *dir,
                         uint64_t *ekeys, int grid, hipStream_t s);
+// ------------------------------------------------- node hash table (hash.hip)
+
+constexpr int HLL_BITS = 10;                 // log2 of the count-estimate registers
+constexpr int HLL_M = 1 << HLL_BITS;
+constexpr int HLL_TILE = 256 * 64;           // rows per estimate tile
+constexpr uint64_t EMPTY_KEY = ~0ull;        // free slot (the key ~0 is flagged aside)
+constexpr uint32_t HFLAG_MAX_KEY = 1;        // the table holds the key ~0
+constexpr uint32_t HFLAG_OVERFLOW = 2;       // a probe sequence exceeded its bound
+
+// regs [S][HLL_M] must start at zero; est[S] receives the distinct-count
+// estimate of each table's 2n keys.
+hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, int grid,
+                      hipStream_t s);
+// hkeys (tab_cap slots per table at tab_off) must hold EMPTY_KEY; flags [S]
+// and count [S] start at zero.  The insert writes the slot of every key to
+// slots [2 * row_off + r] (source) and [2 * row_off + n + r] (destination).
+// After launch_hash_compact, seg_V[s] is the number of distinct keys of table
+// s, or -1 when its table overflowed, and the keys (unordered) are at
+// nodes + 2 * row_off.
+hipError_t launch_hash_insert(const TileLaunch &rows, uint64_t *hkeys, uint32_t *slots,
+                              uint32_t *flags, int grid, hipStream_t s);
+hipError_t launch_hash_compact(const TileLaunch &slot_tiles, const uint64_t *hkeys,
+                               uint64_t *nodes, uint64_t *count, const uint32_t *flags,
+                               int64_t *seg_V, int grid, hipStream_t s);
+// Writes node_ids from the sorted keys and each key's position into hrank at
+// its slot.
+hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
+                            const uint64_t *hkeys, uint32_t *hrank, int grid, hipStream_t s);
+// Every row's (src, dst) slots -> dense positions, packed edge keys.
+hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
+                             uint64_t *ekeys, int grid, hipStream_t s);
+
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
                          uint32_t epoch, int grid, hipStream_t s);

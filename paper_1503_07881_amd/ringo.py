@@ -68,7 +68,12 @@ class TraceEntry(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     """ringo_schedule_t"""
-    _fields_ = [("digit_bits", ctypes.c_int32), ("items_per_thread", ctypes.c_int32)]
+    _fields_ = [("digit_bits", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
+                ("node_method", ctypes.c_int32)]
+
+
+NODES_SORT = 0
+NODES_HASH = 1
 
 
 _lib = None
@@ -156,15 +161,31 @@ def version() -> str:
     return lib().ringo_version().decode()
 
 
-def tune_get(num_rows: int) -> tuple[int, int]:
+def tune_get(num_rows: int) -> tuple[int, int, int]:
+    """(digit_bits, items_per_thread, node_method) used for num_rows rows."""
     s = Schedule()
     _check(lib().ringo_tune_get(num_rows, ctypes.byref(s)), "ringo_tune_get")
-    return s.digit_bits, s.items_per_thread
+    return s.digit_bits, s.items_per_thread, s.node_method
 
 
-def tune_set(num_rows: int, digit_bits: int, items_per_thread: int) -> None:
-    s = Schedule(digit_bits, items_per_thread)
+def tune_set(num_rows: int, digit_bits: int, items_per_thread: int, node_method: int | None = None) -> None:
+    """Overrides the schedule of num_rows' size bucket; node_method None keeps
+    the bucket's current method."""
+    if node_method is None:
+        node_method = tune_get(num_rows)[2]
+    s = Schedule(digit_bits, items_per_thread, node_method)
     _check(lib().ringo_tune_set(num_rows, ctypes.byref(s)), "ringo_tune_set")
+
+
+def set_node_method(node_method: int, min_rows: int = 0) -> None:
+    """Sets the node-numbering method of every size bucket from min_rows up,
+    keeping each bucket's tile shape."""
+    for e in range(63):
+        rows = 1 << e
+        if rows < min_rows:
+            continue
+        d, it, _ = tune_get(rows)
+        tune_set(rows, d, it, node_method)
 
 
 def trace_enable(on: bool) -> None:
@@ -173,8 +194,8 @@ def trace_enable(on: bool) -> None:
 
 def trace_read() -> dict:
     """Per-kernel launches, summed event time (ms), algorithmic bytes, units."""
-    buf = (TraceEntry * 16)()
-    n = lib().ringo_trace_read(buf, 16)
+    buf = (TraceEntry * 32)()
+    n = lib().ringo_trace_read(buf, 32)
     if n < 0:
         raise RingoError(4, "ringo_trace_read")
     return {buf[i].kernel.decode(): {"launches": buf[i].launches, "ms": buf[i].total_ms, "bytes": buf[i].bytes,

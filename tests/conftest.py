@@ -27,3 +27,15 @@ def cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
+
+
+@pytest.fixture(params=["sort", "hash"])
+def method(request):
+    """Runs the test once per node-numbering method (every size bucket set to
+    it), restoring the library's schedule afterwards."""
+    from paper_1503_07881_amd import ringo
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    ringo.set_node_method(ringo.NODES_HASH if request.param == "hash" else ringo.NODES_SORT)
+    yield request.param
+    for e, (d, it, m) in enumerate(saved):
+        ringo.tune_set(1 << e, d, it, m)

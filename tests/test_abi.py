@@ -56,11 +56,17 @@ def test_invalid_arguments_rejected_on_host():
 
 
 def test_tune_schedule_roundtrip():
-    d, it = ringo.tune_get(1000)
-    assert d == 8 and it in (8, 12, 16)
+    d, it, m = ringo.tune_get(1000)
+    assert d == 8 and it in (8, 12, 16) and m == ringo.NODES_SORT
+    assert ringo.tune_get(1 << 24)[2] == ringo.NODES_HASH   # built-in default for large tables
     ringo.tune_set(1 << 20, 8, 12)
-    assert ringo.tune_get(1 << 20) == (8, 12)
-    ringo.tune_set(1 << 20, 8, 16)
+    assert ringo.tune_get(1 << 20) == (8, 12, ringo.NODES_HASH)
+    ringo.tune_set(1 << 20, 8, 12, ringo.NODES_SORT)
+    assert ringo.tune_get(1 << 20) == (8, 12, ringo.NODES_SORT)
+    assert ringo.tune_get(1 << 21)[2] == ringo.NODES_HASH   # other buckets untouched
+    ringo.tune_set(1 << 20, 8, 16, ringo.NODES_HASH)
+    with pytest.raises(ringo.RingoError):
+        ringo.tune_set(1000, 8, 16, 2)
     with pytest.raises(ringo.RingoError):
         ringo.tune_set(1000, 9, 16)
     with pytest.raises(ringo.RingoError):
@@ -98,13 +104,17 @@ def test_config4_sizes():
 def test_autotune_cache_roundtrip(tmp_path):
     from paper_1503_07881_amd import autotune
     cache = {"device": "test", "digit_bits": 8,
-             "buckets": {str(1 << 10): {"items": 8}, str(1 << 20): {"items": 12}, str(1 << 24): {"items": 16}}}
+             "buckets": {str(1 << 10): {"items": 8, "node_method": 0}, str(1 << 20): {"items": 12, "node_method": 1},
+                         str(1 << 24): {"items": 16}}}
     path = autotune.save(cache, str(tmp_path / "tune.json"))
     assert autotune.load(path) == cache
     assert autotune.apply(autotune.load(path)) == 63
     assert ringo.tune_get(1 << 5)[1] == 8      # below the first tuned size: nearest
     assert ringo.tune_get(1 << 15)[1] == 8
-    assert ringo.tune_get(1 << 21)[1] == 12
+    assert ringo.tune_get(1 << 21)[1:] == (12, 1)
     assert ringo.tune_get(1 << 30)[1] == 16
+    assert ringo.tune_get(1 << 15)[2] == 0
     assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
-    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 16}}})  # restore the default
+    # restore the built-in default
+    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 16, "node_method": 0},
+                                                  str(1 << 20): {"items": 16, "node_method": 1}}})

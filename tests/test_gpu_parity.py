@@ -31,9 +31,9 @@ def gpu_graph(src, dst, dev):
     return g
 
 
-def test_hand_examples(cuda):
+def test_hand_examples(cuda, method):
     for ex in json.load(open(GOLDEN))["examples"]:
-        say("hand example", ex["name"])
+        say("hand example", ex["name"], method)
         src = np.array(ex["src"], dtype=np.int64)
         dst = np.array(ex["dst"], dtype=np.int64)
         g = gpu_graph(src, dst, cuda)
@@ -54,24 +54,24 @@ EDGE_SIZES = [1, 2, 3, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 819
 
 
 @pytest.mark.parametrize("n", EDGE_SIZES)
-def test_tile_boundaries(cuda, n):
+def test_tile_boundaries(cuda, method, n):
     for pool in (1, 7, max(1, n // 3), 4 * n):
-        say("tile boundary case n", n, "pool", pool)
+        say("tile boundary case n", n, "pool", pool, method)
         src, dst = random_table(n * 31 + pool, n, pool)
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"n={n} pool={pool}: ")
 
 
 @pytest.mark.parametrize("seed", range(8))
-def test_random_small(cuda, seed):
+def test_random_small(cuda, method, seed):
     rng = np.random.default_rng(1000 + seed)
     n = int(rng.integers(0, 300_000))
     pool = int(rng.integers(1, max(2, 2 * n)))
-    say("random case seed", seed, "n", n, "pool", pool)
+    say("random case seed", seed, "n", n, "pool", pool, method)
     src, dst = random_table(seed, n, pool)
     assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst))
 
 
-def test_special_structures(cuda):
+def test_special_structures(cuda, method):
     k = 61
     ids = np.array([workloads.mix64(i) - (1 << 63) for i in range(k)], dtype=np.int64)
     a, b = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
@@ -90,40 +90,40 @@ def test_special_structures(cuda):
                                                          dtype=np.int64)
         cases[f"path_V{V}"] = (vids, np.roll(vids, -1))
     for name, (src, dst) in cases.items():
-        say("special case", name)
+        say("special case", name, method)
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), name + ": ")
 
 
-def test_config1_full(cuda):
-    say("config 1: 1,000,000 rows")
+def test_config1_full(cuda, method):
+    say("config 1: 1,000,000 rows", method)
     src, dst = workloads.generate_host(workloads.config1())
     g = gpu_graph(src, dst, cuda)
     assert g.num_nodes == 100_000
     assert_same(g, oracle.table_to_graph(src, dst))
 
 
-def test_determinism(cuda):
-    say("determinism: two runs of an R-MAT table")
+def test_determinism(cuda, method):
+    say("determinism: two runs of an R-MAT table", method)
     src, dst = workloads.generate_host(workloads.TableSpec("rmat", 3_000_000, seed=21, scale=18))
     g1 = gpu_graph(src, dst, cuda)
     g2 = gpu_graph(src, dst, cuda)
     assert_same(g1, g2)
 
 
-def test_rmat_medium_vs_oracle(cuda):
-    say("R-MAT scale 20, 4M rows vs oracle")
+def test_rmat_medium_vs_oracle(cuda, method):
+    say("R-MAT scale 20, 4M rows vs oracle", method)
     spec = workloads.TableSpec("rmat", 1 << 22, seed=22, scale=20)
     src, dst = workloads.generate_host(spec)
     g = gpu_graph(src, dst, cuda)
     assert_same(g, oracle.table_to_graph(src, dst))
 
 
-def test_batched_equals_singles_and_oracle(cuda):
+def test_batched_equals_singles_and_oracle(cuda, method):
     import torch
     specs = [workloads.mixed_table(77, i, 1, 300_000) for i in range(40)]
     specs += [workloads.TableSpec("uniform", 0, seed=1), workloads.TableSpec("uniform", 1, seed=2, pool=1)]
     tables = [workloads.generate_host(s) for s in specs]
-    say("batched: tables", len(tables), "rows", sum(s.n for s in specs))
+    say("batched: tables", len(tables), "rows", sum(s.n for s in specs), method)
     ts = [(torch.from_numpy(s).to(cuda), torch.from_numpy(d).to(cuda)) for s, d in tables]
     gb = ringo.to_graph_batched([s for s, _ in ts], [d for _, d in ts])
     torch.cuda.synchronize()
@@ -132,6 +132,24 @@ def test_batched_equals_singles_and_oracle(cuda):
         torch.cuda.synchronize()
         assert_same(gb[i], g1, f"table {i} batched vs single: ")
         assert_same(gb[i], oracle.table_to_graph(hs, hd), f"table {i} vs oracle: ")
+
+
+@pytest.mark.parametrize("cap", [1, 64, 4096])
+def test_hash_overflow_falls_back_to_sort(cuda, cap):
+    """Node hash tables capped far below V (forced from the host): every probe
+    sequence stops at its bound, the call numbers the nodes by sorting, and
+    the graph is still the oracle's.  Tables that fit keep the hash path."""
+    try:
+        os.environ["RINGO_HASH_TEST_CAPACITY"] = str(cap)
+        ringo.set_node_method(ringo.NODES_HASH)
+        for n, pool in ((5, 3), (1000, 40), (20000, 5000), (200_000, 150_000)):
+            say("hash capacity", cap, "n", n, "pool", pool)
+            src, dst = random_table(n + cap, n, pool)
+            assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"cap={cap} n={n}: ")
+    finally:
+        del os.environ["RINGO_HASH_TEST_CAPACITY"]
+        ringo.set_node_method(ringo.NODES_SORT)
+        ringo.set_node_method(ringo.NODES_HASH, 1 << 20)
 
 
 @pytest.mark.slow
@@ -150,9 +168,19 @@ def test_config2_full_size(cuda):
     assert np.array_equal(src[:100_000].cpu().numpy(), hs) and np.array_equal(dst[:100_000].cpu().numpy(), hd)
     g = ringo.to_graph(src, dst)
     torch.cuda.synchronize()
-    say("config 2: V", g.num_nodes, "E", g.num_edges)
+    say("config 2: V", g.num_nodes, "E", g.num_edges, "method", ringo.tune_get(spec.n)[2])
     check_invariants_torch(g, src, dst)
     check_sampled(g, src, dst, num_samples=200)
+    # the other node-numbering method gives the same bytes
+    d, it, m = ringo.tune_get(spec.n)
+    try:
+        ringo.tune_set(spec.n, d, it, 1 - m)
+        g2 = ringo.to_graph(src, dst)
+        torch.cuda.synchronize()
+    finally:
+        ringo.tune_set(spec.n, d, it, m)
+    say("config 2: method", 1 - m, "V", g2.num_nodes, "E", g2.num_edges)
+    assert _same_on_device(g, g2) is None
 
 
 def _device_tables(specs, dev):
