@@ -25,30 +25,55 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sort_pass_node_rmat_s22.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07881_amd", "csrc", "kernels.hip")
+KERNEL_DIR = os.path.join(ROOT, "paper_1503_07881_amd", "csrc")
+
+# Trace entry -> kernel name in a rocprofv3 summary ({items}: items per thread).
+# Radix-pass instantiations: <256, items, mode>, mode 1 node (first pass),
+# 3 node, 4 distinct nodes, 5 edge, 2 in (first pass), 6 in.
+ROCPROF_NAME = {
+    "hash_estimate": "k_hll", "hash_insert": "k_hash_insert", "hash_compact": "k_hash_compact",
+    "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "unique": "k_unique",
+    "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe", "in_csr": "k_in_csr",
+    "sort_node_scatter": "k_downsweep<256, {items}, 1|3>", "sort_vnode_scatter": "k_downsweep<256, {items}, 4>",
+    "sort_edge_scatter": "k_downsweep<256, {items}, 5>", "sort_in_scatter": "k_downsweep<256, {items}, 2|6>",
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_file(kernel: str) -> str:
+    return "hash.hip" if kernel.startswith("hash_") else "kernels.hip"
 
 
-def read_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when the kernel changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+def kernel_source_sha(kernel: str) -> str:
+    """Digest of the source file that holds `kernel` and of the device
+    helpers it includes: counter summaries taken before a change to them no
+    longer describe the kernel."""
+    h = hashlib.sha256()
+    for name in (kernel_source_file(kernel), "device_common.h"):
+        with open(os.path.join(KERNEL_DIR, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(kernel: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when the kernels changed since."""
+    path = traffic_file(kernel, workload)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha") != kernel_source_sha():
+    if vals.get("kernel_source_sha") != kernel_source_sha(kernel):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -296,12 +321,16 @@ def main():
                          "ms_per_step": round(t["ms"] / args.steps, 4),
                          "avg_launch_ms": round(avg_ms, 5),
                          "GBps": round(bpl / (avg_ms / 1e3) / 1e9, 1)}
-    dom = max(trace, key=lambda k: trace[k]["ms"])
+    # the dominant kernel: most time per step among entries that are one kernel
+    dom = max((k for k in trace if not k.endswith("_count")), key=lambda k: trace[k]["ms"])
     t = trace[dom]
     avg_s = t["ms"] / t["launches"] / 1e3
     bytes_per_launch = t["bytes"] / t["launches"]
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = read_traffic() if dom == "sort_pass_node" else None
+    workload = (f"{spec.kind}_scale{spec.scale}_rows{n}" if spec.kind == "rmat"
+                else f"uniform_rows{n}_pool{spec.pool}")
+    traffic = read_traffic(dom, workload)
+    items = ringo.tune_get(n)[1]
 
     out = {
         "metric": "edges/s converted (input rows per second, table to directed simple graph, 1 GPU)",
@@ -316,11 +345,13 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)",
-        "config": {"workload": f"{spec.kind}_scale{spec.scale}_rows{n}" if spec.kind == "rmat"
-                   else f"uniform_rows{n}_pool{spec.pool}",
+        "config": {"workload": workload,
                    "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
-                   "digit_bits": 8, "items_per_thread": ringo.tune_get(n)[1]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                   "digit_bits": 8, "items_per_thread": items,
+                   "node_method": "hash" if ringo.tune_get(n)[2] == ringo.NODES_HASH else "sort"},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 5)},

@@ -498,35 +498,51 @@ int sort_resident_blocks(int items) {
 }
 
 template <int ITEMS, int MODE>
-static hipError_t launch_pass_t(const SortLaunch &a, hipStream_t s) {
-  const int rt = run_tiles_for(a.total_tiles);
-  const int64_t runs = (a.total_tiles + rt - 1) / rt;
-  hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS, rt);
-  hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
-  hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
-  hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
-  const int64_t g = std::max<int64_t>(
-      NUM_XCD, std::min<int64_t>(a.total_tiles, resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);
-  hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
+static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
+  if (parts & SORT_PART_COUNT) {
+    const int rt = run_tiles_for(a.total_tiles);
+    const int64_t runs = (a.total_tiles + rt - 1) / rt;
+    hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS,
+                       rt);
+    hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
+    hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
+    hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
+  }
+  if (parts & SORT_PART_SCATTER) {
+    const int64_t g = std::max<int64_t>(
+        NUM_XCD, std::min<int64_t>(a.total_tiles, resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);
+    hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
+// Every use of the pass has its own instantiation (the kernels differ only
+// for the two first passes that read their keys from elsewhere), so that a
+// profile names the pass a kernel belongs to.
 template <int ITEMS>
-static hipError_t launch_pass_items(const SortLaunch &a, int mode, hipStream_t s) {
+static hipError_t launch_pass_items(const SortLaunch &a, int mode, int parts, hipStream_t s) {
   switch (mode) {
-    case SORT_NODE_FIRST: return launch_pass_t<ITEMS, SORT_NODE_FIRST>(a, s);
-    case SORT_IN_FIRST: return launch_pass_t<ITEMS, SORT_IN_FIRST>(a, s);
-    default: return launch_pass_t<ITEMS, SORT_PLAIN>(a, s);
+    case SORT_NODE_FIRST: return launch_pass_t<ITEMS, SORT_NODE_FIRST>(a, parts, s);
+    case SORT_IN_FIRST: return launch_pass_t<ITEMS, SORT_IN_FIRST>(a, parts, s);
+    case SORT_NODE: return launch_pass_t<ITEMS, SORT_NODE>(a, parts, s);
+    case SORT_VNODE: return launch_pass_t<ITEMS, SORT_VNODE>(a, parts, s);
+    case SORT_EDGE: return launch_pass_t<ITEMS, SORT_EDGE>(a, parts, s);
+    case SORT_IN: return launch_pass_t<ITEMS, SORT_IN>(a, parts, s);
+    default: return launch_pass_t<ITEMS, SORT_PLAIN>(a, parts, s);
+  }
+}
+
+hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts, hipStream_t s) {
+  if (a.total_tiles == 0) return hipSuccess;
+  switch (items) {
+    case 8: return launch_pass_items<8>(a, mode, parts, s);
+    case 12: return launch_pass_items<12>(a, mode, parts, s);
+    default: return launch_pass_items<16>(a, mode, parts, s);
   }
 }
 
 hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s) {
-  if (a.total_tiles == 0) return hipSuccess;
-  switch (items) {
-    case 8: return launch_pass_items<8>(a, mode, s);
-    case 12: return launch_pass_items<12>(a, mode, s);
-    default: return launch_pass_items<16>(a, mode, s);
-  }
+  return launch_sort_part(a, mode, items, SORT_PART_COUNT | SORT_PART_SCATTER, s);
 }
 
 // ------------------------------------------------------ unique (node set)

@@ -326,15 +326,18 @@ struct Call {
 // counts, summed durations and the algorithmic bytes the launches move.
 
 enum TraceKind {
-  TK_SORT_NODE, TK_UNIQUE, TK_DIR, TK_REMAP, TK_SORT_EDGE, TK_DEDUPE, TK_SORT_IN,
-  TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT, TK_SORT_VNODE, TK_HRANK, TK_HREMAP,
-  TK_KINDS
+  TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
+  TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
+  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_KINDS
 };
+// "count" entries are the four small kernels of a pass's digit counting and
+// prefixes; every other entry is a single kernel.
 const char *const kTraceNames[TK_KINDS] = {
-    "sort_pass_node", "unique",         "directory",       "remap_pack",
-    "sort_pass_edge", "dedupe_out_csr", "sort_pass_in",    "in_csr",
-    "aux",            "hash_estimate",  "hash_insert",     "hash_compact",
-    "sort_pass_vnode", "hash_rank",     "hash_remap_pack"};
+    "sort_node_count",   "sort_node_scatter", "unique",          "directory",
+    "remap_pack",        "sort_edge_count",   "sort_edge_scatter", "dedupe_out_csr",
+    "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
+    "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
+    "sort_vnode_scatter", "hash_rank",        "hash_remap_pack"};
 
 struct TraceRec {
   int kind;
@@ -396,6 +399,15 @@ void trace_set_bytes(long idx, double bytes) {
     TraceMark _m = trace_begin(st);                            \
     HIP_TRY(expr);                                             \
     (void)trace_end(_m, (kind), (units), (double)(bytes), st); \
+  } while (0)
+
+// One radix pass as two traced entries: counting (reads every key) and
+// scatter (reads and writes every key, plus extra bytes per key).
+#define TRACED_PASS(kcount, kscatter, keys, extra, mode, a)                                     \
+  do {                                                                                        \
+    TRACED(kcount, keys, 8.0 * (keys), launch_sort_part(a, mode, c.items, SORT_PART_COUNT, st)); \
+    TRACED(kscatter, keys, (16.0 + (extra)) * (keys),                                         \
+           launch_sort_part(a, mode, c.items, SORT_PART_SCATTER, st));                        \
   } while (0)
 
 int grid_for(int64_t tiles, int cap) {
@@ -525,8 +537,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < NODE_PASSES; ++p) {
       SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
                                  RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
-      TRACED(TK_SORT_NODE, 2 * N, 32.0 * N,
-             launch_sort_pass(a, p == 0 ? SORT_NODE_FIRST : SORT_PLAIN, c.items, st));
+      TRACED_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * N, 0.0, p == 0 ? SORT_NODE_FIRST : SORT_NODE,
+                  a);
     }
     // 8 passes end in B; the distinct keys go to A
     const uint32_t ep = ++c.epoch;
@@ -592,7 +604,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < NODE_PASSES; ++p) {  // 8 passes: A -> B -> ... -> A
       SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES,
                                  NODE_PASSES, p, RADIX_BITS * p);
-      TRACED(TK_SORT_VNODE, sumV, 16.0 * sumV, launch_sort_pass(a, SORT_PLAIN, c.items, st));
+      TRACED_PASS(TK_VNODE_COUNT, TK_VNODE_SCATTER, sumV, 0.0, SORT_VNODE, a);
     }
     TRACED(TK_HRANK, sumV, 20.0 * sumV,
            launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), c.A, hkeys, hrank,
@@ -613,7 +625,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
                                  RADIX_BITS * p);
-      TRACED(TK_SORT_EDGE, N, 16.0 * N, launch_sort_pass(a, SORT_PLAIN, c.items, st));
+      TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, N, 0.0, SORT_EDGE, a);
     }
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
@@ -658,8 +670,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + RADIX_BITS * p);
-      TRACED(TK_SORT_IN, sumE, (p == 0 ? 20.0 : 16.0) * sumE,
-             launch_sort_pass(a, p == 0 ? SORT_IN_FIRST : SORT_PLAIN, c.items, st));
+      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, p == 0 ? 4.0 : 0.0,
+                  p == 0 ? SORT_IN_FIRST : SORT_IN, a);
     }
   }
   TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),

@@ -86,7 +86,15 @@ struct SortLaunch {
   uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
 };
 
-enum SortMode : int { SORT_PLAIN = 0, SORT_NODE_FIRST = 1, SORT_IN_FIRST = 2 };
+// Key source of a pass: the two first passes read their keys from elsewhere
+// (the node keys from the columns, the in-keys by repacking the out-keys);
+// the other values are plain passes, kept apart only so that each use of
+// the pass is its own kernel instantiation.
+enum SortMode : int {
+  SORT_PLAIN = 0, SORT_NODE_FIRST = 1, SORT_IN_FIRST = 2,
+  SORT_NODE = 3, SORT_VNODE = 4, SORT_EDGE = 5, SORT_IN = 6
+};
+enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2 };
 
 struct TileLaunch {
   const SegPlan *plan;
@@ -99,6 +107,9 @@ struct TileLaunch {
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s);
+// One part of a pass: SORT_PART_COUNT (digit counts of every tile and their
+// prefixes) or SORT_PART_SCATTER (the stable scatter), or both.
+hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts, hipStream_t s);
 int sort_tile(int items);
 int sort_resident_blocks(int items);
 int64_t sort_runs(int64_t tiles);

@@ -184,9 +184,17 @@ int ringo_gen_uniform_device(int64_t n, int64_t pool, uint64_t s_salt, uint64_t 
 
 __global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
                                                 uint4 *__restrict__ dst, int64_t words) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
-    dst[i] = src[i];
+  // four 16-byte loads per thread in flight before the stores
+  constexpr int U = 4;
+  const int64_t stride = (int64_t)gridDim.x * 256 * U;
+  for (int64_t i = (int64_t)blockIdx.x * 256 * U + threadIdx.x; i < words; i += stride) {
+    uint4 v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = src[std::min<int64_t>(i + j * 256, words - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (i + j * 256 < words) dst[i + j * 256] = v[j];
+  }
 }
 
 extern "C" int ringo_gen_copy_device(void *dst, const void *src, int64_t bytes,
@@ -195,7 +203,7 @@ extern "C" int ringo_gen_copy_device(void *dst, const void *src, int64_t bytes,
     return -1;
   const int64_t words = bytes / 16;
   if (words == 0) return 0;
-  int64_t g = std::min<int64_t>((words + 255) / 256, 256 * 16);
+  int64_t g = std::min<int64_t>((words + 1023) / 1024, 256 * 8);
   hipLaunchKernelGGL(k_copy16, dim3((unsigned)g), dim3(256), 0, stream, (const uint4 *)src,
                      (uint4 *)dst, words);
   return hipGetLastError() == hipSuccess ? 0 : -2;
