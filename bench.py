@@ -44,6 +44,8 @@ def log(*a):
 
 
 def kernel_source_file(kernel: str) -> str:
+    if kernel == "edge_table":
+        return "to_table.hip"
     return "hash.hip" if kernel.startswith("hash_") else "kernels.hip"
 
 
@@ -169,6 +171,79 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _device_table(spec, dev):
+    import torch
+    from paper_1503_07881_amd import workloads
+    src = torch.empty(spec.n, dtype=torch.int64, device=dev)
+    dst = torch.empty(spec.n, dtype=torch.int64, device=dev)
+    if spec.kind == "rmat" or (spec.ndup == 0 and not spec.shuffle):
+        workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    else:
+        hs, hd = workloads.generate_host(spec)
+        src.copy_(torch.from_numpy(hs))
+        dst.copy_(torch.from_numpy(hd))
+    return src, dst
+
+
+def _workload_name(spec) -> str:
+    return (f"{spec.kind}_scale{spec.scale}_rows{spec.n}" if spec.kind == "rmat"
+            else f"uniform_rows{spec.n}_pool{spec.pool}")
+
+
+def bench_to_table(args):
+    """Graph-to-table conversion: the edge table of the graph built from the
+    workload (edges/s = graph edges per second), one kernel per call."""
+    import numpy as np
+    import torch
+    from paper_1503_07881_amd import ringo, workloads
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = {1: workloads.config1, 2: workloads.config2, 3: workloads.config3}[args.config]()
+    src, dst = _device_table(spec, dev)
+    g = ringo.to_graph(src, dst)
+    del src, dst
+    V, E = g.num_nodes, g.num_edges
+    es = torch.empty(E, dtype=torch.int64, device=dev)
+    ed = torch.empty(E, dtype=torch.int64, device=dev)
+    raw = ringo.raw_of(g)
+    sh = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.warmup):
+        ringo.graph_to_edge_table_raw(raw, es.data_ptr(), ed.data_ptr(), sh)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        ringo.graph_to_edge_table_raw(raw, es.data_ptr(), ed.data_ptr(), sh)
+        b.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    nbytes = 36.0 * E + 8.0 * (V + 1)   # offsets, neighbours, two id reads and two id writes per edge
+    achieved = nbytes / (kms / 1e3) / 1e9
+    workload = _workload_name(spec)
+    out = {"metric": "edges/s converted (graph to edge table, 1 GPU)", "value": E / (ms / 1e3),
+           "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic (the graph of the seeded workload table)",
+           "config": {"workload": workload, "rows": spec.n, "nodes": V, "edges": E},
+           "roofline": {"bound": "hbm", "kernel": "edge_table", "rocprof_kernel": "k_edge_table",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                        "traffic": read_traffic("edge_table", workload),
+                        "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(kms, 5)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(g.node_ids.cpu().numpy(), g.out_offsets.cpu().numpy(), g.out_nbrs.cpu().numpy(),
+                          g.in_offsets.cpu().numpy(), g.in_nbrs.cpu().numpy())
+        t1 = time.perf_counter()
+        oracle.graph_to_edge_table(og)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": E / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole graph ({E:,} edges), numpy oracle, {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Served form: Poisson arrivals of conversion requests (rows log-uniform
     in [1e4, 5e7], uniform or R-MAT) from pinned host memory; p50/p99 latency
@@ -232,6 +307,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--op", default="to_graph", choices=("to_graph", "to_table"),
+                    help="to_graph: table-to-graph conversion (default); to_table: graph-to-table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -239,6 +316,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.op == "to_table":
+        bench_to_table(args)
+        return
     if args.config == 4:
         bench_batched(args)
         return

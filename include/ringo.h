@@ -110,6 +110,31 @@ ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *c
  * The caller must make sure no enqueued work still reads the arrays. */
 void ringo_graph_free(ringo_graph_t *g);
 
+/*
+ * Graph-to-table conversion (Section 2.4, "Conversion of graphs to tables";
+ * Table 5 times it for LiveJournal and Twitter2010).
+ *
+ * ringo_graph_to_edge_table writes the edge table of g: row i is
+ * (node_ids[u], node_ids[out_nbrs[i]]) for the i-th edge in out-CSR order,
+ * u being the edge's source; rows are therefore in ascending (source,
+ * destination) order, signed, with no duplicates.  For a graph made by
+ * ringo_table_to_graph this is the sorted distinct rows of the input table.
+ *   g                 : a graph (host struct, device arrays); only num_nodes,
+ *                       num_edges, node_ids, out_offsets and out_nbrs are read.
+ *   src_ids, dst_ids  : caller-allocated DEVICE arrays of g->num_edges int64.
+ * ringo_graph_to_node_table writes the node table of g: row v is
+ * (node_ids[v], out-degree of v, in-degree of v); each of the three DEVICE
+ * arrays of g->num_nodes int64 may be NULL to skip that column.
+ * Both are enqueued on `stream` without any synchronisation and allocate
+ * nothing.  Errors: RINGO_ERR_INVALID_ARG (NULL g, negative sizes, a needed
+ * array NULL), RINGO_ERR_HIP (launch failure).
+ */
+ringo_status_t ringo_graph_to_edge_table(const ringo_graph_t *g, int64_t *src_ids,
+                                         int64_t *dst_ids, hipStream_t stream);
+ringo_status_t ringo_graph_to_node_table(const ringo_graph_t *g, int64_t *node_ids,
+                                         int64_t *out_degree, int64_t *in_degree,
+                                         hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *ringo_status_string(ringo_status_t s);
 

@@ -9,6 +9,11 @@ its Python binding) never imports or calls it, and the two share no code.
 identifiers, and CSR out- and in-adjacency over dense node positions with
 each neighbour list strictly increasing.  See `oracle.cpp` for the steps and
 the readings taken where the paper is silent.
+
+`graph_to_edge_table(g)` and `graph_to_node_table(g)` are the inverse
+direction (Section 2.4, "Conversion of graphs to tables"): one output row per
+edge (visiting the nodes in order, and each node's out-neighbours in order)
+or per node (identifier, out-degree, in-degree).
 """
 from __future__ import annotations
 
@@ -93,3 +98,33 @@ def table_to_graph(src, dst, lib_path: str = LIB_PATH) -> Graph:
     finally:
         L.oracle_free(h)
     return g
+
+
+def graph_to_edge_table(g) -> tuple[np.ndarray, np.ndarray]:
+    """Edge table of a graph (Section 2.4, "Conversion of graphs to tables"):
+    for every node v in order and every out-neighbour w of v in order, the row
+    (id of v, id of w).  `g` has numpy (or array-like) node_ids, out_offsets
+    and out_nbrs."""
+    ids = np.asarray(g.node_ids, dtype=np.int64)
+    off = np.asarray(g.out_offsets, dtype=np.int64)
+    nbr = np.asarray(g.out_nbrs, dtype=np.int64)
+    V = ids.size
+    src_idx = np.repeat(np.arange(V, dtype=np.int64), np.diff(off)) if V else np.zeros(0, np.int64)
+    return ids[src_idx], ids[nbr]
+
+
+def graph_to_node_table(g) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Node table of a graph: identifier, out-degree and in-degree per node."""
+    ids = np.asarray(g.node_ids, dtype=np.int64)
+    return (ids.copy(), np.diff(np.asarray(g.out_offsets, dtype=np.int64)),
+            np.diff(np.asarray(g.in_offsets, dtype=np.int64)))
+
+
+def graph_to_edge_table_loops(g) -> tuple[list, list]:
+    """The same edge table written as two plain loops (small graphs only)."""
+    src, dst = [], []
+    for v in range(len(g.node_ids)):
+        for i in range(int(g.out_offsets[v]), int(g.out_offsets[v + 1])):
+            src.append(int(g.node_ids[v]))
+            dst.append(int(g.node_ids[int(g.out_nbrs[i])]))
+    return src, dst

@@ -36,6 +36,7 @@ EXPORTED_SYMBOLS = (
     "ringo_version", "ringo_trace_enable", "ringo_trace_read",
     "ringo_server_create", "ringo_server_submit", "ringo_server_poll", "ringo_server_release",
     "ringo_server_stats", "ringo_server_destroy",
+    "ringo_graph_to_edge_table", "ringo_graph_to_node_table",
 )
 
 
@@ -106,6 +107,10 @@ def lib() -> ctypes.CDLL:
         L.ringo_trace_read.restype = ctypes.c_int
         L.ringo_version.argtypes = []
         L.ringo_version.restype = ctypes.c_char_p
+        L.ringo_graph_to_edge_table.argtypes = [ctypes.POINTER(RawGraph), p, p, p]
+        L.ringo_graph_to_edge_table.restype = ctypes.c_int
+        L.ringo_graph_to_node_table.argtypes = [ctypes.POINTER(RawGraph), p, p, p, p]
+        L.ringo_graph_to_node_table.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -147,6 +152,18 @@ def table_to_graph_batched_raw(src_ptrs, dst_ptrs, num_rows, stream: int) -> lis
     outs = (RawGraph * k)()
     _check(lib().ringo_table_to_graph_batched(k, S, D, N, outs, stream), "ringo_table_to_graph_batched")
     return [outs[i] for i in range(k)]
+
+
+def graph_to_edge_table_raw(g: RawGraph, src_ptr: int, dst_ptr: int, stream: int) -> None:
+    """ringo_graph_to_edge_table into caller-allocated device arrays."""
+    _check(lib().ringo_graph_to_edge_table(ctypes.byref(g), src_ptr, dst_ptr, stream),
+           "ringo_graph_to_edge_table")
+
+
+def graph_to_node_table_raw(g: RawGraph, ids_ptr: int, out_deg_ptr: int, in_deg_ptr: int,
+                            stream: int) -> None:
+    _check(lib().ringo_graph_to_node_table(ctypes.byref(g), ids_ptr, out_deg_ptr, in_deg_ptr, stream),
+           "ringo_graph_to_node_table")
 
 
 def graph_free(g: RawGraph) -> None:
@@ -281,6 +298,36 @@ def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None) -> Graph:
     with torch.cuda.device(src.device):
         raw = table_to_graph_raw(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream))
     return _wrap(raw, src.device)
+
+
+def raw_of(g: Graph) -> RawGraph:
+    """A RawGraph struct over the tensors of `g` (it owns nothing)."""
+    r = RawGraph()
+    r.num_rows, r.num_nodes, r.num_edges = g.num_rows, g.num_nodes, g.num_edges
+    for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs"):
+        t = getattr(g, f)
+        setattr(r, f, t.data_ptr() if t.numel() else None)
+    return r
+
+
+def to_edge_table(g: Graph, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    """Graph-to-table conversion: the (src, dst) identifier columns of the
+    graph's edges in ascending (src, dst) order."""
+    dev = g.out_offsets.device
+    src = torch.empty(g.num_edges, dtype=torch.int64, device=dev)
+    dst = torch.empty(g.num_edges, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        graph_to_edge_table_raw(raw_of(g), src.data_ptr(), dst.data_ptr(), _stream_handle(stream))
+    return src, dst
+
+
+def to_node_table(g: Graph, stream=None) -> tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """The node table: identifiers, out-degrees and in-degrees."""
+    dev = g.out_offsets.device
+    cols = [torch.empty(g.num_nodes, dtype=torch.int64, device=dev) for _ in range(3)]
+    with torch.cuda.device(dev):
+        graph_to_node_table_raw(raw_of(g), *(c.data_ptr() for c in cols), _stream_handle(stream))
+    return tuple(cols)
 
 
 def to_graph_batched(srcs, dsts, stream=None) -> list[Graph]:

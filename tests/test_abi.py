@@ -53,6 +53,16 @@ def test_invalid_arguments_rejected_on_host():
     assert L.ringo_table_to_graph_batched(0, None, None, None, None, None) == 0
     ringo.graph_free(g)  # zeroed struct: no-op
     L.ringo_graph_free(None)
+    # graph to table: checked on the host, nothing launched
+    assert L.ringo_graph_to_edge_table(None, None, None, None) == 1
+    assert L.ringo_graph_to_node_table(None, None, None, None, None) == 1
+    g.num_nodes, g.num_edges = 3, 5
+    assert L.ringo_graph_to_edge_table(ctypes.byref(g), None, None, None) == 1
+    g.num_edges = -1
+    assert L.ringo_graph_to_edge_table(ctypes.byref(g), None, None, None) == 1
+    g.num_nodes, g.num_edges = 0, 0
+    assert L.ringo_graph_to_edge_table(ctypes.byref(g), None, None, None) == 0
+    assert L.ringo_graph_to_node_table(ctypes.byref(g), None, None, None, None) == 0
 
 
 def test_tune_schedule_roundtrip():
