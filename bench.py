@@ -244,6 +244,60 @@ def bench_to_table(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_pagerank(args):
+    """PageRank, ten iterations (the count the paper times), on the graph of
+    the workload; value = edges x iterations per second."""
+    import torch
+    from paper_1503_07881_amd import ringo, workloads
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = {1: workloads.config1, 2: workloads.config2, 3: workloads.config3}[args.config]()
+    src, dst = _device_table(spec, dev)
+    g = ringo.to_graph(src, dst)
+    del src, dst
+    V, E, iters = g.num_nodes, g.num_edges, 10
+    ranks = torch.empty(V, dtype=torch.float64, device=dev)
+    raw = ringo.raw_of(g)
+    sh = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.warmup):
+        ringo.pagerank_raw(raw, 0.85, iters, ranks.data_ptr(), sh)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        ringo.pagerank_raw(raw, 0.85, iters, ranks.data_ptr(), sh)
+        b.record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    # per iteration: in-neighbour index + gathered contribution per edge; per
+    # node the two offsets, the rank, the contribution (written, then read) and
+    # the new rank
+    nbytes = iters * (12.0 * E + 48.0 * V)
+    achieved = nbytes / (kms / 1e3) / 1e9
+    workload = _workload_name(spec)
+    out = {"metric": "PageRank edge-iterations/s (10 iterations, fp64, 1 GPU)", "value": E * iters / (ms / 1e3),
+           "unit": "edges*iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (the graph of the seeded workload table)",
+           "config": {"workload": workload, "rows": spec.n, "nodes": V, "edges": E, "iterations": iters,
+                      "damping": 0.85},
+           "roofline": {"bound": "hbm", "kernel": "pagerank_10_iterations", "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                        "traffic": None, "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(kms, 5)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(g.node_ids.cpu().numpy(), g.out_offsets.cpu().numpy(), g.out_nbrs.cpu().numpy(),
+                          g.in_offsets.cpu().numpy(), g.in_nbrs.cpu().numpy())
+        t1 = time.perf_counter()
+        oracle.pagerank(og, 0.85, iters)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": E * iters / dt, "unit": "edges*iterations/s", "cores": 1,
+                               "kind": "oracle", "sample": f"the whole graph, 10 iterations, numpy oracle, {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Served form: Poisson arrivals of conversion requests (rows log-uniform
     in [1e4, 5e7], uniform or R-MAT) from pinned host memory; p50/p99 latency
@@ -307,8 +361,9 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--op", default="to_graph", choices=("to_graph", "to_table"),
-                    help="to_graph: table-to-graph conversion (default); to_table: graph-to-table")
+    ap.add_argument("--op", default="to_graph", choices=("to_graph", "to_table", "pagerank"),
+                    help="to_graph: table-to-graph conversion (default); to_table: graph-to-table; "
+                         "pagerank: ten PageRank iterations on the converted graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -318,6 +373,9 @@ def main():
 
     if args.op == "to_table":
         bench_to_table(args)
+        return
+    if args.op == "pagerank":
+        bench_pagerank(args)
         return
     if args.config == 4:
         bench_batched(args)

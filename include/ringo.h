@@ -135,6 +135,26 @@ ringo_status_t ringo_graph_to_node_table(const ringo_graph_t *g, int64_t *node_i
                                          int64_t *out_degree, int64_t *in_degree,
                                          hipStream_t stream);
 
+/*
+ * PageRank of a graph (the paper's workflow computes it on a converted graph,
+ * Section 4; Table 3 times ten iterations).  Page, Brin, Motwani & Winograd's
+ * definition, in fp64, with the teleport and the rank of nodes without
+ * out-edges spread uniformly over all nodes:
+ *   r_0[v] = 1/V;  r_{t+1}[v] = (1-d)/V + d * (sum over edges u->v of
+ *   r_t[u]/outdeg(u) + (sum of r_t[u] over nodes without out-edges)/V).
+ *   g          : a graph; num_nodes, num_edges, out_offsets, in_offsets and
+ *                in_nbrs are read (in-CSR pull, out-degrees from out_offsets).
+ *   damping    : d in [0, 1] (0.85 is the usual value).
+ *   iterations : t >= 0; the result is r_t.
+ *   ranks      : caller-allocated DEVICE array of num_nodes doubles.
+ * Enqueued on `stream`; stream-ordered workspace from the library's
+ * allocator, released in stream order.  Results are deterministic (fixed
+ * summation order).  Errors: RINGO_ERR_INVALID_ARG, RINGO_ERR_OUT_OF_MEMORY,
+ * RINGO_ERR_HIP.
+ */
+ringo_status_t ringo_pagerank(const ringo_graph_t *g, double damping, int32_t iterations,
+                              double *ranks, hipStream_t stream);
+
 /* Static, human-readable name of a status code. */
 const char *ringo_status_string(ringo_status_t s);
 

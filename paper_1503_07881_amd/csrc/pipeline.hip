@@ -844,3 +844,16 @@ int ringo_trace_read(ringo_trace_entry_t *out, int max_entries) {
 const char *ringo_version(void) { return "ringo-mi355x 0.1 (gfx950)"; }
 
 }  // extern "C"
+
+// ------------------------------------------------ workspace for other entry points
+
+namespace ringo {
+
+void *workspace_alloc(size_t bytes, hipStream_t s) {
+  prepare_pool();
+  return dev_alloc(hooks(), bytes, s);
+}
+
+void workspace_free(void *p, hipStream_t s) { dev_free(hooks(), p, s); }
+
+}  // namespace ringo

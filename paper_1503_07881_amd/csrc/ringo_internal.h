@@ -167,4 +167,10 @@ hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, int grid, hipS
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
 int device_cu_count();
 
+// Stream-ordered device memory from the library's allocator (the caller's
+// hooks when set, else the device pool); used by the entry points other than
+// the conversion itself.
+void *workspace_alloc(size_t bytes, hipStream_t s);
+void workspace_free(void *p, hipStream_t s);
+
 }  // namespace ringo

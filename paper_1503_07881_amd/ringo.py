@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "ringo_version", "ringo_trace_enable", "ringo_trace_read",
     "ringo_server_create", "ringo_server_submit", "ringo_server_poll", "ringo_server_release",
     "ringo_server_stats", "ringo_server_destroy",
-    "ringo_graph_to_edge_table", "ringo_graph_to_node_table",
+    "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
 )
 
 
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
         L.ringo_graph_to_edge_table.restype = ctypes.c_int
         L.ringo_graph_to_node_table.argtypes = [ctypes.POINTER(RawGraph), p, p, p, p]
         L.ringo_graph_to_node_table.restype = ctypes.c_int
+        L.ringo_pagerank.argtypes = [ctypes.POINTER(RawGraph), ctypes.c_double, ctypes.c_int32, p, p]
+        L.ringo_pagerank.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -164,6 +166,10 @@ def graph_to_node_table_raw(g: RawGraph, ids_ptr: int, out_deg_ptr: int, in_deg_
                             stream: int) -> None:
     _check(lib().ringo_graph_to_node_table(ctypes.byref(g), ids_ptr, out_deg_ptr, in_deg_ptr, stream),
            "ringo_graph_to_node_table")
+
+
+def pagerank_raw(g: RawGraph, damping: float, iterations: int, ranks_ptr: int, stream: int) -> None:
+    _check(lib().ringo_pagerank(ctypes.byref(g), damping, iterations, ranks_ptr, stream), "ringo_pagerank")
 
 
 def graph_free(g: RawGraph) -> None:
@@ -328,6 +334,15 @@ def to_node_table(g: Graph, stream=None) -> tuple[torch.Tensor, torch.Tensor, to
     with torch.cuda.device(dev):
         graph_to_node_table_raw(raw_of(g), *(c.data_ptr() for c in cols), _stream_handle(stream))
     return tuple(cols)
+
+
+def pagerank(g: Graph, damping: float = 0.85, iterations: int = 10, stream=None) -> torch.Tensor:
+    """PageRank scores (fp64) of every node after `iterations` iterations."""
+    dev = g.out_offsets.device
+    ranks = torch.empty(g.num_nodes, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        pagerank_raw(raw_of(g), damping, iterations, ranks.data_ptr(), _stream_handle(stream))
+    return ranks
 
 
 def to_graph_batched(srcs, dsts, stream=None) -> list[Graph]:

@@ -63,6 +63,13 @@ def test_invalid_arguments_rejected_on_host():
     g.num_nodes, g.num_edges = 0, 0
     assert L.ringo_graph_to_edge_table(ctypes.byref(g), None, None, None) == 0
     assert L.ringo_graph_to_node_table(ctypes.byref(g), None, None, None, None) == 0
+    # pagerank: argument checks on the host
+    assert L.ringo_pagerank(None, ctypes.c_double(0.85), 10, None, None) == 1
+    assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(0.85), 10, None, None) == 0  # V = 0
+    g.num_nodes = 4
+    assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(0.85), 10, None, None) == 1
+    assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(1.5), 10, None, None) == 1
+    assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(0.85), -2, None, None) == 1
 
 
 def test_tune_schedule_roundtrip():
