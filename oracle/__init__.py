@@ -77,6 +77,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         L.oracle_copy.restype = None
         L.oracle_free.argtypes = [p]
         L.oracle_free.restype = None
+        L.oracle_table_to_graph_kind.argtypes = [p, p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_table_to_graph_kind.restype = ctypes.c_int
+        L.oracle_copy_eids.argtypes = [p, p, p]
+        L.oracle_copy_eids.restype = None
         _libs[path] = L
     return _libs[path]
 
@@ -99,6 +104,47 @@ def table_to_graph(src, dst, lib_path: str = LIB_PATH) -> Graph:
                   np.empty(V.value + 1, np.int64), np.empty(E.value, np.int32))
         L.oracle_copy(h, g.node_ids.ctypes.data, g.out_offsets.ctypes.data, g.out_nbrs.ctypes.data,
                       g.in_offsets.ctypes.data, g.in_nbrs.ctypes.data)
+    finally:
+        L.oracle_free(h)
+    return g
+
+
+DIRECTED, UNDIRECTED, MULTIGRAPH = 0, 1, 2
+
+
+@dataclass
+class MultiGraph(Graph):
+    out_eids: np.ndarray = None  # int32 [E] row index of each out-list entry
+    in_eids: np.ndarray = None   # int32 [E] row index of each in-list entry
+
+
+def table_to_graph_kind(src, dst, kind: int, lib_path: str = LIB_PATH) -> Graph:
+    """The conversion for one graph kind: DIRECTED (as table_to_graph),
+    UNDIRECTED (adjacency = distinct neighbours over both orientations; the
+    in-arrays equal the out-arrays) or MULTIGRAPH (every row an edge, lists
+    ordered by (neighbour, row), with the row index of every entry)."""
+    src = np.ascontiguousarray(src, dtype=np.int64)
+    dst = np.ascontiguousarray(dst, dtype=np.int64)
+    if src.shape != dst.shape or src.ndim != 1:
+        raise ValueError("src and dst must be 1-D arrays of equal length")
+    L = load(lib_path)
+    h = ctypes.c_void_p()
+    V = ctypes.c_int64()
+    E = ctypes.c_int64()
+    rc = L.oracle_table_to_graph_kind(src.ctypes.data, dst.ctypes.data, src.size, kind, ctypes.byref(h),
+                                      ctypes.byref(V), ctypes.byref(E))
+    if rc != 0:
+        raise OracleError({1: "invalid argument", 2: "too many nodes", 3: "out of memory"}.get(rc, str(rc)))
+    try:
+        arrays = (np.empty(V.value, np.int64), np.empty(V.value + 1, np.int64), np.empty(E.value, np.int32),
+                  np.empty(V.value + 1, np.int64), np.empty(E.value, np.int32))
+        g = MultiGraph(*arrays) if kind == MULTIGRAPH else Graph(*arrays)
+        L.oracle_copy(h, g.node_ids.ctypes.data, g.out_offsets.ctypes.data, g.out_nbrs.ctypes.data,
+                      g.in_offsets.ctypes.data, g.in_nbrs.ctypes.data)
+        if kind == MULTIGRAPH:
+            g.out_eids = np.empty(E.value, np.int32)
+            g.in_eids = np.empty(E.value, np.int32)
+            L.oracle_copy_eids(h, g.out_eids.ctypes.data, g.in_eids.ctypes.data)
     finally:
         L.oracle_free(h)
     return g

@@ -28,6 +28,15 @@
 //
 // Parity: pinned by hand-worked fixtures, brute force over Python sets,
 // an independent numpy/scipy route, closed forms and invariants (tests/).
+//
+// Two further graph kinds (oracle_table_to_graph_kind), the same definition
+// with another edge rule (the paper limits its discussion to directed graphs,
+// Section 2.4; these are the readings taken for the other two):
+//   * undirected: the adjacency of v is the set of w with a row (v, w) or
+//     (w, v), ascending; a self-loop appears once; the in-direction is the
+//     out-direction.
+//   * multigraph: every row is its own edge, identified by its row index;
+//     out-lists ascend by (destination, row), in-lists by (source, row).
 
 #include <stdint.h>
 
@@ -42,7 +51,31 @@ struct OracleGraph {
   std::vector<int64_t> nodes;
   std::vector<int64_t> out_off, in_off;
   std::vector<int32_t> out_nbr, in_nbr;
+  std::vector<int32_t> out_eid, in_eid;  // multigraph only
 };
+
+struct Triple {
+  int32_t owner, nbr, row;
+  bool operator<(const Triple &o) const {
+    if (owner != o.owner) return owner < o.owner;
+    if (nbr != o.nbr) return nbr < o.nbr;
+    return row < o.row;
+  }
+};
+
+// Offsets, neighbour list and row list of one direction from sorted triples.
+void build_direction_rows(const std::vector<Triple> &t, int64_t V, std::vector<int64_t> &off,
+                          std::vector<int32_t> &nbr, std::vector<int32_t> &eid) {
+  off.assign((size_t)V + 1, 0);
+  for (const auto &x : t) off[(size_t)x.owner + 1] += 1;
+  for (size_t v = 1; v < off.size(); ++v) off[v] += off[v - 1];
+  nbr.resize(t.size());
+  eid.resize(t.size());
+  for (size_t i = 0; i < t.size(); ++i) {
+    nbr[i] = t[i].nbr;
+    eid[i] = t[i].row;
+  }
+}
 
 // Offsets and neighbour list of one direction from (owner, neighbour) pairs
 // that are already sorted and distinct: count the neighbours of each node,
@@ -114,6 +147,71 @@ void oracle_copy(const void *handle, int64_t *nodes, int64_t *out_off, int32_t *
   std::copy(g->out_nbr.begin(), g->out_nbr.end(), out_nbr);
   std::copy(g->in_off.begin(), g->in_off.end(), in_off);
   std::copy(g->in_nbr.begin(), g->in_nbr.end(), in_nbr);
+}
+
+// kind 0: as oracle_table_to_graph; 1: undirected; 2: multigraph (see the
+// header).  Same return codes.
+int oracle_table_to_graph_kind(const int64_t *src, const int64_t *dst, int64_t n, int kind,
+                               void **handle, int64_t *num_nodes, int64_t *num_edges) {
+  if (kind == 0) return oracle_table_to_graph(src, dst, n, handle, num_nodes, num_edges);
+  if (kind != 1 && kind != 2) return 1;
+  if (!handle || !num_nodes || !num_edges || n < 0 || n > INT32_MAX) return 1;
+  if (n > 0 && (!src || !dst)) return 1;
+  *handle = nullptr;
+  try {
+    OracleGraph *g = new OracleGraph();
+    std::vector<int64_t> ids(src, src + n);
+    ids.insert(ids.end(), dst, dst + n);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    g->nodes.swap(ids);
+    const int64_t V = (int64_t)g->nodes.size();
+    if (V > INT32_MAX) {
+      delete g;
+      return 2;
+    }
+    auto index_of = [&](int64_t id) {
+      return (int32_t)(std::lower_bound(g->nodes.begin(), g->nodes.end(), id) - g->nodes.begin());
+    };
+    if (kind == 1) {
+      // both orientations of every row, sorted, repeats removed
+      std::vector<std::pair<int32_t, int32_t>> both;
+      both.reserve((size_t)2 * n);
+      for (int64_t r = 0; r < n; ++r) {
+        const int32_t s = index_of(src[r]), d = index_of(dst[r]);
+        both.push_back({s, d});
+        both.push_back({d, s});
+      }
+      std::sort(both.begin(), both.end());
+      both.erase(std::unique(both.begin(), both.end()), both.end());
+      build_direction(both, V, g->out_off, g->out_nbr);
+      g->in_off = g->out_off;
+      g->in_nbr = g->out_nbr;
+      *num_edges = (int64_t)both.size();
+    } else {
+      // every row an edge: (source, destination, row), then (destination, source, row)
+      std::vector<Triple> t3((size_t)n);
+      for (int64_t r = 0; r < n; ++r) t3[(size_t)r] = {index_of(src[r]), index_of(dst[r]), (int32_t)r};
+      std::sort(t3.begin(), t3.end());
+      build_direction_rows(t3, V, g->out_off, g->out_nbr, g->out_eid);
+      for (auto &x : t3) std::swap(x.owner, x.nbr);
+      std::sort(t3.begin(), t3.end());
+      build_direction_rows(t3, V, g->in_off, g->in_nbr, g->in_eid);
+      *num_edges = n;
+    }
+    *num_nodes = V;
+    *handle = g;
+    return 0;
+  } catch (const std::bad_alloc &) {
+    return 3;
+  }
+}
+
+// Multigraph row indices (arrays of E), after oracle_table_to_graph_kind(2).
+void oracle_copy_eids(const void *handle, int32_t *out_eid, int32_t *in_eid) {
+  const OracleGraph *g = (const OracleGraph *)handle;
+  std::copy(g->out_eid.begin(), g->out_eid.end(), out_eid);
+  std::copy(g->in_eid.begin(), g->in_eid.end(), in_eid);
 }
 
 void oracle_free(void *handle) { delete (OracleGraph *)handle; }
