@@ -54,10 +54,30 @@ typedef enum {
 #define RINGO_MAX_NODES ((int64_t)2147483647)
 
 /*
+ * Graph kinds.  The paper discusses directed graphs (Section 2.4) and
+ * defines the conversion for them; the other two kinds apply the same
+ * definition with another edge rule:
+ *   RINGO_GRAPH_DIRECTED   E is the set of distinct (src, dst) pairs
+ *                          (a simple directed graph; self-loops kept).
+ *   RINGO_GRAPH_UNDIRECTED the adjacency of v is the set of w with a row
+ *                          (v, w) or (w, v), ascending; a self-loop appears
+ *                          once.  num_edges is the number of adjacency
+ *                          entries (each non-loop pair counts twice), and
+ *                          the in-arrays are the out-arrays (same pointers).
+ *   RINGO_GRAPH_MULTI      every row is its own edge (num_edges = num_rows),
+ *                          identified by its row index: out-lists ascend by
+ *                          (destination, row), in-lists by (source, row),
+ *                          and out_eids / in_eids give each entry's row.
+ */
+#define RINGO_GRAPH_DIRECTED 0
+#define RINGO_GRAPH_UNDIRECTED 1
+#define RINGO_GRAPH_MULTI 2
+
+/*
  * The converted graph (Section 2.4).  Scalars are host values, valid when
  * the call returns; arrays are device memory owned by the library, valid
  * once the stream passed to the call has completed, released with
- * ringo_graph_free.
+ * ringo_graph_free.  (Field comments describe the directed kind.)
  */
 typedef struct {
   int64_t num_rows;     /* n: rows of the input table                          */
@@ -70,6 +90,10 @@ typedef struct {
   int64_t *in_offsets;  /* [V+1] in_offsets[0] = 0, in_offsets[V] = E          */
   int32_t *in_nbrs;     /* [E]   in-neighbours, strictly increasing            */
   void *_alloc;         /* opaque owner of the arrays                          */
+  int32_t kind;         /* RINGO_GRAPH_*                                       */
+  int32_t _reserved;
+  int32_t *out_eids;    /* [E]   RINGO_GRAPH_MULTI: row of each out-entry      */
+  int32_t *in_eids;     /* [E]   RINGO_GRAPH_MULTI: row of each in-entry       */
 } ringo_graph_t;
 
 /*
@@ -105,6 +129,21 @@ ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int6
 ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,
                                             const int64_t *const *dst, const int64_t *num_rows,
                                             ringo_graph_t *outs, hipStream_t stream);
+
+/*
+ * The conversion for any graph kind (RINGO_GRAPH_*; ringo_table_to_graph and
+ * ringo_table_to_graph_batched are the RINGO_GRAPH_DIRECTED cases).  Same
+ * arguments, ownership and errors, plus RINGO_ERR_INVALID_ARG for an unknown
+ * kind.  Undirected graphs sort both orientations of every row (2n edge
+ * keys) and have no separate in-direction; multigraphs carry every row's
+ * index through the edge sorts and keep every row.
+ */
+ringo_status_t ringo_table_to_graph_ex(const int64_t *src, const int64_t *dst, int64_t num_rows,
+                                       int32_t kind, ringo_graph_t *out, hipStream_t stream);
+ringo_status_t ringo_table_to_graph_batched_ex(int32_t num_tables, const int64_t *const *src,
+                                               const int64_t *const *dst, const int64_t *num_rows,
+                                               int32_t kind, ringo_graph_t *outs,
+                                               hipStream_t stream);
 
 /* Releases the arrays of a graph and zeroes *g.  Idempotent; NULL is a no-op.
  * The caller must make sure no enqueued work still reads the arrays. */

@@ -332,7 +332,8 @@ hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
 // ---------------------------------------------------------------- remap
 
 __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t *slots,
-                                                    const uint32_t *hrank, uint64_t *ekeys) {
+                                                    const uint32_t *hrank, uint64_t *ekeys,
+                                                    int sym) {
   const int tid = threadIdx.x;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
@@ -359,16 +360,21 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
         if (r0 + j * 256 < end) {
           const uint32_t rs = q[j] == NO_SLOT ? last : rk[j];
           const uint32_t rd = q[U + j] == NO_SLOT ? last : rk[U + j];
-          G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+          if (sym) {  // both orientations, 2n keys at 2 * row_off
+            G(ekeys)[2 * P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+            G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rd << b) | rs;
+          } else {
+            G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+          }
         }
     }
   }
 }
 
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
-                             uint64_t *ekeys, int grid, hipStream_t s) {
+                             uint64_t *ekeys, int sym, int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_remap, dim3(grid), dim3(256), 0, s, rows, slots, hrank, ekeys);
+  hipLaunchKernelGGL(k_hash_remap, dim3(grid), dim3(256), 0, s, rows, slots, hrank, ekeys, sym);
   return hipGetLastError();
 }
 

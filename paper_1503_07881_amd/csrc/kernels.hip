@@ -182,7 +182,7 @@ __device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan 
     // one load from a selected pointer: no branch, so loads stay in flight
     const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? G(P.src) + e : G(P.dst) + (e - P.n);
     return (uint64_t)*ptr ^ SIGN_FLIP;
-  } else if (MODE == SORT_IN_FIRST) {
+  } else if (MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV) {
     const uint64_t x = G(a.in)[start + e];
     const uint64_t d = x & ((1ull << P.b) - 1);
     return (d << 32) | (x >> P.b);
@@ -331,8 +331,11 @@ template <int BLOCK, int ITEMS, int MODE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(ITEMS), 8))) void k_downsweep(SortLaunch a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
+  constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV;
+  constexpr bool IN_FIRST = MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV;
   static_assert(BLOCK >= RADIX, "one thread per digit");
   __shared__ uint64_t s_stage[TILE];
+  __shared__ uint32_t s_vstage[KV ? TILE : 1];
   __shared__ uint32_t s_whist[WAVES * RADIX];
   __shared__ uint32_t s_lstart[RADIX];
   __shared__ int64_t s_goff[RADIX];
@@ -371,18 +374,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     // are unconditional so that all of them are in flight before the first
     // wait.
     uint64_t keys[ITEMS];
+    uint32_t vals[KV ? ITEMS : 1];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
       keys[i] = pass_key<MODE>(a, H.P, H.start, base + (idx < cnt ? idx : 0));
+      if (KV) vals[KV ? i : 0] = G(a.vin)[H.start + base + (idx < cnt ? idx : 0)];
     }
-    if (MODE == SORT_IN_FIRST) {
-      // out-neighbours, already in (s, d) order; stored after all loads are
-      // issued so that no load waits for another
+    if (IN_FIRST) {
+      // out-neighbours (and multigraph rows), already in (s, d) order; stored
+      // after all loads are issued so that no load waits for another
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) {
         const int idx = wave * (ITEMS * 64) + i * 64 + lane;
-        if (idx < cnt) G(H.P.out_nbr)[base + idx] = (int32_t)(uint32_t)(keys[i] >> 32);
+        if (idx < cnt) {
+          G(H.P.out_nbr)[base + idx] = (int32_t)(uint32_t)(keys[i] >> 32);
+          if (KV) G(H.P.out_eid)[base + idx] = (int32_t)vals[KV ? i : 0];
+        }
       }
     }
     const uint32_t tprefix = tid < RADIX ? a.counts[tile * RADIX + tid] : 0u;
@@ -435,7 +443,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     for (int i = 0; i < ITEMS; ++i) {
       if (wave * (ITEMS * 64) + i * 64 + lane < cnt) {
         const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
-        s_stage[s_lstart[d] + s_whist[wave * RADIX + d] + rank[i]] = keys[i];
+        const uint32_t slot = s_lstart[d] + s_whist[wave * RADIX + d] + rank[i];
+        s_stage[slot] = keys[i];
+        if (KV) s_vstage[KV ? slot : 0] = vals[KV ? i : 0];
       }
     }
     __syncthreads();
@@ -448,7 +458,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       if (p < cnt) {
         const uint64_t k = s_stage[p];
         const int64_t pos = s_goff[(uint32_t)(k >> shift) & (RADIX - 1)] + p;
-        if ((uint64_t)(pos - H.start) < (uint64_t)H.count) G(a.out)[pos] = k;  // in range by construction
+        if ((uint64_t)(pos - H.start) < (uint64_t)H.count) {  // in range by construction
+          G(a.out)[pos] = k;
+          if (KV) G(a.vout)[pos] = s_vstage[KV ? p : 0];
+        }
       }
     }
     for (int i = tid; i < WAVES * RADIX; i += BLOCK) s_whist[i] = 0;
@@ -528,6 +541,9 @@ static hipError_t launch_pass_items(const SortLaunch &a, int mode, int parts, hi
     case SORT_VNODE: return launch_pass_t<ITEMS, SORT_VNODE>(a, parts, s);
     case SORT_EDGE: return launch_pass_t<ITEMS, SORT_EDGE>(a, parts, s);
     case SORT_IN: return launch_pass_t<ITEMS, SORT_IN>(a, parts, s);
+    case SORT_EDGE_KV: return launch_pass_t<ITEMS, SORT_EDGE_KV>(a, parts, s);
+    case SORT_IN_FIRST_KV: return launch_pass_t<ITEMS, SORT_IN_FIRST_KV>(a, parts, s);
+    case SORT_IN_KV: return launch_pass_t<ITEMS, SORT_IN_KV>(a, parts, s);
     default: return launch_pass_t<ITEMS, SORT_PLAIN>(a, parts, s);
   }
 }
@@ -751,7 +767,7 @@ __device__ __forceinline__ void node_rank_n(const uint64_t *nd, const DirEntry *
 }
 
 __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nodes,
-                                               const DirEntry *dir, uint64_t *ekeys) {
+                                               const DirEntry *dir, uint64_t *ekeys, int sym) {
   const int tid = threadIdx.x;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
@@ -777,16 +793,22 @@ __global__ __launch_bounds__(256) void k_remap(TileLaunch t, const uint64_t *nod
       node_rank_n<2 * U>(nd, D, lo, shift, nb, u, rk);
 #pragma unroll
       for (int j = 0; j < U; ++j)
-        if (r0 + j * 256 < end)
-          G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rk[j] << b) | rk[U + j];
+        if (r0 + j * 256 < end) {
+          if (sym) {
+            G(ekeys)[2 * P.row_off + r0 + j * 256] = ((uint64_t)rk[j] << b) | rk[U + j];
+            G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rk[U + j] << b) | rk[j];
+          } else {
+            G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rk[j] << b) | rk[U + j];
+          }
+        }
     }
   }
 }
 
 hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEntry *dir,
-                        uint64_t *ekeys, int grid, hipStream_t s) {
+                        uint64_t *ekeys, int sym, int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys);
+  hipLaunchKernelGGL(k_remap, dim3(grid), dim3(256), 0, s, t, nodes, dir, ekeys, sym);
   return hipGetLastError();
 }
 
@@ -799,7 +821,7 @@ hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEnt
 __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint64_t *in,
                                                        uint64_t *out, int64_t *seg_count,
                                                        uint64_t *status, uint32_t *counter,
-                                                       uint32_t epoch) {
+                                                       uint32_t epoch, int keep_all) {
   constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
   __shared__ uint64_t s_k[TILE];
   __shared__ uint32_t s_cnt[64];
@@ -819,8 +841,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
     const SegPlan P = t.plan[seg];
     const int64_t first = t.tmap[seg];
     const int64_t base = (tile - first) * (int64_t)TILE;
-    const int64_t start = P.row_off;
-    const int64_t count = P.n;
+    const int64_t start = range_start(P, t.range_kind);
+    const int64_t count = range_count(P, t.range_kind);
     const int cnt = (int)std::min<int64_t>(TILE, count - base);
     const int b = P.b;
     for (int i = 0; i < ITEMS; ++i) {
@@ -836,7 +858,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
       bool h = false;
       if (idx < cnt) {
         const uint64_t k = s_k[idx];
-        h = (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
+        h = keep_all || (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
       }
       heads[i] = __ballot(h);
       if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
@@ -884,10 +906,10 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
 
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
-                         uint32_t epoch, int grid, hipStream_t s) {
+                         uint32_t epoch, int keep_all, int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_dedupe, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count,
-                     status, counter, epoch);
+                     status, counter, epoch, keep_all);
   return hipGetLastError();
 }
 
@@ -896,7 +918,8 @@ hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
 // The unique edges sorted by (d, s): in-neighbours are the low words, and
 // in_off[v] is the position of the first edge whose destination is >= v.
 
-__global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in) {
+__global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in,
+                                                const uint32_t *vals) {
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
@@ -906,6 +929,7 @@ __global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in
     for (int64_t j = base + threadIdx.x; j < end; j += 256) {
       const uint64_t k = K[j];
       G(P.in_nbr)[j] = (int32_t)(uint32_t)k;
+      if (vals) G(P.in_eid)[j] = (int32_t)G(vals)[P.row_off + j];
       const int64_t h = std::min<int64_t>((int64_t)(k >> 32), P.V - 1);
       const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(K[j - 1] >> 32), P.V - 1);
       for (int64_t v = hp + 1; v <= h; ++v) G(P.in_off)[v] = j;
@@ -915,9 +939,50 @@ __global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in
   }
 }
 
-hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s) {
+hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, const uint32_t *vals, int grid,
+                         hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_in_csr, dim3(grid), dim3(256), 0, s, t, in);
+  hipLaunchKernelGGL(k_in_csr, dim3(grid), dim3(256), 0, s, t, in, vals);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- undirected / multigraph
+//
+// Undirected graphs: the unique keys of both orientations are the adjacency
+// (in (v, w) order), so the neighbours are their low b bits.
+__global__ __launch_bounds__(256) void k_out_nbr(TileLaunch t, const uint64_t *in) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint64_t *K = in + range_start(P, t.range_kind);
+    const uint64_t mask = (1ull << P.b) - 1;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
+    const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.E);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256)
+      G(P.out_nbr)[j] = (int32_t)(uint32_t)(G(K)[j] & mask);
+  }
+}
+
+hipError_t launch_out_nbr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_out_nbr, dim3(grid), dim3(256), 0, s, t, in);
+  return hipGetLastError();
+}
+
+// Multigraph: every edge starts out as its row.
+__global__ __launch_bounds__(256) void k_iota(TileLaunch t, uint32_t *v) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    for (int64_t r = base + threadIdx.x; r < end; r += 256) G(v)[P.row_off + r] = (uint32_t)r;
+  }
+}
+
+hipError_t launch_iota(const TileLaunch &rows, uint32_t *v, int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(grid), dim3(256), 0, s, rows, v);
   return hipGetLastError();
 }
 

@@ -215,6 +215,8 @@ struct Call {
   DirEntry *dir = nullptr;
   void *tab = nullptr;    // node hash tables: keys, then ranks
   uint32_t *hslots = nullptr;  // slot of every node key
+  uint32_t *vals = nullptr;    // multigraph: rows carried through the sorts (2 x N)
+  int kind = RINGO_GRAPH_DIRECTED;
   void *hmeta = nullptr;  // estimate registers, slot counts and flags of the hash tables
   uint32_t *counts = nullptr;
   uint32_t *bsum = nullptr;
@@ -228,10 +230,11 @@ struct Call {
 
   void release_workspace() {
     void *bufs[] = {A, B, status, base, counters, results, meta, dir, tab, hslots, hmeta, counts,
-                    bsum};
+                    bsum, vals};
     for (void *b : bufs) dev_free(hooks, b, stream);
     tab = nullptr;
     hslots = nullptr;
+    vals = nullptr;
     hmeta = nullptr;
     A = B = nullptr;
     status = nullptr;
@@ -308,6 +311,8 @@ struct Call {
     a.digit_base = base;
     a.counts = counts;
     a.bsum = bsum;
+    a.vin = nullptr;
+    a.vout = nullptr;
     return a;
   }
 };
@@ -593,8 +598,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   const int P_in = (b_max + RADIX_BITS - 1) / RADIX_BITS;
   c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
   c.set_tiles(TM_VSORT, RANGE_NODES, c.sort_tile);
-  c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
-  c.set_tiles(TM_DEDUP, RANGE_ROWS, SCAN_TILE);
+  // edge keys: n per table at row_off, or both orientations (2n at
+  // 2 row_off) for undirected graphs
+  const bool undirected = c.kind == RINGO_GRAPH_UNDIRECTED, multi = c.kind == RINGO_GRAPH_MULTI;
+  const int erange = undirected ? RANGE_NODE_KEYS : RANGE_ROWS;
+  const int64_t NE = undirected ? 2 * N : N;
+  c.set_tiles(TM_ESORT, erange, c.sort_tile);
+  c.set_tiles(TM_DEDUP, erange, SCAN_TILE);
   HIP_TRY(c.upload());
 
   // ------------------------------------------------------------- phase E
@@ -610,73 +620,107 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
            launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), c.A, hkeys, hrank,
                             grid_for(c.total(TM_DIR), cus * 8), st));
     TRACED(TK_HREMAP, N, 16.0 * N,
-           launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B,
+           launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else {
     TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
            launch_dir(c.tiles(TM_DIR, RANGE_NODES), c.A, c.dir,
                       grid_for(c.total(TM_DIR), cus * 8), st));
     TRACED(TK_REMAP, N, 24.0 * N,
-           launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B,
+           launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B, undirected,
                         grid_for(c.total(TM_REMAP), cus * 8), st));
   }
   uint64_t *ebuf[2] = {c.B, c.A};
+  // multigraph: every key carries its row through the sorts
+  uint32_t *vbuf[2] = {nullptr, nullptr};
+  if (multi) {
+    c.vals = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 2 * std::max<int64_t>(N, 1), st);
+    if (!c.vals) return RINGO_ERR_OUT_OF_MEMORY;
+    vbuf[0] = c.vals;
+    vbuf[1] = c.vals + N;
+    HIP_TRY(launch_iota(c.tiles(TM_REMAP, RANGE_ROWS), vbuf[0], grid_for(c.total(TM_REMAP), cus * 8),
+                        st));
+  }
   {
     for (int p = 0; p < P_e; ++p) {
-      SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, p,
+      SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, erange, P_e, p,
                                  RADIX_BITS * p);
-      TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, N, 0.0, SORT_EDGE, a);
+      if (multi) {
+        a.vin = vbuf[p & 1];
+        a.vout = vbuf[(p + 1) & 1];
+      }
+      TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0,
+                  multi ? SORT_EDGE_KV : SORT_EDGE, a);
     }
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
   uint64_t *ukeys = ebuf[(P_e + 1) & 1];
+  uint32_t *uvals = vbuf[P_e & 1];  // rows of the (kept) sorted keys, same positions
   {
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, RANGE_ROWS), sorted_edges, ukeys, c.results + S,
-                          c.status, c.counters + ep, ep,
+    HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
+                          c.status, c.counters + ep, ep, multi,
                           grid_for(c.total(TM_DEDUP), cus * 4), st));
-    dedupe_rec = trace_end(m, TK_DEDUPE, N, 8.0 * N, st);
+    dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   }
 
   // -------------------------------------------------------------- sync #2
   std::vector<int64_t> E;
   HIP_TRY(c.readback(S, E));
+  // int32 arrays of E per table: out_nbr, then (directed, multigraph)
+  // in_nbr, then (multigraph) out_eid and in_eid
+  const int narr = undirected ? 1 : multi ? 4 : 2;
   size_t arena2 = 0;
-  std::vector<size_t> off2(2 * (size_t)S);
+  std::vector<size_t> off2((size_t)narr * S);
   for (int i = 0; i < S; ++i) {
     c.plan[i].E = E[i];
-    off2[2 * i] = arena2;
-    arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
-    off2[2 * i + 1] = arena2;
-    arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
+    for (int k = 0; k < narr; ++k) {
+      off2[(size_t)narr * i + k] = arena2;
+      arena2 = align_up(arena2 + sizeof(int32_t) * E[i]);
+    }
   }
   for (int i = 0; i < S; ++i) sumE += E[i];
-  trace_set_bytes(dedupe_rec, 8.0 * N + 8.0 * sumE + 8.0 * (sumV + S));
+  trace_set_bytes(dedupe_rec, 8.0 * NE + 8.0 * sumE + 8.0 * (sumV + S));
   c.owner->blocks[1] = dev_alloc(c.hooks, arena2, st);
   if (!c.owner->blocks[1]) return RINGO_ERR_OUT_OF_MEMORY;
   char *a2 = (char *)c.owner->blocks[1];
   for (int i = 0; i < S; ++i) {
-    c.plan[i].out_nbr = (int32_t *)(a2 + off2[2 * i]);
-    c.plan[i].in_nbr = (int32_t *)(a2 + off2[2 * i + 1]);
+    SegPlan &p = c.plan[i];
+    p.out_nbr = (int32_t *)(a2 + off2[(size_t)narr * i]);
+    p.in_nbr = undirected ? p.out_nbr : (int32_t *)(a2 + off2[(size_t)narr * i + 1]);
+    p.out_eid = multi ? (int32_t *)(a2 + off2[(size_t)narr * i + 2]) : nullptr;
+    p.in_eid = multi ? (int32_t *)(a2 + off2[(size_t)narr * i + 3]) : nullptr;
+    if (undirected) p.in_off = p.out_off;  // the adjacency is its own transpose
   }
   c.set_tiles(TM_ISORT, RANGE_EDGES, c.sort_tile);
-  c.set_tiles(TM_ICSR, RANGE_EDGES, SCAN_TILE);
+  c.set_tiles(TM_ICSR, undirected ? RANGE_EDGES2 : RANGE_EDGES, SCAN_TILE);
   HIP_TRY(c.upload());
 
   // ------------------------------------------------------------- phase I
-  uint64_t *ibuf[2] = {ukeys, sorted_edges};
-  {
+  if (undirected) {
+    TRACED(TK_IN_CSR, sumE, 12.0 * sumE,
+           launch_out_nbr(c.tiles(TM_ICSR, RANGE_EDGES2), ukeys,
+                          grid_for(c.total(TM_ICSR), cus * 8), st));
+  } else {
+    uint64_t *ibuf[2] = {ukeys, sorted_edges};
+    uint32_t *ivb[2] = {uvals, multi ? vbuf[(P_e + 1) & 1] : nullptr};
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + RADIX_BITS * p);
-      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, p == 0 ? 4.0 : 0.0,
-                  p == 0 ? SORT_IN_FIRST : SORT_IN, a);
+      int mode = p == 0 ? SORT_IN_FIRST : SORT_IN;
+      if (multi) {
+        a.vin = ivb[p & 1];
+        a.vout = ivb[(p + 1) & 1];
+        mode = p == 0 ? SORT_IN_FIRST_KV : SORT_IN_KV;
+      }
+      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, (p == 0 ? 4.0 : 0.0) + (multi ? 8.0 : 0.0),
+                  mode, a);
     }
+    TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
+           launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1], multi ? ivb[P_in & 1] : nullptr,
+                         grid_for(c.total(TM_ICSR), cus * 8), st));
   }
-  TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
-         launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1],
-                       grid_for(c.total(TM_ICSR), cus * 8), st));
 
   // ------------------------------------------------------------- handoff
   c.owner->refs.store(S);
@@ -692,14 +736,20 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     g.in_offsets = p.in_off;
     g.in_nbrs = p.E > 0 ? p.in_nbr : nullptr;
     g._alloc = c.owner;
+    g.kind = c.kind;
+    g.out_eids = p.E > 0 ? p.out_eid : nullptr;
+    g.in_eids = p.E > 0 ? p.in_eid : nullptr;
   }
   c.owner = nullptr;  // now owned by the graphs
   return RINGO_OK;
 }
 
 ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *const *dst,
-                       const int64_t *num_rows, ringo_graph_t *outs, hipStream_t stream) {
+                       const int64_t *num_rows, int32_t kind, ringo_graph_t *outs,
+                       hipStream_t stream) {
   if (S < 0 || (S > 0 && (!src || !dst || !num_rows || !outs))) return RINGO_ERR_INVALID_ARG;
+  if (kind != RINGO_GRAPH_DIRECTED && kind != RINGO_GRAPH_UNDIRECTED && kind != RINGO_GRAPH_MULTI)
+    return RINGO_ERR_INVALID_ARG;
   for (int i = 0; i < S; ++i) std::memset(&outs[i], 0, sizeof(ringo_graph_t));
   for (int i = 0; i < S; ++i) {
     if (num_rows[i] < 0 || num_rows[i] > RINGO_MAX_ROWS) return RINGO_ERR_INVALID_ARG;
@@ -710,6 +760,7 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
   prepare_pool();
   Call c;
   c.S = S;
+  c.kind = kind;
   c.stream = stream;
   c.hooks = hooks();
   ringo_status_t rc = run(c, src, dst, num_rows, outs);
@@ -735,13 +786,26 @@ extern "C" {
 ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int64_t num_rows,
                                     ringo_graph_t *out, hipStream_t stream) {
   if (!out) return RINGO_ERR_INVALID_ARG;
-  return convert(1, &src, &dst, &num_rows, out, stream);
+  return convert(1, &src, &dst, &num_rows, RINGO_GRAPH_DIRECTED, out, stream);
 }
 
 ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,
                                             const int64_t *const *dst, const int64_t *num_rows,
                                             ringo_graph_t *outs, hipStream_t stream) {
-  return convert(num_tables, src, dst, num_rows, outs, stream);
+  return convert(num_tables, src, dst, num_rows, RINGO_GRAPH_DIRECTED, outs, stream);
+}
+
+ringo_status_t ringo_table_to_graph_ex(const int64_t *src, const int64_t *dst, int64_t num_rows,
+                                       int32_t kind, ringo_graph_t *out, hipStream_t stream) {
+  if (!out) return RINGO_ERR_INVALID_ARG;
+  return convert(1, &src, &dst, &num_rows, kind, out, stream);
+}
+
+ringo_status_t ringo_table_to_graph_batched_ex(int32_t num_tables, const int64_t *const *src,
+                                               const int64_t *const *dst, const int64_t *num_rows,
+                                               int32_t kind, ringo_graph_t *outs,
+                                               hipStream_t stream) {
+  return convert(num_tables, src, dst, num_rows, kind, outs, stream);
 }
 
 void ringo_graph_free(ringo_graph_t *g) {

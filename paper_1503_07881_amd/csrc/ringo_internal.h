@@ -25,6 +25,7 @@ enum RangeKind : int32_t {
   RANGE_EDGES = 2,      // E unique edges at row_off
   RANGE_NODES = 3,      // V unique nodes at 2 * row_off
   RANGE_SLOTS = 4,      // tab_cap node hash table slots at tab_off
+  RANGE_EDGES2 = 5,     // E unique edges at 2 * row_off (undirected graphs)
 };
 
 // Per-table plan, written by the host before each phase.
@@ -45,17 +46,21 @@ struct SegPlan {
   int32_t *out_nbr;
   int64_t *in_off;
   int32_t *in_nbr;
+  int32_t *out_eid;  // multigraph: row of every out-list entry
+  int32_t *in_eid;   // multigraph: row of every in-list entry
 };
 
 __host__ __device__ inline int64_t range_start(const SegPlan &p, int kind) {
   if (kind == RANGE_SLOTS) return p.tab_off;
-  return (kind == RANGE_NODE_KEYS || kind == RANGE_NODES) ? 2 * p.row_off : p.row_off;
+  return (kind == RANGE_NODE_KEYS || kind == RANGE_NODES || kind == RANGE_EDGES2) ? 2 * p.row_off
+                                                                                  : p.row_off;
 }
 __host__ __device__ inline int64_t range_count(const SegPlan &p, int kind) {
   switch (kind) {
     case RANGE_NODE_KEYS: return 2 * p.n;
     case RANGE_ROWS: return p.n;
-    case RANGE_EDGES: return p.E;
+    case RANGE_EDGES:
+    case RANGE_EDGES2: return p.E;
     case RANGE_SLOTS: return p.tab_cap;
     default: return p.V;
   }
@@ -84,15 +89,20 @@ struct SortLaunch {
   int64_t *digit_base;        // [S][RADIX] first output position of each digit's run
   uint32_t *counts;           // [tiles + 1][RADIX] digit counts, then their prefixes
   uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
+  const uint32_t *vin;        // values carried with the keys (key-value modes), else null
+  uint32_t *vout;
 };
 
 // Key source of a pass: the two first passes read their keys from elsewhere
 // (the node keys from the columns, the in-keys by repacking the out-keys);
 // the other values are plain passes, kept apart only so that each use of
 // the pass is its own kernel instantiation.
+// The _KV modes carry a 32-bit value (the row of a multigraph edge) with
+// every key.
 enum SortMode : int {
   SORT_PLAIN = 0, SORT_NODE_FIRST = 1, SORT_IN_FIRST = 2,
-  SORT_NODE = 3, SORT_VNODE = 4, SORT_EDGE = 5, SORT_IN = 6
+  SORT_NODE = 3, SORT_VNODE = 4, SORT_EDGE = 5, SORT_IN = 6,
+  SORT_EDGE_KV = 7, SORT_IN_FIRST_KV = 8, SORT_IN_KV = 9
 };
 enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2 };
 
@@ -126,8 +136,9 @@ struct alignas(16) DirEntry {
 
 hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, DirEntry *dir, int grid,
                       hipStream_t s);
+// sym (undirected graphs): both orientations, 2n keys at 2 * row_off.
 hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEntry *dir,
-                        uint64_t *ekeys, int grid, hipStream_t s);
+                        uint64_t *ekeys, int sym, int grid, hipStream_t s);
 // ------------------------------------------------- node hash table (hash.hip)
 
 constexpr int HLL_BITS = 10;                 // log2 of the count-estimate registers
@@ -156,14 +167,22 @@ hipError_t launch_hash_compact(const TileLaunch &slot_tiles, const uint64_t *hke
 // its slot.
 hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
                             const uint64_t *hkeys, uint32_t *hrank, int grid, hipStream_t s);
-// Every row's (src, dst) slots -> dense positions, packed edge keys.
+// Every row's (src, dst) slots -> dense positions, packed edge keys (sym as
+// for launch_remap).
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
-                             uint64_t *ekeys, int grid, hipStream_t s);
+                             uint64_t *ekeys, int sym, int grid, hipStream_t s);
 
+// keep_all: every sorted key is its own edge (multigraph), offsets only.
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
-                         uint32_t epoch, int grid, hipStream_t s);
-hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s);
+                         uint32_t epoch, int keep_all, int grid, hipStream_t s);
+// vals (multigraph): the row of every (d, s)-sorted edge, copied to in_eid.
+hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, const uint32_t *vals, int grid,
+                         hipStream_t s);
+// Undirected graphs: out-neighbours from the unique keys (E at 2 * row_off).
+hipError_t launch_out_nbr(const TileLaunch &t, const uint64_t *in, int grid, hipStream_t s);
+// Multigraph: v[row_off + r] = r for every row of every table.
+hipError_t launch_iota(const TileLaunch &rows, uint32_t *v, int grid, hipStream_t s);
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
 int device_cu_count();
 

@@ -37,6 +37,7 @@ EXPORTED_SYMBOLS = (
     "ringo_server_create", "ringo_server_submit", "ringo_server_poll", "ringo_server_release",
     "ringo_server_stats", "ringo_server_destroy",
     "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
+    "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex",
 )
 
 
@@ -58,7 +59,14 @@ class RawGraph(ctypes.Structure):
         ("in_offsets", ctypes.c_void_p),
         ("in_nbrs", ctypes.c_void_p),
         ("_alloc", ctypes.c_void_p),
+        ("kind", ctypes.c_int32),
+        ("_reserved", ctypes.c_int32),
+        ("out_eids", ctypes.c_void_p),
+        ("in_eids", ctypes.c_void_p),
     ]
+
+
+GRAPH_DIRECTED, GRAPH_UNDIRECTED, GRAPH_MULTI = 0, 1, 2
 
 
 class TraceEntry(ctypes.Structure):
@@ -91,6 +99,11 @@ def lib() -> ctypes.CDLL:
         L.ringo_table_to_graph.restype = ctypes.c_int
         L.ringo_table_to_graph_batched.argtypes = [ctypes.c_int32, p, p, p, ctypes.POINTER(RawGraph), p]
         L.ringo_table_to_graph_batched.restype = ctypes.c_int
+        L.ringo_table_to_graph_ex.argtypes = [p, p, i64, ctypes.c_int32, ctypes.POINTER(RawGraph), p]
+        L.ringo_table_to_graph_ex.restype = ctypes.c_int
+        L.ringo_table_to_graph_batched_ex.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32,
+                                                      ctypes.POINTER(RawGraph), p]
+        L.ringo_table_to_graph_batched_ex.restype = ctypes.c_int
         L.ringo_graph_free.argtypes = [ctypes.POINTER(RawGraph)]
         L.ringo_graph_free.restype = None
         L.ringo_status_string.argtypes = [ctypes.c_int]
@@ -138,21 +151,30 @@ def _column(t: torch.Tensor, name: str) -> torch.Tensor:
 
 # ------------------------------------------------------------- raw calls
 
-def table_to_graph_raw(src_ptr: int, dst_ptr: int, num_rows: int, stream: int) -> RawGraph:
-    """ringo_table_to_graph on raw device pointers; free with graph_free."""
+def table_to_graph_raw(src_ptr: int, dst_ptr: int, num_rows: int, stream: int,
+                       kind: int = GRAPH_DIRECTED) -> RawGraph:
+    """ringo_table_to_graph(_ex) on raw device pointers; free with graph_free."""
     g = RawGraph()
-    _check(lib().ringo_table_to_graph(src_ptr, dst_ptr, num_rows, ctypes.byref(g), stream),
-           "ringo_table_to_graph")
+    if kind == GRAPH_DIRECTED:
+        rc = lib().ringo_table_to_graph(src_ptr, dst_ptr, num_rows, ctypes.byref(g), stream)
+    else:
+        rc = lib().ringo_table_to_graph_ex(src_ptr, dst_ptr, num_rows, kind, ctypes.byref(g), stream)
+    _check(rc, "ringo_table_to_graph")
     return g
 
 
-def table_to_graph_batched_raw(src_ptrs, dst_ptrs, num_rows, stream: int) -> list[RawGraph]:
+def table_to_graph_batched_raw(src_ptrs, dst_ptrs, num_rows, stream: int,
+                               kind: int = GRAPH_DIRECTED) -> list[RawGraph]:
     k = len(num_rows)
     S = (ctypes.c_void_p * k)(*src_ptrs)
     D = (ctypes.c_void_p * k)(*dst_ptrs)
     N = (ctypes.c_int64 * k)(*num_rows)
     outs = (RawGraph * k)()
-    _check(lib().ringo_table_to_graph_batched(k, S, D, N, outs, stream), "ringo_table_to_graph_batched")
+    if kind == GRAPH_DIRECTED:
+        rc = lib().ringo_table_to_graph_batched(k, S, D, N, outs, stream)
+    else:
+        rc = lib().ringo_table_to_graph_batched_ex(k, S, D, N, kind, outs, stream)
+    _check(rc, "ringo_table_to_graph_batched")
     return [outs[i] for i in range(k)]
 
 
@@ -268,33 +290,38 @@ class Graph:
     out_nbrs: torch.Tensor     # int32 [E]
     in_offsets: torch.Tensor   # int64 [V+1]
     in_nbrs: torch.Tensor      # int32 [E]
+    kind: int = 0              # GRAPH_DIRECTED / GRAPH_UNDIRECTED / GRAPH_MULTI
+    out_eids: torch.Tensor | None = None  # int32 [E] multigraph: row of each out-entry
+    in_eids: torch.Tensor | None = None   # int32 [E] multigraph: row of each in-entry
 
 
-def _wrap(raw: RawGraph, device) -> Graph:
-    owner = _Owner(raw)
+def _graph_of(raw: RawGraph, owner, device) -> Graph:
     V, E = raw.num_nodes, raw.num_edges
+    multi = raw.kind == GRAPH_MULTI
     return Graph(raw.num_rows, V, E,
                  _view(raw.node_ids, V, torch.int64, owner, device),
                  _view(raw.out_offsets, V + 1, torch.int64, owner, device),
                  _view(raw.out_nbrs, E, torch.int32, owner, device),
                  _view(raw.in_offsets, V + 1, torch.int64, owner, device),
-                 _view(raw.in_nbrs, E, torch.int32, owner, device))
+                 _view(raw.in_nbrs, E, torch.int32, owner, device),
+                 raw.kind,
+                 _view(raw.out_eids, E, torch.int32, owner, device) if multi else None,
+                 _view(raw.in_eids, E, torch.int32, owner, device) if multi else None)
+
+
+def _wrap(raw: RawGraph, device) -> Graph:
+    return _graph_of(raw, _Owner(raw), device)
 
 
 def view_graph(raw: RawGraph, device) -> Graph:
     """Tensor views of a graph owned elsewhere (for example by the server);
     valid only while the owner keeps it."""
-    V, E = raw.num_nodes, raw.num_edges
-    return Graph(raw.num_rows, V, E,
-                 _view(raw.node_ids, V, torch.int64, None, device),
-                 _view(raw.out_offsets, V + 1, torch.int64, None, device),
-                 _view(raw.out_nbrs, E, torch.int32, None, device),
-                 _view(raw.in_offsets, V + 1, torch.int64, None, device),
-                 _view(raw.in_nbrs, E, torch.int32, None, device))
+    return _graph_of(raw, None, device)
 
 
-def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None) -> Graph:
-    """Table-to-graph conversion of one edge table (src, dst columns)."""
+def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None, kind: int = GRAPH_DIRECTED) -> Graph:
+    """Table-to-graph conversion of one edge table (src, dst columns);
+    kind: GRAPH_DIRECTED (default), GRAPH_UNDIRECTED or GRAPH_MULTI."""
     src = _column(src, "src")
     dst = _column(dst, "dst")
     if src.numel() != dst.numel():
@@ -302,7 +329,7 @@ def to_graph(src: torch.Tensor, dst: torch.Tensor, stream=None) -> Graph:
     if src.device != dst.device:
         raise ValueError("src and dst must be on the same device")
     with torch.cuda.device(src.device):
-        raw = table_to_graph_raw(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream))
+        raw = table_to_graph_raw(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream), kind)
     return _wrap(raw, src.device)
 
 
@@ -310,9 +337,10 @@ def raw_of(g: Graph) -> RawGraph:
     """A RawGraph struct over the tensors of `g` (it owns nothing)."""
     r = RawGraph()
     r.num_rows, r.num_nodes, r.num_edges = g.num_rows, g.num_nodes, g.num_edges
-    for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs"):
+    for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs", "out_eids", "in_eids"):
         t = getattr(g, f)
-        setattr(r, f, t.data_ptr() if t.numel() else None)
+        setattr(r, f, t.data_ptr() if t is not None and t.numel() else None)
+    r.kind = g.kind
     return r
 
 
@@ -345,7 +373,7 @@ def pagerank(g: Graph, damping: float = 0.85, iterations: int = 10, stream=None)
     return ranks
 
 
-def to_graph_batched(srcs, dsts, stream=None) -> list[Graph]:
+def to_graph_batched(srcs, dsts, stream=None, kind: int = GRAPH_DIRECTED) -> list[Graph]:
     """Batched conversion: one library call for all tables."""
     if len(srcs) != len(dsts):
         raise ValueError("srcs and dsts must have the same length")
@@ -361,5 +389,5 @@ def to_graph_batched(srcs, dsts, stream=None) -> list[Graph]:
             raise ValueError("all tables must be on the same device")
     with torch.cuda.device(dev):
         raws = table_to_graph_batched_raw([s.data_ptr() for s in srcs], [d.data_ptr() for d in dsts],
-                                          [s.numel() for s in srcs], _stream_handle(stream))
+                                          [s.numel() for s in srcs], _stream_handle(stream), kind)
     return [_wrap(r, dev) for r in raws]
