@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kind", default="directed", choices=("directed", "undirected", "multi"),
+                    help="graph kind of the table-to-graph conversion")
     ap.add_argument("--op", default="to_graph", choices=("to_graph", "to_table", "pagerank"),
                     help="to_graph: table-to-graph conversion (default); to_table: graph-to-table; "
                          "pagerank: ten PageRank iterations on the converted graph")
@@ -420,8 +422,11 @@ def main():
     del ca, cb
     log(f"bench: copy kernel {copy_gbps:.0f} GB/s")
 
+    kind = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
+            "multi": ringo.GRAPH_MULTI}[args.kind]
+
     def step():
-        g = ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh)
+        g = ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh, kind)
         V, E = g.num_nodes, g.num_edges
         ringo.graph_free(g)
         return V, E
@@ -471,7 +476,9 @@ def main():
     items = ringo.tune_get(n)[1]
 
     out = {
-        "metric": "edges/s converted (input rows per second, table to directed simple graph, 1 GPU)",
+        "metric": ("edges/s converted (input rows per second, table to directed simple graph, 1 GPU)"
+                   if args.kind == "directed" else
+                   f"edges/s converted (input rows per second, table to {args.kind} graph, 1 GPU)"),
         "value": n / (ms / 1e3),
         "unit": "edges/s",
         "n_gpus": 1,
@@ -483,7 +490,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)",
-        "config": {"workload": workload,
+        "config": {"workload": workload, "graph_kind": args.kind,
                    "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
                    "digit_bits": 8, "items_per_thread": items,
                    "node_method": "hash" if ringo.tune_get(n)[2] == ringo.NODES_HASH else "sort"},

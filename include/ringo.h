@@ -226,7 +226,8 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
  *                     sizes the table).  Should a probe sequence exceed its
  *                     bound (an estimate far too low), the call falls back to
  *                     RINGO_NODES_SORT by itself.
- * Built-in default: RINGO_NODES_HASH from 2^20 rows, RINGO_NODES_SORT below.
+ * Built-in defaults (measured on an MI355X): RINGO_NODES_SORT up to 2^23 rows,
+ * RINGO_NODES_HASH above; 8 items per thread up to 2^24 rows, 16 above.
  */
 #define RINGO_NODES_SORT 0
 #define RINGO_NODES_HASH 1

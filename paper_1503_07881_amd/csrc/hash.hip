@@ -1,9 +1,9 @@
 // Node numbering through a node hash table.
 //
-// The paper keeps a graph's nodes in an open-addressing hash table with
-// linear probing (Ringo Implementation, "Concurrent hash tables and vectors",
-// Section 2.5) and inserts both identifiers of every row into it (the
-// Twitter2010 walk-through of Section 3).  Here that table replaces the
+// The paper keeps a graph's nodes in a hash table whose collisions go to the
+// next free slot (Section 2.5, the paragraph on concurrent hash tables), and
+// its Twitter2010 walk-through (Section 3) inserts both identifiers of every
+// row into that table.  Here that table replaces the
 // 2n-key radix sort of the node keys: only the V distinct keys are sorted,
 // which is what fixes the dense positions, so the output is identical to
 // the sort-based numbering.

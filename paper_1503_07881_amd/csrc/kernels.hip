@@ -182,7 +182,7 @@ __device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan 
     // one load from a selected pointer: no branch, so loads stay in flight
     const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? G(P.src) + e : G(P.dst) + (e - P.n);
     return (uint64_t)*ptr ^ SIGN_FLIP;
-  } else if (MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV) {
+  } else if (MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_FIRST_DEDUP) {
     const uint64_t x = G(a.in)[start + e];
     const uint64_t d = x & ((1ull << P.b) - 1);
     return (d << 32) | (x >> P.b);
@@ -238,16 +238,27 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         // Lanes hold consecutive keys: a run of equal digits over
-        // neighbouring lanes (clustered identifiers after the first passes)
-        // is added once, by the lane that starts it.
-        const bool valid = e0 + j * 64 < k1;
+        // neighbouring valid lanes (clustered identifiers after the first
+        // passes) is added once, by the lane that starts it.
+        const int64_t e = e0 + j * 64;
+        bool valid = e < k1;
+        if (MODE == SORT_IN_FIRST_DEDUP) {
+          // only the first copy of every key counts
+          uint64_t prev = __shfl_up(k[j], 1, 64);
+          // lane 0 reads its predecessor, only for elements inside the tile
+          if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
+          valid = valid && (e == 0 || k[j] != prev);
+        }
         const uint32_t d = (uint32_t)(k[j] >> shift) & (RADIX - 1);
         const uint32_t dp = __shfl_up(d, 1, 64);
-        const uint64_t heads = __ballot(valid && (lane == 0 || d != dp));
         const uint64_t vmask = __ballot(valid);
+        const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
+        const uint64_t heads = __ballot(valid && (lane == 0 || d != dp || !prev_valid));
         if ((heads >> lane) & 1ull) {
-          const uint64_t after = lane < 63 ? heads & ~((2ull << lane) - 1) : 0ull;  // heads above
-          const int end = after ? __builtin_ctzll(after) : 64 - __builtin_clzll(vmask);
+          // the run ends at the next run head or invalid lane above this one
+          const uint64_t stop = heads | ~vmask;
+          const uint64_t after = lane < 63 ? stop & ~((2ull << lane) - 1) : 0ull;
+          const int end = after ? __builtin_ctzll(after) : 64;
           atomicAdd(&h[d], (uint32_t)(end - lane));
         }
       }
@@ -321,6 +332,7 @@ __global__ __launch_bounds__(RADIX) void k_seg_base(SortLaunch a) {
   uint32_t all;
   const uint32_t ex = block_excl_scan<RADIX>(tot, s_w, all);
   a.digit_base[(int64_t)seg * RADIX + d] = range_start(a.plan[seg], a.range_kind) + (int64_t)ex;
+  if (a.seg_total && d == 0) a.seg_total[seg] = (int64_t)all;
 }
 
 // Waves per SIMD the downsweep is compiled for: the register budget that
@@ -332,6 +344,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
   constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV;
+  constexpr bool DEDUP = MODE == SORT_IN_FIRST_DEDUP;
   constexpr bool IN_FIRST = MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV;
   static_assert(BLOCK >= RADIX, "one thread per digit");
   __shared__ uint64_t s_stage[TILE];
@@ -340,6 +353,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   __shared__ uint32_t s_lstart[RADIX];
   __shared__ int64_t s_goff[RADIX];
   __shared__ uint32_t s_w[WAVES];
+  __shared__ uint32_t s_wu[DEDUP ? WAVES : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
@@ -393,6 +407,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         }
       }
     }
+    // Live keys: all keys of the tile, or (dedupe folded into the pass) the
+    // first copy of every key; ub[i] is row i's ballot of live lanes.
+    uint32_t live_bits = 0;
+    uint64_t ub[DEDUP ? ITEMS : 1];
+    uint32_t wave_live = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+      bool live = idx < cnt;
+      if (DEDUP) {
+        const int64_t e = base + idx;
+        uint64_t prev = __shfl_up(keys[i], 1, 64);
+        const uint64_t above = __shfl(keys[i > 0 ? i - 1 : 0], 63, 64);
+        // lane 0 reads its predecessor, only for elements inside the tile
+        if (lane == 0 && idx < cnt)
+          prev = i > 0 ? above : (e > 0 ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~keys[i]);
+        live = live && (e == 0 || keys[i] != prev);
+        ub[DEDUP ? i : 0] = __ballot(live);
+        wave_live += (uint32_t)__popcll(ub[DEDUP ? i : 0]);
+      }
+      live_bits |= (uint32_t)live << i;
+    }
+    if (DEDUP && lane == 0) s_wu[DEDUP ? wave : 0] = wave_live;
     const uint32_t tprefix = tid < RADIX ? a.counts[tile * RADIX + tid] : 0u;
 
     // Stable rank inside the wave: lanes with an equal digit are found with
@@ -400,7 +437,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      const bool valid = wave * (ITEMS * 64) + i * 64 + lane < cnt;
+      const bool valid = (live_bits >> i) & 1u;
       const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
       uint64_t m = __ballot(valid);
 #pragma unroll
@@ -436,12 +473,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       s_lstart[tid] = lstart;
       s_goff[tid] = dbase + (int64_t)(uint32_t)(tprefix - pfirst) - (int64_t)lstart;
     }
+    if (DEDUP) {
+      // De-duplicated position of every live key: the table's live keys in
+      // earlier tiles (the digit prefixes summed), earlier waves, earlier rows.
+      uint32_t tile_hp;
+      (void)block_excl_scan<BLOCK>(tid < RADIX ? (uint32_t)(tprefix - pfirst) : 0u, s_w, tile_hp);
+      uint32_t pos = tile_hp;
+      for (int w = 0; w < wave; ++w) pos += s_wu[w];
+      const int64_t V = H.P.V;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+        const int64_t e = base + idx;
+        uint64_t prev = __shfl_up(keys[i], 1, 64);
+        const uint64_t above = __shfl(keys[i > 0 ? i - 1 : 0], 63, 64);
+        if (lane == 0 && idx < cnt)
+          prev = i > 0 ? above : (e > 0 ? pass_key<MODE>(a, H.P, H.start, e - 1) : 0ull);
+        const int64_t s_own = (int64_t)(uint32_t)keys[i];
+        if ((live_bits >> i) & 1u) {
+          const int64_t j = (int64_t)pos + lanes_below(ub[DEDUP ? i : 0]);
+          G(H.P.out_nbr)[j] = (int32_t)(uint32_t)(keys[i] >> 32);
+          // out_off[v] = first position whose source is >= v
+          const int64_t hp = e == 0 ? -1 : (int64_t)(uint32_t)prev;
+          for (int64_t v = hp + 1; v <= s_own; ++v) G(H.P.out_off)[v] = j;
+        }
+        if (idx < cnt && e == H.count - 1)  // the table's last key closes the offsets
+          for (int64_t v = s_own + 1; v <= V; ++v) G(H.P.out_off)[v] = H.P.E;
+        pos += (uint32_t)__popcll(ub[DEDUP ? i : 0]);
+      }
+    }
     __syncthreads();
 
     // Stage the tile in LDS in digit order.
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      if (wave * (ITEMS * 64) + i * 64 + lane < cnt) {
+      if ((live_bits >> i) & 1u) {
         const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
         const uint32_t slot = s_lstart[d] + s_whist[wave * RADIX + d] + rank[i];
         s_stage[slot] = keys[i];
@@ -455,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int p = i * BLOCK + tid;
-      if (p < cnt) {
+      if (p < (int)tile_total) {
         const uint64_t k = s_stage[p];
         const int64_t pos = s_goff[(uint32_t)(k >> shift) & (RADIX - 1)] + p;
         if ((uint64_t)(pos - H.start) < (uint64_t)H.count) {  // in range by construction
@@ -544,6 +610,7 @@ static hipError_t launch_pass_items(const SortLaunch &a, int mode, int parts, hi
     case SORT_EDGE_KV: return launch_pass_t<ITEMS, SORT_EDGE_KV>(a, parts, s);
     case SORT_IN_FIRST_KV: return launch_pass_t<ITEMS, SORT_IN_FIRST_KV>(a, parts, s);
     case SORT_IN_KV: return launch_pass_t<ITEMS, SORT_IN_KV>(a, parts, s);
+    case SORT_IN_FIRST_DEDUP: return launch_pass_t<ITEMS, SORT_IN_FIRST_DEDUP>(a, parts, s);
     default: return launch_pass_t<ITEMS, SORT_PLAIN>(a, parts, s);
   }
 }

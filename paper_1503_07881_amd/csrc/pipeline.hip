@@ -143,16 +143,20 @@ void pinned_release(Pinned *b, hipStream_t s) {
 // ------------------------------------------------------------- schedule
 
 // Items per thread of the scatter tile and node-numbering method by table
-// size (log2 buckets).  Built-in default: the hash numbering from 2^20 rows.
+// size (log2 buckets of rows).  Built-in defaults, from the autotuner's
+// measurements on an MI355X (R-MAT tables, 2^10 to 2^26 rows): the sort
+// numbering up to 2^23 rows and the hash numbering above; 8 items per
+// thread up to 2^24 rows and 16 above.
 int g_items[64];
 int g_method[64];
 bool g_items_init = false;
-constexpr int HASH_DEFAULT_LOG2 = 20;
+constexpr int HASH_DEFAULT_LOG2 = 24;
+constexpr int ITEMS16_DEFAULT_LOG2 = 25;
 
 void schedule_init_locked() {
   if (g_items_init) return;
   for (int i = 0; i < 64; ++i) {
-    g_items[i] = 16;
+    g_items[i] = i >= ITEMS16_DEFAULT_LOG2 ? 16 : 8;
     g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
   }
   g_items_init = true;
@@ -313,6 +317,7 @@ struct Call {
     a.bsum = bsum;
     a.vin = nullptr;
     a.vout = nullptr;
+    a.seg_total = nullptr;
     return a;
   }
 };
@@ -656,7 +661,16 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   uint64_t *sorted_edges = ebuf[P_e & 1];
   uint64_t *ukeys = ebuf[(P_e + 1) & 1];
   uint32_t *uvals = vbuf[P_e & 1];  // rows of the (kept) sorted keys, same positions
-  {
+  const bool folded = !undirected && !multi;
+  SortLaunch in0;  // folded: the first in-pass, counted before sync #2, scattered after
+  if (folded) {
+    // Directed graphs: dedupe is folded into the first in-pass, which counts
+    // only the first copy of every key; its per-table totals are E.
+    in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
+    in0.seg_total = c.results + S;
+    TRACED(TK_IN_COUNT, N, 8.0 * N,
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, SORT_PART_COUNT, st));
+  } else {
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
     HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
@@ -702,6 +716,20 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     TRACED(TK_IN_CSR, sumE, 12.0 * sumE,
            launch_out_nbr(c.tiles(TM_ICSR, RANGE_EDGES2), ukeys,
                           grid_for(c.total(TM_ICSR), cus * 8), st));
+  } else if (folded) {
+    // first in-pass: sorted edge keys with repeats -> distinct (d, s) keys,
+    // out_nbr and out_off at the de-duplicated positions
+    TRACED(TK_IN_SCATTER, N, 8.0 * N + 12.0 * sumE + 8.0 * (sumV + S),
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, SORT_PART_SCATTER, st));
+    uint64_t *ib[2] = {ukeys, sorted_edges};
+    for (int p = 1; p < P_in; ++p) {
+      SortLaunch a = c.sort_args(ib[(p - 1) & 1], ib[p & 1], TM_ISORT, RANGE_EDGES, P_in, p,
+                                 32 + RADIX_BITS * p);
+      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a);
+    }
+    TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
+           launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ib[(P_in - 1) & 1], nullptr,
+                         grid_for(c.total(TM_ICSR), cus * 8), st));
   } else {
     uint64_t *ibuf[2] = {ukeys, sorted_edges};
     uint32_t *ivb[2] = {uvals, multi ? vbuf[(P_e + 1) & 1] : nullptr};

@@ -91,6 +91,7 @@ struct SortLaunch {
   uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
   const uint32_t *vin;        // values carried with the keys (key-value modes), else null
   uint32_t *vout;
+  int64_t *seg_total;         // if set, the count part writes each table's key total
 };
 
 // Key source of a pass: the two first passes read their keys from elsewhere
@@ -102,7 +103,11 @@ struct SortLaunch {
 enum SortMode : int {
   SORT_PLAIN = 0, SORT_NODE_FIRST = 1, SORT_IN_FIRST = 2,
   SORT_NODE = 3, SORT_VNODE = 4, SORT_EDGE = 5, SORT_IN = 6,
-  SORT_EDGE_KV = 7, SORT_IN_FIRST_KV = 8, SORT_IN_KV = 9
+  SORT_EDGE_KV = 7, SORT_IN_FIRST_KV = 8, SORT_IN_KV = 9,
+  // first in-pass over the sorted edge keys with their repeats: only the
+  // first copy of each key is sorted, and the pass also writes out_nbr and
+  // out_off at the de-duplicated positions (dedupe folded into the pass)
+  SORT_IN_FIRST_DEDUP = 10
 };
 enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2 };
 

@@ -1,9 +1,9 @@
 // Served form of the conversion: an interactive request loop that keeps
 // built graphs resident on the device.
 //
-// The paper's goal is interactive use: tables of hundreds of millions of
-// rows converted "at speeds that make the system suitable for interactive
-// use" (Section 2.4), with graphs kept in memory for the analysis that
+// The paper aims the conversion at interactive sessions: very large tables
+// have to become graphs quickly enough for an analyst to wait on them
+// (Section 2.4), and the graphs stay in memory for the analysis that
 // follows (Sections 1 and 2.1).  The server here:
 //   * queues requests (host edge tables) in arrival order;
 //   * runs W worker threads, each with its own HIP stream; a free worker

@@ -76,12 +76,13 @@ def test_tune_schedule_roundtrip():
     d, it, m = ringo.tune_get(1000)
     assert d == 8 and it in (8, 12, 16) and m == ringo.NODES_SORT
     assert ringo.tune_get(1 << 24)[2] == ringo.NODES_HASH   # built-in default for large tables
+    assert ringo.tune_get(1 << 20)[2] == ringo.NODES_SORT   # built-in default below 2^24 rows
     ringo.tune_set(1 << 20, 8, 12)
-    assert ringo.tune_get(1 << 20) == (8, 12, ringo.NODES_HASH)
-    ringo.tune_set(1 << 20, 8, 12, ringo.NODES_SORT)
     assert ringo.tune_get(1 << 20) == (8, 12, ringo.NODES_SORT)
-    assert ringo.tune_get(1 << 21)[2] == ringo.NODES_HASH   # other buckets untouched
-    ringo.tune_set(1 << 20, 8, 16, ringo.NODES_HASH)
+    ringo.tune_set(1 << 20, 8, 12, ringo.NODES_HASH)
+    assert ringo.tune_get(1 << 20) == (8, 12, ringo.NODES_HASH)
+    assert ringo.tune_get(1 << 21)[2] == ringo.NODES_SORT   # other buckets untouched
+    ringo.tune_set(1 << 20, 8, 8, ringo.NODES_SORT)         # back to the built-in default
     with pytest.raises(ringo.RingoError):
         ringo.tune_set(1000, 8, 16, 2)
     with pytest.raises(ringo.RingoError):
@@ -133,5 +134,6 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert ringo.tune_get(1 << 15)[2] == 0
     assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
     # restore the built-in default
-    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 16, "node_method": 0},
-                                                  str(1 << 20): {"items": 16, "node_method": 1}}})
+    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 8, "node_method": 0},
+                                                  str(1 << 24): {"items": 8, "node_method": 1},
+                                                  str(1 << 25): {"items": 16, "node_method": 1}}})
