@@ -335,12 +335,19 @@ __global__ __launch_bounds__(RADIX) void k_seg_base(SortLaunch a) {
   if (a.seg_total && d == 0) a.seg_total[seg] = (int64_t)all;
 }
 
-// Waves per SIMD the downsweep is compiled for: the register budget that
-// still holds a tile of 8 or 12 keys per thread without spilling.
-constexpr int ds_waves(int items) { return items <= 8 ? 5 : items <= 12 ? 4 : 3; }
+// Waves per SIMD the downsweep is compiled for: as many as the kernel's
+// registers allow without spilling (a tile of 8 keys per thread needs about
+// 105 VGPRs, 12 about 140, 16 about 175 and fits 168; carrying values and
+// folding the dedupe take more).
+constexpr int ds_waves(int items, int mode) {
+  return mode == SORT_IN_FIRST_DEDUP ? (items <= 8 ? 3 : 2)
+         : (mode == SORT_EDGE_KV || mode == SORT_IN_FIRST_KV || mode == SORT_IN_KV)
+             ? (items <= 8 ? 4 : items <= 12 ? 3 : 2)
+             : (items <= 8 ? 4 : 3);
+}
 
 template <int BLOCK, int ITEMS, int MODE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(ITEMS), 8))) void k_downsweep(SortLaunch a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(ITEMS, MODE), 8))) void k_downsweep(SortLaunch a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
   constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV;
@@ -410,8 +417,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     // Live keys: all keys of the tile, or (dedupe folded into the pass) the
     // first copy of every key; ub[i] is row i's ballot of live lanes.
     uint32_t live_bits = 0;
-    uint64_t ub[DEDUP ? ITEMS : 1];
     uint32_t wave_live = 0;
+    uint32_t psrc[DEDUP ? ITEMS : 1];  // DEDUP: source of each key's predecessor
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
@@ -424,8 +431,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         if (lane == 0 && idx < cnt)
           prev = i > 0 ? above : (e > 0 ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~keys[i]);
         live = live && (e == 0 || keys[i] != prev);
-        ub[DEDUP ? i : 0] = __ballot(live);
-        wave_live += (uint32_t)__popcll(ub[DEDUP ? i : 0]);
+        psrc[DEDUP ? i : 0] = (uint32_t)prev;
+        wave_live += (uint32_t)__popcll(__ballot(live));
       }
       live_bits |= (uint32_t)live << i;
     }
@@ -473,34 +480,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       s_lstart[tid] = lstart;
       s_goff[tid] = dbase + (int64_t)(uint32_t)(tprefix - pfirst) - (int64_t)lstart;
     }
+    uint32_t dpos = 0;  // DEDUP: de-duplicated position of this wave's first live key
     if (DEDUP) {
-      // De-duplicated position of every live key: the table's live keys in
-      // earlier tiles (the digit prefixes summed), earlier waves, earlier rows.
+      // the table's live keys in earlier tiles (the digit prefixes summed),
+      // then in earlier waves of this tile
       uint32_t tile_hp;
       (void)block_excl_scan<BLOCK>(tid < RADIX ? (uint32_t)(tprefix - pfirst) : 0u, s_w, tile_hp);
-      uint32_t pos = tile_hp;
-      for (int w = 0; w < wave; ++w) pos += s_wu[w];
-      const int64_t V = H.P.V;
-#pragma unroll
-      for (int i = 0; i < ITEMS; ++i) {
-        const int idx = wave * (ITEMS * 64) + i * 64 + lane;
-        const int64_t e = base + idx;
-        uint64_t prev = __shfl_up(keys[i], 1, 64);
-        const uint64_t above = __shfl(keys[i > 0 ? i - 1 : 0], 63, 64);
-        if (lane == 0 && idx < cnt)
-          prev = i > 0 ? above : (e > 0 ? pass_key<MODE>(a, H.P, H.start, e - 1) : 0ull);
-        const int64_t s_own = (int64_t)(uint32_t)keys[i];
-        if ((live_bits >> i) & 1u) {
-          const int64_t j = (int64_t)pos + lanes_below(ub[DEDUP ? i : 0]);
-          G(H.P.out_nbr)[j] = (int32_t)(uint32_t)(keys[i] >> 32);
-          // out_off[v] = first position whose source is >= v
-          const int64_t hp = e == 0 ? -1 : (int64_t)(uint32_t)prev;
-          for (int64_t v = hp + 1; v <= s_own; ++v) G(H.P.out_off)[v] = j;
-        }
-        if (idx < cnt && e == H.count - 1)  // the table's last key closes the offsets
-          for (int64_t v = s_own + 1; v <= V; ++v) G(H.P.out_off)[v] = H.P.E;
-        pos += (uint32_t)__popcll(ub[DEDUP ? i : 0]);
-      }
+      dpos = tile_hp;
+      for (int w = 0; w < wave; ++w) dpos += s_wu[w];
     }
     __syncthreads();
 
@@ -512,6 +499,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         const uint32_t slot = s_lstart[d] + s_whist[wave * RADIX + d] + rank[i];
         s_stage[slot] = keys[i];
         if (KV) s_vstage[KV ? slot : 0] = vals[KV ? i : 0];
+      }
+    }
+    if (DEDUP) {
+      // out-neighbours and out-offsets at the de-duplicated positions (rank
+      // is dead here, which keeps the kernel within its registers)
+      const int64_t V = H.P.V;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+        const int64_t e = base + idx;
+        const bool live = (live_bits >> i) & 1u;
+        const uint64_t lb = __ballot(live);
+        const int64_t s_own = (int64_t)(uint32_t)keys[i];
+        if (live) {
+          const int64_t j = (int64_t)dpos + lanes_below(lb);
+          G(H.P.out_nbr)[j] = (int32_t)(uint32_t)(keys[i] >> 32);
+          // out_off[v] = first position whose source is >= v
+          const int64_t hp = e == 0 ? -1 : (int64_t)psrc[DEDUP ? i : 0];
+          for (int64_t v = hp + 1; v <= s_own; ++v) G(H.P.out_off)[v] = j;
+        }
+        if (idx < cnt && e == H.count - 1)  // the table's last key closes the offsets
+          for (int64_t v = s_own + 1; v <= V; ++v) G(H.P.out_off)[v] = H.P.E;
+        dpos += (uint32_t)__popcll(lb);
       }
     }
     __syncthreads();
@@ -588,8 +598,10 @@ static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
     hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
   }
   if (parts & SORT_PART_SCATTER) {
+    // four blocks per resident slot: blocks that finish early make room for
+    // the next ones (measured faster than one persistent block per slot)
     const int64_t g = std::max<int64_t>(
-        NUM_XCD, std::min<int64_t>(a.total_tiles, resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);
+        NUM_XCD, std::min<int64_t>(a.total_tiles, 4 * resident_t<ITEMS>()) / NUM_XCD * NUM_XCD);
     hipLaunchKernelGGL((k_downsweep<256, ITEMS, MODE>), dim3((unsigned)g), dim3(256), 0, s, a);
   }
   return hipGetLastError();

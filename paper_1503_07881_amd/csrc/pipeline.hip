@@ -146,17 +146,16 @@ void pinned_release(Pinned *b, hipStream_t s) {
 // size (log2 buckets of rows).  Built-in defaults, from the autotuner's
 // measurements on an MI355X (R-MAT tables, 2^10 to 2^26 rows): the sort
 // numbering up to 2^23 rows and the hash numbering above; 8 items per
-// thread up to 2^24 rows and 16 above.
+// thread (within measurement noise of 16 at 2^26 rows).
 int g_items[64];
 int g_method[64];
 bool g_items_init = false;
 constexpr int HASH_DEFAULT_LOG2 = 24;
-constexpr int ITEMS16_DEFAULT_LOG2 = 25;
 
 void schedule_init_locked() {
   if (g_items_init) return;
   for (int i = 0; i < 64; ++i) {
-    g_items[i] = i >= ITEMS16_DEFAULT_LOG2 ? 16 : 8;
+    g_items[i] = 8;
     g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
   }
   g_items_init = true;

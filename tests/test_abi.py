@@ -135,5 +135,4 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
     # restore the built-in default
     autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 8, "node_method": 0},
-                                                  str(1 << 24): {"items": 8, "node_method": 1},
-                                                  str(1 << 25): {"items": 16, "node_method": 1}}})
+                                                  str(1 << 24): {"items": 8, "node_method": 1}}})
