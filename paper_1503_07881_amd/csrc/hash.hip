@@ -10,7 +10,7 @@
 //
 //   estimate   HyperLogLog count of the distinct keys of each table
 //              (Flajolet, Fusy, Gandouet & Meunier 2007), 2^10 registers;
-//              the host sizes each table's slots from it (load <= 1/2)
+//              the host sizes each table's slots from it (load <= 2/3)
 //   insert     every row's two keys, lock-free compare-and-swap into the
 //              first free slot of the probe sequence; the slot of every
 //              key is written out (32-bit, src then dst per table)
