@@ -26,7 +26,7 @@ FLAGS = [
 ]
 
 LIBS = {
-    "libringo.so": ["kernels.hip", "hash.hip", "to_table.hip", "pagerank.hip", "pipeline.hip", "serve.hip"],
+    "libringo.so": ["kernels.hip", "hash.hip", "to_table.hip", "pagerank.hip", "small.hip", "pipeline.hip", "serve.hip"],
     "libringo_gen.so": ["workloads.hip"],
 }
 

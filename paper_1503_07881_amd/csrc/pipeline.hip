@@ -84,7 +84,7 @@ void dev_free(const AllocHooks &h, void *p, hipStream_t s) {
 // Owner of the output arrays of one call (shared by the graphs of a batch).
 struct Owner {
   std::atomic<int> refs{0};
-  void *blocks[2] = {nullptr, nullptr};
+  void *blocks[3] = {nullptr, nullptr, nullptr};  // node-sized, edge-sized, small tables
   hipStream_t stream = nullptr;
   AllocHooks hooks;
 };
@@ -220,6 +220,12 @@ struct Call {
   uint32_t *hslots = nullptr;  // slot of every node key
   uint32_t *vals = nullptr;    // multigraph: rows carried through the sorts (2 x N)
   int kind = RINGO_GRAPH_DIRECTED;
+  // small tables converted in LDS (one workgroup each)
+  std::vector<int> small;        // their indices in the call
+  void *small_ws = nullptr;      // SmallTable array + V/E results
+  void *small_arena = nullptr;   // their outputs, until an Owner takes them
+  Pinned *spin = nullptr;        // staging of the SmallTable array and the results
+  std::vector<SmallTable> small_tabs;
   void *hmeta = nullptr;  // estimate registers, slot counts and flags of the hash tables
   uint32_t *counts = nullptr;
   uint32_t *bsum = nullptr;
@@ -233,8 +239,12 @@ struct Call {
 
   void release_workspace() {
     void *bufs[] = {A, B, status, base, counters, results, meta, dir, tab, hslots, hmeta, counts,
-                    bsum, vals};
+                    bsum, vals, small_ws, small_arena};
     for (void *b : bufs) dev_free(hooks, b, stream);
+    small_ws = nullptr;
+    small_arena = nullptr;
+    if (spin) pinned_release(spin, stream);
+    spin = nullptr;
     tab = nullptr;
     hslots = nullptr;
     vals = nullptr;
@@ -337,7 +347,7 @@ struct Call {
 enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
-  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_KINDS
+  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_KINDS
 };
 // "count" entries are the four small kernels of a pass's digit counting and
 // prefixes; every other entry is a single kernel.
@@ -346,7 +356,7 @@ const char *const kTraceNames[TK_KINDS] = {
     "remap_pack",        "sort_edge_count",   "sort_edge_scatter", "dedupe_out_csr",
     "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
-    "sort_vnode_scatter", "hash_rank",        "hash_remap_pack"};
+    "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables"};
 
 struct TraceRec {
   int kind;
@@ -424,6 +434,76 @@ int grid_for(int64_t tiles, int cap) {
 }
 
 
+// Launches the small tables of a call (c.small): worst-case-sized outputs in
+// one arena, the SmallTable array uploaded through pinned memory, one
+// workgroup per table, and the V/E results copied back to pinned memory on
+// the same stream (read after the call's next synchronisation).
+ringo_status_t launch_small_part(Call &c, const int64_t *const *src, const int64_t *const *dst,
+                                 const int64_t *num_rows) {
+  const int K = (int)c.small.size();
+  hipStream_t st = c.stream;
+  size_t arena = 0;
+  std::vector<size_t> off((size_t)5 * K);
+  for (int k = 0; k < K; ++k) {
+    const int64_t n = num_rows[c.small[k]];
+    const size_t sz[5] = {sizeof(int64_t) * 2 * n, sizeof(int64_t) * (2 * n + 1),
+                          sizeof(int64_t) * (2 * n + 1), sizeof(int32_t) * n, sizeof(int32_t) * n};
+    for (int f = 0; f < 5; ++f) {
+      off[(size_t)5 * k + f] = arena;
+      arena = align_up(arena + sz[f]);
+    }
+  }
+  const size_t tab_bytes = align_up(sizeof(SmallTable) * K);
+  c.small_arena = dev_alloc(c.hooks, arena, st);
+  c.small_ws = dev_alloc(c.hooks, tab_bytes + sizeof(int64_t) * 2 * K, st);
+  c.spin = pinned_acquire(tab_bytes + sizeof(int64_t) * 2 * K);
+  if (!c.small_arena || !c.small_ws || !c.spin) return RINGO_ERR_OUT_OF_MEMORY;
+  char *a = (char *)c.small_arena;
+  c.small_tabs.resize(K);
+  for (int k = 0; k < K; ++k) {
+    const int i = c.small[k];
+    SmallTable &T = c.small_tabs[k];
+    T.src = src[i];
+    T.dst = dst[i];
+    T.n = num_rows[i];
+    T.node_ids = (int64_t *)(a + off[(size_t)5 * k]);
+    T.out_off = (int64_t *)(a + off[(size_t)5 * k + 1]);
+    T.in_off = (int64_t *)(a + off[(size_t)5 * k + 2]);
+    T.out_nbr = (int32_t *)(a + off[(size_t)5 * k + 3]);
+    T.in_nbr = (int32_t *)(a + off[(size_t)5 * k + 4]);
+  }
+  std::memcpy(c.spin->p, c.small_tabs.data(), sizeof(SmallTable) * K);
+  int64_t *vres = (int64_t *)((char *)c.small_ws + tab_bytes);
+  HIP_TRY(hipMemcpyAsync(c.small_ws, c.spin->p, sizeof(SmallTable) * K, hipMemcpyHostToDevice, st));
+  TRACED(TK_SMALL, K, 0.0, launch_small((const SmallTable *)c.small_ws, K, vres, st));
+  HIP_TRY(hipMemcpyAsync((char *)c.spin->p + tab_bytes, vres, sizeof(int64_t) * 2 * K,
+                         hipMemcpyDeviceToHost, st));
+  return RINGO_OK;
+}
+
+// Fills the graphs of the small tables (after a synchronisation).
+void handoff_small(Call &c, const int64_t *num_rows, ringo_graph_t *outs, Owner *owner) {
+  const int K = (int)c.small.size();
+  const int64_t *vres = (const int64_t *)((char *)c.spin->p + align_up(sizeof(SmallTable) * K));
+  for (int k = 0; k < K; ++k) {
+    const SmallTable &T = c.small_tabs[k];
+    ringo_graph_t &g = outs[c.small[k]];
+    std::memset(&g, 0, sizeof(g));
+    g.num_rows = num_rows[c.small[k]];
+    g.num_nodes = vres[2 * k];
+    g.num_edges = vres[2 * k + 1];
+    g.node_ids = T.node_ids;
+    g.out_offsets = T.out_off;
+    g.out_nbrs = T.out_nbr;
+    g.in_offsets = T.in_off;
+    g.in_nbrs = T.in_nbr;
+    g.kind = RINGO_GRAPH_DIRECTED;
+    g._alloc = owner;
+  }
+  owner->blocks[2] = c.small_arena;
+  c.small_arena = nullptr;  // now owned by the graphs
+}
+
 ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst,
                    const int64_t *num_rows, ringo_graph_t *outs) {
   const int S = c.S;
@@ -432,15 +512,40 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   long unique_rec = -1, dedupe_rec = -1;
   int64_t sumV = 0, sumE = 0;
 
+  // ------------------------------------------------------- small tables
+  // Directed tables of at most SMALL_ROWS rows: one workgroup each, in LDS,
+  // launched first; the pass pipeline below sees them as empty.
+  c.small.clear();
+  // RINGO_SMALL_TABLES=0 (test support) sends every table through the pipeline
+  const char *small_env = std::getenv("RINGO_SMALL_TABLES");
+  if (c.kind == RINGO_GRAPH_DIRECTED && !(small_env && small_env[0] == '0'))
+    for (int i = 0; i < S; ++i)
+      if (num_rows[i] > 0 && num_rows[i] <= SMALL_ROWS) c.small.push_back(i);
+  std::vector<char> is_small(S, 0);
+  for (int i : c.small) is_small[i] = 1;
+  if (!c.small.empty()) {
+    const ringo_status_t rs = launch_small_part(c, src, dst, num_rows);
+    if (rs != RINGO_OK) return rs;
+    if ((int)c.small.size() == S) {  // nothing for the pipeline: one synchronisation
+      HIP_TRY(hipStreamSynchronize(st));
+      Owner *owner = new Owner();
+      owner->stream = st;
+      owner->hooks = c.hooks;
+      owner->refs.store(S);
+      handoff_small(c, num_rows, outs, owner);
+      return RINGO_OK;
+    }
+  }
+
   // ---------------------------------------------------------------- plan N
   c.plan.assign(S, SegPlan{});
   c.tmap.assign((size_t)TM_KINDS * (S + 1), 0);
   int64_t N = 0, max_rows = 0;
   for (int i = 0; i < S; ++i) {
     SegPlan &p = c.plan[i];
-    p.src = src[i];
-    p.dst = dst[i];
-    p.n = num_rows[i];
+    p.src = is_small[i] ? nullptr : src[i];
+    p.dst = is_small[i] ? nullptr : dst[i];
+    p.n = is_small[i] ? 0 : num_rows[i];
     p.row_off = N;
     N += p.n;
     max_rows = std::max(max_rows, p.n);
@@ -767,6 +872,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     g.out_eids = p.E > 0 ? p.out_eid : nullptr;
     g.in_eids = p.E > 0 ? p.in_eid : nullptr;
   }
+  if (!c.small.empty()) handoff_small(c, num_rows, outs, c.owner);
   c.owner = nullptr;  // now owned by the graphs
   return RINGO_OK;
 }

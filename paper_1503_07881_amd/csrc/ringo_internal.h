@@ -191,6 +191,27 @@ hipError_t launch_iota(const TileLaunch &rows, uint32_t *v, int grid, hipStream_
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
 int device_cu_count();
 
+// ------------------------------------------------ small tables (small.hip)
+
+constexpr int SMALL_ROWS = 2048;  // tables of at most this many rows fit one workgroup's LDS
+
+// One small table: its columns and worst-case-sized outputs (V <= 2n,
+// E <= n): node_ids [2n], out_off and in_off [2n + 1], out_nbr and in_nbr [n].
+struct SmallTable {
+  const int64_t *src;
+  const int64_t *dst;
+  int64_t n;
+  int64_t *node_ids;
+  int64_t *out_off;
+  int64_t *in_off;
+  int32_t *out_nbr;
+  int32_t *in_nbr;
+};
+
+// Converts count small tables (directed kind), one workgroup each; V and E
+// of table i go to vres[2i] and vres[2i + 1].
+hipError_t launch_small(const SmallTable *tabs, int count, int64_t *vres, hipStream_t s);
+
 // Stream-ordered device memory from the library's allocator (the caller's
 // hooks when set, else the device pool); used by the entry points other than
 // the conversion itself.

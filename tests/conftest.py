@@ -39,3 +39,13 @@ def method(request):
     yield request.param
     for e, (d, it, m) in enumerate(saved):
         ringo.tune_set(1 << e, d, it, m)
+
+
+@pytest.fixture(params=["lds", "pipeline"])
+def small_path(request):
+    """Runs the test with small tables converted in LDS (the default) and
+    with every table sent through the pass pipeline."""
+    if request.param == "pipeline":
+        os.environ["RINGO_SMALL_TABLES"] = "0"
+    yield request.param
+    os.environ.pop("RINGO_SMALL_TABLES", None)

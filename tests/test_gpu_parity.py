@@ -31,9 +31,9 @@ def gpu_graph(src, dst, dev):
     return g
 
 
-def test_hand_examples(cuda, method):
+def test_hand_examples(cuda, method, small_path):
     for ex in json.load(open(GOLDEN))["examples"]:
-        say("hand example", ex["name"], method)
+        say("hand example", ex["name"], method, small_path)
         src = np.array(ex["src"], dtype=np.int64)
         dst = np.array(ex["dst"], dtype=np.int64)
         g = gpu_graph(src, dst, cuda)
@@ -54,9 +54,9 @@ EDGE_SIZES = [1, 2, 3, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 819
 
 
 @pytest.mark.parametrize("n", EDGE_SIZES)
-def test_tile_boundaries(cuda, method, n):
+def test_tile_boundaries(cuda, method, small_path, n):
     for pool in (1, 7, max(1, n // 3), 4 * n):
-        say("tile boundary case n", n, "pool", pool, method)
+        say("tile boundary case n", n, "pool", pool, method, small_path)
         src, dst = random_table(n * 31 + pool, n, pool)
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"n={n} pool={pool}: ")
 
@@ -71,7 +71,7 @@ def test_random_small(cuda, method, seed):
     assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst))
 
 
-def test_special_structures(cuda, method):
+def test_special_structures(cuda, method, small_path):
     k = 61
     ids = np.array([workloads.mix64(i) - (1 << 63) for i in range(k)], dtype=np.int64)
     a, b = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
@@ -90,7 +90,7 @@ def test_special_structures(cuda, method):
                                                          dtype=np.int64)
         cases[f"path_V{V}"] = (vids, np.roll(vids, -1))
     for name, (src, dst) in cases.items():
-        say("special case", name, method)
+        say("special case", name, method, small_path)
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), name + ": ")
 
 
@@ -132,6 +132,23 @@ def test_batched_equals_singles_and_oracle(cuda, method):
         torch.cuda.synchronize()
         assert_same(gb[i], g1, f"table {i} batched vs single: ")
         assert_same(gb[i], oracle.table_to_graph(hs, hd), f"table {i} vs oracle: ")
+
+
+def test_small_tables_batched(cuda, method):
+    """Batches of small tables only (one workgroup each, one synchronisation)
+    and small tables among large ones, against the oracle."""
+    import torch
+    rng = np.random.default_rng(404)
+    sizes = [1, 2, 3, 64, 1000, 2047, 2048, 1500, 17, 999]
+    tables = [random_table(int(rng.integers(1 << 30)), n, max(1, n // 4)) for n in sizes]
+    big = [random_table(5, 9000, 700), random_table(6, 2049, 100)]
+    for label, tabs in (("small only", tables), ("mixed", tables + big)):
+        say("small tables batched:", label, method)
+        ts = [(torch.from_numpy(s).to(cuda), torch.from_numpy(d).to(cuda)) for s, d in tabs]
+        gb = ringo.to_graph_batched([s for s, _ in ts], [d for _, d in ts])
+        torch.cuda.synchronize()
+        for i, (hs, hd) in enumerate(tabs):
+            assert_same(gb[i], oracle.table_to_graph(hs, hd), f"{label} table {i}: ")
 
 
 @pytest.mark.parametrize("cap", [1, 64, 4096])
