@@ -498,6 +498,10 @@ def main():
                      "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     # the counter-measured bytes over the same launch time (line-granular
+                     # traffic of random accesses included), against the same peak
+                     "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBPS, 4) if traffic else None,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 5)},
         "ms_per_step_untraced": ms_untraced,
