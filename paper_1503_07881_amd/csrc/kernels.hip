@@ -13,11 +13,15 @@
 //   remap       every row's (src, dst) -> dense positions, packed into
 //               (s << b) | d with b = ceil(log2 V)
 //   edge keys   radix sort of the packed keys over their 2b low bits
-//   dedupe      adjacent compare + compaction -> unique edges, out-offsets
-//   in keys     repack to (d << 32) | s, stable radix sort on d only
+//   in keys     repack to (d << 32) | s, stable radix sort on d only; the
+//               first in-pass also drops repeated edges (first copy only)
+//               and writes out-neighbours and out-offsets
 //   in-CSR      in-neighbours + in-offsets
+//   dedupe      adjacent compare + compaction (undirected graphs,
+//               multigraph offsets)
 //
-// (hash.hip holds the alternative node numbering through a node hash table.)
+// (hash.hip holds the alternative node numbering through a node hash table,
+// small.hip the single-workgroup conversion of small tables.)
 //
 // Each radix pass is a tile-granular reduce-then-scan: an upsweep counts the
 // digits of every tile, a scan over tiles turns the counts into per-tile
@@ -578,14 +582,6 @@ static int resident_t() {
   return nb * device_cu_count();
 }
 
-int sort_resident_blocks(int items) {
-  switch (items) {
-    case 8: return resident_t<8>();
-    case 12: return resident_t<12>();
-    default: return resident_t<16>();
-  }
-}
-
 template <int ITEMS, int MODE>
 static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
   if (parts & SORT_PART_COUNT) {
@@ -636,9 +632,6 @@ hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts,
   }
 }
 
-hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s) {
-  return launch_sort_part(a, mode, items, SORT_PART_COUNT | SORT_PART_SCATTER, s);
-}
 
 // ------------------------------------------------------ unique (node set)
 //

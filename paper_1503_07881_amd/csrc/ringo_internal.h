@@ -75,7 +75,6 @@ __host__ __device__ inline int ceil_log2(int64_t x) {
 
 // ------------------------------------------------------------ kernel launchers
 
-struct Workspace;  // host-side view of the device buffers of one call
 
 struct SortLaunch {
   const uint64_t *in;
@@ -121,12 +120,10 @@ struct TileLaunch {
 
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
-hipError_t launch_sort_pass(const SortLaunch &a, int mode, int items, hipStream_t s);
 // One part of a pass: SORT_PART_COUNT (digit counts of every tile and their
 // prefixes) or SORT_PART_SCATTER (the stable scatter), or both.
 hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts, hipStream_t s);
 int sort_tile(int items);
-int sort_resident_blocks(int items);
 int64_t sort_runs(int64_t tiles);
 int64_t sort_runs_bound(int64_t max_tiles);  // >= sort_runs(t) for every t <= max_tiles
 hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
