@@ -105,9 +105,14 @@ typedef struct {
  *              the other arrays are NULL.
  *   out      : host struct filled on success (see ringo_graph_t).
  *   stream   : all device work is ordered on this stream.  The call
- *              synchronises with the stream twice to size its outputs
- *              (after the node set and after the edge set are known) and
- *              returns with the in-direction still enqueued.
+ *              synchronises with the stream to size its outputs: after the
+ *              node set and after the edge set are known, plus once before
+ *              the node hash table is sized (RINGO_NODES_HASH); it returns
+ *              with the in-direction still enqueued.  A table of at most
+ *              2048 rows is converted by one workgroup in LDS instead (one
+ *              launch, one synchronisation); its arrays are then sized for
+ *              the worst case (V <= 2n, E <= n), of which the first V,
+ *              V + 1 and E entries hold the graph.
  * Errors: RINGO_ERR_INVALID_ARG (NULL out, NULL src/dst with rows > 0,
  * rows out of range), RINGO_ERR_TOO_MANY_NODES, RINGO_ERR_OUT_OF_MEMORY,
  * RINGO_ERR_HIP.
@@ -122,8 +127,10 @@ ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int6
  *   num_rows : HOST array of num_tables row counts (each as above).
  *   outs     : HOST array of num_tables structs, filled on success.
  * Every phase of the pipeline runs once for the whole batch: one launch per
- * pass covers all tables, and the batch synchronises with the stream twice
- * in total.  outs[i] is bit-identical to ringo_table_to_graph on table i.
+ * pass covers all tables, and the batch synchronises with the stream as
+ * often as one call does.  Tables of at most 2048 rows (directed kind) are
+ * converted by one workgroup each, all in one launch beside the pipeline.
+ * outs[i] is bit-identical to ringo_table_to_graph on table i.
  * All-or-nothing: on error every outs[i] is zeroed.
  */
 ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,
@@ -144,6 +151,22 @@ ringo_status_t ringo_table_to_graph_batched_ex(int32_t num_tables, const int64_t
                                                const int64_t *const *dst, const int64_t *num_rows,
                                                int32_t kind, ringo_graph_t *outs,
                                                hipStream_t stream);
+
+/*
+ * Stable least-significant-digit radix sort of uint64 keys: the sort the
+ * conversion runs on its column copies (Section 2.4), exposed as a primitive.
+ * It takes ceil(bits / 8) passes of 8-bit digits, so keys are ordered by
+ * their low 8 * ceil(bits / 8) bits (all of them for bits = 64); keys equal
+ * in those bits keep their input order, and the higher bits travel with the
+ * keys.  For keys below 2^b, bits = b gives the full ascending order.
+ *   in, out : DEVICE arrays of n keys; they must not overlap.
+ *   n       : 0 <= n <= 2 * RINGO_MAX_ROWS.
+ *   bits    : 1..64.
+ * Enqueued on `stream` with stream-ordered workspace; no synchronisation.
+ * Errors: RINGO_ERR_INVALID_ARG, RINGO_ERR_OUT_OF_MEMORY, RINGO_ERR_HIP.
+ */
+ringo_status_t ringo_sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int32_t bits,
+                               hipStream_t stream);
 
 /* Releases the arrays of a graph and zeroes *g.  Idempotent; NULL is a no-op.
  * The caller must make sure no enqueued work still reads the arrays. */

@@ -434,6 +434,24 @@ int grid_for(int64_t tiles, int cap) {
 }
 
 
+// Largest V a table may have: RINGO_MAX_NODES (int32 neighbours), or less
+// under RINGO_TEST_MAX_NODES (test support: exercises the error path
+// without building a graph of 2^31 nodes).
+int64_t max_nodes() {
+  const char *e = std::getenv("RINGO_TEST_MAX_NODES");
+  const int64_t v = e ? std::atoll(e) : 0;
+  return v > 0 && v < RINGO_MAX_NODES ? v : (int64_t)RINGO_MAX_NODES;
+}
+
+// True when a small table's V exceeds the limit (results read back).
+bool small_too_many_nodes(const Call &c) {
+  const int K = (int)c.small.size();
+  const int64_t *vres = (const int64_t *)((char *)c.spin->p + align_up(sizeof(SmallTable) * K));
+  for (int k = 0; k < K; ++k)
+    if (vres[2 * k] > max_nodes()) return true;
+  return false;
+}
+
 // Launches the small tables of a call (c.small): worst-case-sized outputs in
 // one arena, the SmallTable array uploaded through pinned memory, one
 // workgroup per table, and the V/E results copied back to pinned memory on
@@ -528,6 +546,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     if (rs != RINGO_OK) return rs;
     if ((int)c.small.size() == S) {  // nothing for the pipeline: one synchronisation
       HIP_TRY(hipStreamSynchronize(st));
+      if (small_too_many_nodes(c)) return RINGO_ERR_TOO_MANY_NODES;
       Owner *owner = new Owner();
       owner->stream = st;
       owner->hooks = c.hooks;
@@ -668,8 +687,9 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   int64_t dir_words = 0;
   size_t arena1 = 0;
   std::vector<size_t> off1(3 * (size_t)S);
+  if (!c.small.empty() && small_too_many_nodes(c)) return RINGO_ERR_TOO_MANY_NODES;
   for (int i = 0; i < S; ++i) {
-    if (V[i] > RINGO_MAX_NODES) return RINGO_ERR_TOO_MANY_NODES;
+    if (V[i] > max_nodes()) return RINGO_ERR_TOO_MANY_NODES;
     SegPlan &p = c.plan[i];
     p.V = V[i];
     p.dirk = p.V > 0 ? ceil_log2(p.V) : 0;
@@ -877,6 +897,51 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   return RINGO_OK;
 }
 
+// Stable LSD sort of n keys by their low `bits` bits with the conversion's
+// radix passes (one table, plain mode); the last pass writes `out`.
+ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits, hipStream_t st) {
+  prepare_pool();
+  Call c;
+  c.S = 1;
+  c.stream = st;
+  c.hooks = hooks();
+  c.plan.assign(1, SegPlan{});
+  c.plan[0].n = n;
+  c.tmap.assign((size_t)TM_KINDS * 2, 0);
+  c.items = items_for(n);
+  c.sort_tile = sort_tile(c.items);
+  c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
+  const int64_t max_tiles = c.total(TM_ESORT) + 1;
+  const int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  c.meta_bytes = align_up(align_up(sizeof(SegPlan)) + sizeof(int64_t) * c.tmap.size());
+  c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t));
+  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
+  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * sort_runs_bound(max_tiles), st);
+  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * RADIX, st);
+  c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
+  c.A = passes > 1 ? (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * n, st) : nullptr;
+  ringo_status_t rc = RINGO_OK;
+  if (!c.pin || !c.counts || !c.bsum || !c.base || !c.meta || (passes > 1 && !c.A)) {
+    rc = RINGO_ERR_OUT_OF_MEMORY;
+  } else if (c.upload() != hipSuccess) {
+    rc = RINGO_ERR_HIP;
+  } else {
+    // destinations alternate so that the last pass lands in `out`
+    uint64_t *dst_of[2] = {(passes & 1) ? out : c.A, (passes & 1) ? c.A : out};
+    const uint64_t *src_p = in;
+    for (int p = 0; p < passes && rc == RINGO_OK; ++p) {
+      uint64_t *dst_p = dst_of[p & 1];
+      const SortLaunch a = c.sort_args(src_p, dst_p, TM_ESORT, RANGE_ROWS, passes, p, RADIX_BITS * p);
+      if (launch_sort_part(a, SORT_PLAIN, c.items, SORT_PART_COUNT | SORT_PART_SCATTER, st) !=
+          hipSuccess)
+        rc = RINGO_ERR_HIP;
+      src_p = dst_p;
+    }
+  }
+  c.release_workspace();
+  return rc;
+}
+
 ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *const *dst,
                        const int64_t *num_rows, int32_t kind, ringo_graph_t *outs,
                        hipStream_t stream) {
@@ -939,6 +1004,19 @@ ringo_status_t ringo_table_to_graph_batched_ex(int32_t num_tables, const int64_t
                                                int32_t kind, ringo_graph_t *outs,
                                                hipStream_t stream) {
   return convert(num_tables, src, dst, num_rows, kind, outs, stream);
+}
+
+ringo_status_t ringo_sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int32_t bits,
+                               hipStream_t stream) {
+  if (n < 0 || n > 2 * (int64_t)RINGO_MAX_ROWS || bits < 1 || bits > 64) return RINGO_ERR_INVALID_ARG;
+  if (n == 0) return RINGO_OK;
+  if (!in || !out) return RINGO_ERR_INVALID_ARG;
+  // overlapping arrays would be read and written by the same pass
+  const uintptr_t a0 = (uintptr_t)in, a1 = a0 + sizeof(uint64_t) * n;
+  const uintptr_t b0 = (uintptr_t)out, b1 = b0 + sizeof(uint64_t) * n;
+  if (a0 < b1 && b0 < a1) return RINGO_ERR_INVALID_ARG;
+  (void)hipGetLastError();
+  return sort_keys(in, out, n, bits, stream);
 }
 
 void ringo_graph_free(ringo_graph_t *g) {

@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = (
     "ringo_server_create", "ringo_server_submit", "ringo_server_poll", "ringo_server_release",
     "ringo_server_stats", "ringo_server_destroy",
     "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
-    "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex",
+    "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex", "ringo_sort_keys",
 )
 
 
@@ -126,6 +126,8 @@ def lib() -> ctypes.CDLL:
         L.ringo_graph_to_node_table.restype = ctypes.c_int
         L.ringo_pagerank.argtypes = [ctypes.POINTER(RawGraph), ctypes.c_double, ctypes.c_int32, p, p]
         L.ringo_pagerank.restype = ctypes.c_int
+        L.ringo_sort_keys.argtypes = [p, p, i64, ctypes.c_int32, p]
+        L.ringo_sort_keys.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -192,6 +194,22 @@ def graph_to_node_table_raw(g: RawGraph, ids_ptr: int, out_deg_ptr: int, in_deg_
 
 def pagerank_raw(g: RawGraph, damping: float, iterations: int, ranks_ptr: int, stream: int) -> None:
     _check(lib().ringo_pagerank(ctypes.byref(g), damping, iterations, ranks_ptr, stream), "ringo_pagerank")
+
+
+def sort_keys_raw(in_ptr: int, out_ptr: int, n: int, bits: int, stream: int) -> None:
+    _check(lib().ringo_sort_keys(in_ptr, out_ptr, n, bits, stream), "ringo_sort_keys")
+
+
+def sort_keys(keys: torch.Tensor, bits: int = 64, stream=None) -> torch.Tensor:
+    """Stable radix sort of int64 keys (as uint64 bit patterns) by their low
+    8 * ceil(bits / 8) bits (whole 8-bit digits); returns a new tensor."""
+    if not isinstance(keys, torch.Tensor) or keys.dtype != torch.int64 or keys.dim() != 1 or not keys.is_cuda:
+        raise TypeError("keys must be a 1-D int64 tensor on the GPU")
+    keys = keys.contiguous()
+    out = torch.empty_like(keys)
+    with torch.cuda.device(keys.device):
+        sort_keys_raw(keys.data_ptr(), out.data_ptr(), keys.numel(), bits, _stream_handle(stream))
+    return out
 
 
 def graph_free(g: RawGraph) -> None:

@@ -70,6 +70,17 @@ def test_invalid_arguments_rejected_on_host():
     assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(0.85), 10, None, None) == 1
     assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(1.5), 10, None, None) == 1
     assert L.ringo_pagerank(ctypes.byref(g), ctypes.c_double(0.85), -2, None, None) == 1
+    # sort primitive: argument checks on the host (the pointers are never read)
+    a, b = 0x10000, 0x10008
+    assert L.ringo_sort_keys(None, None, 0, 64, None) == 0
+    assert L.ringo_sort_keys(None, None, -1, 64, None) == 1
+    assert L.ringo_sort_keys(None, None, 5, 64, None) == 1
+    assert L.ringo_sort_keys(a, b, 5, 0, None) == 1
+    assert L.ringo_sort_keys(a, b, 5, 65, None) == 1
+    assert L.ringo_sort_keys(a, b, 2, 64, None) == 1        # out starts inside in
+    assert L.ringo_sort_keys(b, a, 2, 64, None) == 1        # in starts inside out
+    assert L.ringo_sort_keys(a, a, 1, 64, None) == 1        # in place
+    assert L.ringo_sort_keys(a, b, 1 << 33, 64, None) == 1  # above 2 * RINGO_MAX_ROWS
 
 
 def test_tune_schedule_roundtrip():

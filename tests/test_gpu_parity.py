@@ -170,6 +170,41 @@ def test_hash_overflow_falls_back_to_sort(cuda, cap):
 
 
 @pytest.mark.slow
+def test_too_many_nodes_limit(cuda, method, small_path, monkeypatch):
+    """The node-count limit (RINGO_MAX_NODES, int32 neighbours) lowered
+    through the RINGO_TEST_MAX_NODES hook: a table over it fails with
+    TOO_MANY_NODES (alone and in a batch, all-or-nothing, outputs zeroed), a
+    table at it converts, and the library works on afterwards."""
+    import ctypes
+    import torch
+    rng = np.random.default_rng(77)
+    for rows in (300, 9000):  # LDS-sized and pipeline-sized tables
+        src = rng.integers(0, 1 << 40, rows, dtype=np.int64)
+        dst = rng.integers(0, 1 << 40, rows, dtype=np.int64)
+        V = np.unique(np.concatenate([src, dst])).size
+        s, d = (torch.from_numpy(a).to(cuda) for a in (src, dst))
+        say("node limit", rows, "rows", V, "nodes", method, small_path)
+        monkeypatch.setenv("RINGO_TEST_MAX_NODES", str(V - 1))
+        with pytest.raises(ringo.RingoError) as err:
+            ringo.to_graph(s, d)
+        assert err.value.status == 2
+        # a batch with one table over the limit: every output zeroed
+        ok_s, ok_d = s[:5].contiguous(), d[:5].contiguous()
+        P = (ctypes.c_void_p * 2)(ok_s.data_ptr(), s.data_ptr())
+        Q = (ctypes.c_void_p * 2)(ok_d.data_ptr(), d.data_ptr())
+        N = (ctypes.c_int64 * 2)(5, rows)
+        outs = (ringo.RawGraph * 2)()
+        rc = ringo.lib().ringo_table_to_graph_batched(2, P, Q, N, outs, torch.cuda.current_stream().cuda_stream)
+        assert rc == 2
+        assert all(o.num_nodes == 0 and o.node_ids is None and o.out_nbrs is None for o in outs)
+        monkeypatch.setenv("RINGO_TEST_MAX_NODES", str(V))
+        g = ringo.to_graph(s, d)
+        torch.cuda.synchronize()
+        assert g.num_nodes == V
+        monkeypatch.delenv("RINGO_TEST_MAX_NODES")
+        assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), "after the limit: ")
+
+
 def test_config2_full_size(cuda):
     """The 2^26-row R-MAT workload at full size, in the configuration the
     benchmark times: complete invariants (torch on the device) and the exact

@@ -1,0 +1,108 @@
+"""The radix sort primitive (ringo_sort_keys) on the GPU through the C ABI:
+the conversion's LSD passes (Section 2.4 sorts the column copies) against a
+stable sort by the same key bits (numpy's stable argsort), bit-exact, across
+tile and run boundaries, digit counts and key distributions."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1503_07881_amd import ringo
+
+pytestmark = pytest.mark.gpu
+
+TILE = 2048  # 256 threads x 8 items: the scatter tile at the default schedule
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def expected(keys: np.ndarray, bits: int) -> np.ndarray:
+    """Stable sort by the low 8 * ceil(bits / 8) bits; higher bits ride along."""
+    width = 8 * ((bits + 7) // 8)
+    u = keys.view(np.uint64)
+    k = u if width == 64 else u & np.uint64((1 << width) - 1)
+    return keys[np.argsort(k, kind="stable")]
+
+
+def run(keys: np.ndarray, bits: int, dev) -> np.ndarray:
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(keys, dtype=np.int64)).to(dev)
+    out = ringo.sort_keys(t, bits)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def keys_of(kind: str, n: int, bits: int, rng) -> np.ndarray:
+    full = rng.integers(-(1 << 63), (1 << 63) - 1, n, dtype=np.int64, endpoint=True)
+    width = 8 * ((bits + 7) // 8)
+    low = np.uint64((1 << width) - 1) if width < 64 else np.uint64(~np.uint64(0))
+    if kind == "uniform":
+        return full
+    if kind == "few":  # 17 distinct low parts, distinct high parts: stability shows
+        low_vals = rng.integers(0, 1 << min(bits, 62), 17, dtype=np.int64)
+        v = low_vals[rng.integers(0, 17, n)].view(np.uint64)
+        hi = full.view(np.uint64) & ~low
+        return (hi | (v & low)).view(np.int64)
+    if kind == "equal":  # one low part for all: output = input order
+        hi = full.view(np.uint64) & ~low
+        return (hi | (np.uint64(0x5A5A5A5A5A5A5A5A) & low)).view(np.int64)
+    if kind == "sorted":
+        return expected(full, bits)
+    if kind == "reverse":
+        return expected(full, bits)[::-1].copy()
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("n", [1, 2, TILE - 1, TILE, TILE + 1, 4 * TILE - 1, 4 * TILE + 1,
+                               100_000, (1 << 20) + 3])
+def test_sizes_across_tiles(cuda, n):
+    rng = np.random.default_rng(1000 + n)
+    for bits in (8, 64):
+        say("sort_keys n", n, "bits", bits)
+        keys = keys_of("uniform", n, bits, rng)
+        assert np.array_equal(run(keys, bits, cuda), expected(keys, bits)), (n, bits)
+
+
+@pytest.mark.parametrize("bits", [1, 7, 8, 9, 16, 22, 31, 32, 44, 63, 64])
+def test_bit_widths(cuda, bits):
+    rng = np.random.default_rng(2000 + bits)
+    n = 3 * TILE * 8 + 11
+    for kind in ("uniform", "few"):
+        say("sort_keys bits", bits, kind)
+        keys = keys_of(kind, n, bits, rng)
+        assert np.array_equal(run(keys, bits, cuda), expected(keys, bits)), (bits, kind)
+
+
+@pytest.mark.parametrize("kind", ["few", "equal", "sorted", "reverse"])
+def test_distributions(cuda, kind):
+    rng = np.random.default_rng(3000 + len(kind))
+    for bits in (16, 40, 64):
+        n = 250_001
+        say("sort_keys", kind, "bits", bits)
+        keys = keys_of(kind, n, bits, rng)
+        got = run(keys, bits, cuda)
+        assert np.array_equal(got, expected(keys, bits)), (kind, bits)
+        if kind == "equal":
+            assert np.array_equal(got, keys)  # a stable sort keeps the order
+
+
+def test_large(cuda):
+    rng = np.random.default_rng(4000)
+    n = (1 << 24) + 5
+    say("sort_keys large n", n)
+    keys = rng.integers(-(1 << 63), (1 << 63) - 1, n, dtype=np.int64, endpoint=True)
+    assert np.array_equal(run(keys, 64, cuda), expected(keys, 64))
+
+
+def test_empty_and_invalid(cuda):
+    import torch
+    e = torch.empty(0, dtype=torch.int64, device=cuda)
+    assert ringo.sort_keys(e).numel() == 0
+    t = torch.arange(10, dtype=torch.int64, device=cuda)
+    with pytest.raises(ringo.RingoError):
+        ringo.sort_keys_raw(t.data_ptr(), t.data_ptr() + 8, 4, 64, 0)  # overlapping
+    with pytest.raises(ringo.RingoError):
+        ringo.sort_keys(t, 0)
