@@ -172,6 +172,8 @@ constexpr int NUM_XCD = 8;    // accelerator complex dies of the MI355X
 // s_waitcnt immediate: lgkmcnt(0), vmcnt and expcnt left at their maxima
 constexpr int LGKMCNT_0 = 0xC07F;
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
@@ -214,56 +216,75 @@ struct TileHeader {
 // the block only meets once, to add up the four waves' sums over its run of
 // run_tiles tiles.  LDS atomics of a wave are not ordered with its later LDS
 // reads and writes, so the wave waits for its LDS operations to complete
-// (lgkmcnt(0)) between clearing, counting and reading the histogram.
+// (lgkmcnt(0)) between clearing, counting and reading the histogram.  Plain
+// passes read their keys in place two per lane (16-byte loads) where the
+// tile's first key is 16-byte aligned.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, int run_tiles) {
-  constexpr int W = 4, U = 8;
-  __shared__ uint32_t s_h[W * RADIX];
+  // Every wave counts its tiles in a private LDS histogram whose bins are
+  // split over SUB sub-counters (lane % SUB, adjacent words): lanes with an
+  // equal digit (clustered identifiers) meet at most 64 / SUB to a counter,
+  // and a plain atomic add per key costs less than finding the runs.
+  constexpr int W = 4, U = 16, U2 = 4, SUB = 4;
+  // the passes that read their keys from elsewhere, or compare neighbours
+  constexpr bool FIRST = MODE == SORT_NODE_FIRST || MODE == SORT_IN_FIRST ||
+                         MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_FIRST_DEDUP;
+  __shared__ uint4 s_h4[W * RADIX];
+  uint32_t *s_h = (uint32_t *)s_h4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
   const int64_t t0 = (int64_t)blockIdx.x * run_tiles;
   const int64_t t1 = std::min<int64_t>(t0 + run_tiles, a.total_tiles);
   TileHeader H;
   uint32_t run_sum[RADIX / 64] = {0, 0, 0, 0};
-  uint32_t *h = s_h + wave * RADIX;
+  uint4 *h4 = s_h4 + wave * RADIX;  // h4[d] = the SUB counters of digit d
+  uint32_t *h = s_h + wave * RADIX * SUB + (lane & (SUB - 1));
   for (int64_t t = t0 + wave; t < t1; t += W) {
 #pragma unroll
-    for (int j = 0; j < RADIX / 64; ++j) h[lane + 64 * j] = 0;
+    for (int j = 0; j < RADIX / 64; ++j) h4[lane + 64 * j] = make_uint4(0, 0, 0, 0);
     __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
     __builtin_amdgcn_wave_barrier();
     H.at(a, t);
     const int64_t k0 = (t - H.first) * tile_keys;
     const int64_t k1 = std::min<int64_t>(k0 + tile_keys, H.count);
-    for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
-      uint64_t k[U];
+    if (!FIRST && ((uintptr_t)(a.in + H.start + k0) & 15) == 0) {
+      // keys read in place, two per lane (16-byte loads); an odd last key
+      // on its own
+      const int cnt = (int)(k1 - k0);
+      const int np = cnt >> 1;
+      const __attribute__((address_space(1))) u64x2 *p2 =
+          (const __attribute__((address_space(1))) u64x2 *)(G(a.in) + H.start + k0);
+      for (int q0 = lane; q0 < np; q0 += U2 * 64) {
+        u64x2 k[U2];
 #pragma unroll
-      for (int j = 0; j < U; ++j)
-        k[j] = pass_key<MODE>(a, H.P, H.start, std::min<int64_t>(e0 + j * 64, k1 - 1));
+        for (int j = 0; j < U2; ++j) k[j] = p2[std::min(q0 + j * 64, np - 1)];
 #pragma unroll
-      for (int j = 0; j < U; ++j) {
-        // Lanes hold consecutive keys: a run of equal digits over
-        // neighbouring valid lanes (clustered identifiers after the first
-        // passes) is added once, by the lane that starts it.
-        const int64_t e = e0 + j * 64;
-        bool valid = e < k1;
-        if (MODE == SORT_IN_FIRST_DEDUP) {
-          // only the first copy of every key counts
-          uint64_t prev = __shfl_up(k[j], 1, 64);
-          // lane 0 reads its predecessor, only for elements inside the tile
-          if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
-          valid = valid && (e == 0 || k[j] != prev);
-        }
-        const uint32_t d = (uint32_t)(k[j] >> shift) & (RADIX - 1);
-        const uint32_t dp = __shfl_up(d, 1, 64);
-        const uint64_t vmask = __ballot(valid);
-        const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
-        const uint64_t heads = __ballot(valid && (lane == 0 || d != dp || !prev_valid));
-        if ((heads >> lane) & 1ull) {
-          // the run ends at the next run head or invalid lane above this one
-          const uint64_t stop = heads | ~vmask;
-          const uint64_t after = lane < 63 ? stop & ~((2ull << lane) - 1) : 0ull;
-          const int end = after ? __builtin_ctzll(after) : 64;
-          atomicAdd(&h[d], (uint32_t)(end - lane));
+        for (int j = 0; j < U2; ++j)
+          if (q0 + j * 64 < np) {
+            atomicAdd(&h[((uint32_t)(k[j].x >> shift) & (RADIX - 1)) * SUB], 1u);
+            atomicAdd(&h[((uint32_t)(k[j].y >> shift) & (RADIX - 1)) * SUB], 1u);
+          }
+      }
+      if ((cnt & 1) && lane == 0)
+        atomicAdd(&h[((uint32_t)(G(a.in)[H.start + k1 - 1] >> shift) & (RADIX - 1)) * SUB], 1u);
+    } else {
+      for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
+        uint64_t k[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+          k[j] = pass_key<MODE>(a, H.P, H.start, std::min<int64_t>(e0 + j * 64, k1 - 1));
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const int64_t e = e0 + j * 64;
+          bool valid = e < k1;
+          if (MODE == SORT_IN_FIRST_DEDUP) {
+            // only the first copy of every key counts
+            uint64_t prev = __shfl_up(k[j], 1, 64);
+            // lane 0 reads its predecessor, only for elements inside the tile
+            if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
+            valid = valid && (e == 0 || k[j] != prev);
+          }
+          if (valid) atomicAdd(&h[((uint32_t)(k[j] >> shift) & (RADIX - 1)) * SUB], 1u);
         }
       }
     }
@@ -271,14 +292,15 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int j = 0; j < RADIX / 64; ++j) {
-      const uint32_t v = h[lane + 64 * j];
+      const uint4 c = h4[lane + 64 * j];
+      const uint32_t v = c.x + c.y + c.z + c.w;
       a.counts[t * RADIX + lane + 64 * j] = v;
       run_sum[j] += v;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < RADIX / 64; ++j) h[lane + 64 * j] = run_sum[j];
+  for (int j = 0; j < RADIX / 64; ++j) s_h[wave * RADIX + lane + 64 * j] = run_sum[j];
   __syncthreads();
   uint32_t v = 0;
 #pragma unroll
@@ -318,10 +340,17 @@ __global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a, int run_til
   const int64_t t0 = (int64_t)blockIdx.x * run_tiles;
   const int64_t t1 = std::min<int64_t>(t0 + run_tiles, a.total_tiles);
   uint32_t run = a.bsum[(int64_t)blockIdx.x * RADIX + d];
-  for (int64_t t = t0; t < t1; ++t) {
-    const uint32_t v = a.counts[t * RADIX + d];
-    a.counts[t * RADIX + d] = run;
-    run += v;
+  // C tiles at a time: their loads are in flight together
+  constexpr int C = 8;
+  for (int64_t t = t0; t < t1; t += C) {
+    uint32_t v[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = t + i < t1 ? a.counts[(t + i) * RADIX + d] : 0u;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      if (t + i < t1) a.counts[(t + i) * RADIX + d] = run;
+      run += v[i];
+    }
   }
 }
 
@@ -798,7 +827,6 @@ hipError_t launch_dir(const TileLaunch &t, const uint64_t *nodes, DirEntry *dir,
 // key (s << b) | d.  Keys that open their bucket are found by the directory
 // read alone; the others by a binary search inside the bucket.  All keys of
 // a thread advance together so that their loads overlap.
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 template <int K>
 __device__ __forceinline__ void node_rank_n(const uint64_t *nd, const DirEntry *D, uint64_t lo,
