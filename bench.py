@@ -83,6 +83,39 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
+CONVERSION_SOURCES = ("kernels.hip", "hash.hip", "pipeline.hip", "device_common.h")
+
+
+def conversion_source_sha() -> str:
+    """Digest of every source that decides which kernels one conversion runs
+    and how they touch memory."""
+    h = hashlib.sha256()
+    for name in CONVERSION_SOURCES:
+        with open(os.path.join(KERNEL_DIR, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def read_conversion_traffic(workload: str):
+    """HBM bytes (fetched + written) of one whole conversion on `workload`,
+    summed over all of its kernels, from the committed rocprofv3 counter
+    summary; None when the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_conversion_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("conversion_source_sha") != conversion_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_conversion"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(rows: int):
     import numpy as np  # noqa: F401
     import oracle
@@ -473,6 +506,8 @@ def main():
     workload = (f"{spec.kind}_scale{spec.scale}_rows{n}" if spec.kind == "rmat"
                 else f"uniform_rows{n}_pool{spec.pool}")
     traffic = read_traffic(dom, workload)
+    conv_bytes = read_conversion_traffic(workload) if args.kind == "directed" else None
+    io_min = 16 * n + 24 * V + 8 + 8 * E
     items = ringo.tune_get(n)[1]
 
     out = {
@@ -505,6 +540,14 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 5)},
         "ms_per_step_untraced": ms_untraced,
+        # every kernel of one conversion together: counter-measured HBM bytes
+        # over the untraced conversion time
+        "conversion_traffic": ({"bytes": conv_bytes, "GBps": round(conv_bytes / (ms_untraced / 1e3) / 1e9, 1),
+                                "frac": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                               if conv_bytes else None),
+        # reading the table once and writing the graph once: 16n + 24V + 8 + 8E bytes
+        "io_minimum": {"bytes": io_min, "GBps": round(io_min / (ms_untraced / 1e3) / 1e9, 1),
+                       "frac": round(io_min / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)},
         "copy_kernel_GBps": round(copy_gbps, 1),
         "kernels": kernels,
     }
