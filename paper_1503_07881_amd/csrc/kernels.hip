@@ -160,7 +160,9 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
 //   block scan   exclusive prefix of the run counts, per digit
 //   tile prefix  exclusive prefix of the tile counts, per digit: the
 //                position of a tile's first key of each digit, relative to
-//                the first tile of its table
+//                the first tile of its table (passes of at most
+//                SMALL_SCAN_TILES tiles do both scans in one kernel)
+//   seg base     every table's digit bases
 //   downsweep    wave-ballot stable rank inside the tile, LDS staging in
 //                digit order, contiguous write-out of every digit run
 // No block waits on another.  Tiles in flight are always neighbours in
@@ -352,6 +354,37 @@ __global__ __launch_bounds__(RADIX) void k_tile_prefix(SortLaunch a, int run_til
       run += v[i];
     }
   }
+}
+
+// Small passes (at most SMALL_SCAN_TILES tiles): the run scan and the tile
+// prefixes in one kernel, one block per digit.  Each thread takes a
+// contiguous group of tiles; the block scan of the group sums gives each
+// group's start.  Same result as k_block_scan followed by k_tile_prefix.
+constexpr int SMALL_SCAN_TILES = 16 * 256;
+
+__global__ __launch_bounds__(256) void k_scan_small(SortLaunch a) {
+  __shared__ uint32_t s_w[4];
+  const int d = blockIdx.x, tid = threadIdx.x;
+  const int64_t T = a.total_tiles;
+  const int64_t per = (T + 255) / 256;
+  const int64_t t0 = std::min<int64_t>(tid * per, T), t1 = std::min<int64_t>(t0 + per, T);
+  uint32_t v[16];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    v[i] = t0 + i < t1 ? a.counts[(t0 + i) * RADIX + d] : 0u;
+    sum += v[i];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan<256>(sum, s_w, total);
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (t0 + i < t1) {
+      a.counts[(t0 + i) * RADIX + d] = run;
+      run += v[i];
+    }
+  // sentinel row: prefix one past the last tile
+  if (tid == 0) a.counts[T * RADIX + d] = total;
 }
 
 // Digit bases of every table for this pass: the table's digit totals are
@@ -618,8 +651,12 @@ static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
     const int64_t runs = (a.total_tiles + rt - 1) / rt;
     hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS,
                        rt);
-    hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
-    hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
+    if (a.total_tiles <= SMALL_SCAN_TILES) {
+      hipLaunchKernelGGL(k_scan_small, dim3(RADIX), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL(k_block_scan, dim3(RADIX), dim3(1024), 0, s, a, runs);
+      hipLaunchKernelGGL(k_tile_prefix, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
+    }
     hipLaunchKernelGGL(k_seg_base, dim3(a.num_segs), dim3(RADIX), 0, s, a);
   }
   if (parts & SORT_PART_SCATTER) {

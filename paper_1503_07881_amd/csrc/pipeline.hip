@@ -349,8 +349,8 @@ enum TraceKind {
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
   TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_KINDS
 };
-// "count" entries are the four small kernels of a pass's digit counting and
-// prefixes; every other entry is a single kernel.
+// "count" entries are the small kernels of a pass's digit counting and
+// prefixes (three or four); every other entry is a single kernel.
 const char *const kTraceNames[TK_KINDS] = {
     "sort_node_count",   "sort_node_scatter", "unique",          "directory",
     "remap_pack",        "sort_edge_count",   "sort_edge_scatter", "dedupe_out_csr",
