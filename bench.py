@@ -361,7 +361,8 @@ def bench_serve(args):
     runs = {}
     for frac in (0.5, 0.8):
         arrivals = workloads.config5_arrivals(n_req + warm, frac * mu)
-        with serve.Server(budget, num_streams=args.serve_streams, max_batch_tables=16) as srv:
+        with serve.Server(budget, num_streams=args.serve_streams, max_batch_tables=16,
+                          max_batch_rows=args.serve_batch_rows) as srv:
             cb = serve.replay(srv, trace, arrivals, warmup=warm).summary()
         with serve.Server(budget, num_streams=1, max_batch_tables=1) as fifo:
             ff = serve.replay(fifo, trace, arrivals, warmup=warm).summary()
@@ -375,7 +376,8 @@ def bench_serve(args):
         "ms_per_step": hi["mean_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic (seeded uniform and R-MAT request tables, pinned host memory)",
         "config": {"workload": "serve_poisson_rows_1e4_to_5e7", "pool_tables": pool, "requests": n_req,
-                   "budget_bytes": budget, "streams": args.serve_streams},
+                   "budget_bytes": budget, "streams": args.serve_streams,
+                   "max_batch_rows": args.serve_batch_rows},
         "p99_ms": hi["p99_ms"], "edges_per_s": hi["edges_per_s"], "capacity_one_at_a_time_per_s": mu,
         "runs": runs,
     }
@@ -391,7 +393,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=100)
-    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-batch-rows", type=int, default=8 << 20,
+                    help="rows a batch may hold (a larger request runs alone)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kind", default="directed", choices=("directed", "undirected", "multi"),

@@ -56,8 +56,8 @@ def _lib():
 class Server:
     """A running server on the current device."""
 
-    def __init__(self, budget_bytes: int = 200 << 30, num_streams: int = 2, max_batch_tables: int = 16,
-                 max_batch_rows: int = 64 << 20):
+    def __init__(self, budget_bytes: int = 200 << 30, num_streams: int = 3, max_batch_tables: int = 16,
+                 max_batch_rows: int = 8 << 20):
         self._cfg = ServerConfig(budget_bytes, num_streams, max_batch_tables, max_batch_rows)
         h = ctypes.c_void_p()
         rc = _lib().ringo_server_create(ctypes.byref(self._cfg), ctypes.byref(h))
