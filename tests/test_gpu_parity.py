@@ -61,6 +61,22 @@ def test_tile_boundaries(cuda, method, small_path, n):
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"n={n} pool={pool}: ")
 
 
+@pytest.mark.parametrize("n", [(1 << 22) - 1, 1 << 22, (1 << 22) + 1])
+def test_scan_paths_boundary(cuda, n):
+    """Sort numbering of 2n node keys at 4096 tiles of 2048: the node passes
+    sit on both sides of the switch between the one-kernel scan of small
+    passes and the run scan plus tile prefixes."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    try:
+        ringo.set_node_method(ringo.NODES_SORT)
+        say("scan boundary conversion n", n)
+        src, dst = random_table(n + 11, n, 1 << 20)
+        assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"n={n}: ")
+    finally:
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_small(cuda, method, seed):
     rng = np.random.default_rng(1000 + seed)
@@ -156,6 +172,7 @@ def test_hash_overflow_falls_back_to_sort(cuda, cap):
     """Node hash tables capped far below V (forced from the host): every probe
     sequence stops at its bound, the call numbers the nodes by sorting, and
     the graph is still the oracle's.  Tables that fit keep the hash path."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
     try:
         os.environ["RINGO_HASH_TEST_CAPACITY"] = str(cap)
         ringo.set_node_method(ringo.NODES_HASH)
@@ -165,8 +182,8 @@ def test_hash_overflow_falls_back_to_sort(cuda, cap):
             assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"cap={cap} n={n}: ")
     finally:
         del os.environ["RINGO_HASH_TEST_CAPACITY"]
-        ringo.set_node_method(ringo.NODES_SORT)
-        ringo.set_node_method(ringo.NODES_HASH, 1 << 20)
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
 
 
 @pytest.mark.slow

@@ -89,6 +89,16 @@ def test_distributions(cuda, kind):
             assert np.array_equal(got, keys)  # a stable sort keeps the order
 
 
+@pytest.mark.parametrize("n", [4096 * TILE - 1, 4096 * TILE, 4096 * TILE + 1])
+def test_scan_paths_boundary(cuda, n):
+    """Passes of at most 4096 tiles scan their counts in one kernel, larger
+    ones in two: both sides of the switch."""
+    rng = np.random.default_rng(5000 + n % 7)
+    say("sort_keys scan boundary n", n)
+    keys = keys_of("few", n, 24, rng)
+    assert np.array_equal(run(keys, 24, cuda), expected(keys, 24))
+
+
 def test_large(cuda):
     rng = np.random.default_rng(4000)
     n = (1 << 24) + 5
