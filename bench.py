@@ -32,7 +32,8 @@ KERNEL_DIR = os.path.join(ROOT, "paper_1503_07881_amd", "csrc")
 # 3 node, 4 distinct nodes, 5 edge, 2 in (first pass), 6 in.
 ROCPROF_NAME = {
     "hash_estimate": "k_hll", "hash_insert": "k_hash_insert", "hash_compact": "k_hash_compact",
-    "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "unique": "k_unique",
+    "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
+    "unique": "k_unique",
     "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe", "in_csr": "k_in_csr",
     "sort_node_scatter": "k_downsweep<256, {items}, 1|3>", "sort_vnode_scatter": "k_downsweep<256, {items}, 4>",
     "sort_edge_scatter": "k_downsweep<256, {items}, 5>", "sort_in_scatter": "k_downsweep<256, {items}, 2|6>",

@@ -224,11 +224,136 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
   }
 }
 
+// Exclusive scan of the bucket counts (bstart [NBUCKETS + 1], bcur a copy of
+// its first NBUCKETS entries), the largest bucket into *max_bucket and the
+// total into *count.
+__global__ __launch_bounds__(1024) void k_bucket_plan(const uint32_t *bcnt, uint32_t *bstart,
+                                                      uint32_t *bcur, int64_t *max_bucket,
+                                                      uint64_t *count) {
+  __shared__ uint32_t s_w[16];
+  __shared__ uint32_t s_m[16];
+  constexpr int PER = NBUCKETS / 1024;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t v[PER], sum = 0, mx = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    v[i] = bcnt[tid * PER + i];
+    sum += v[i];
+    mx = std::max(mx, v[i]);
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan<1024>(sum, s_w, total);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    bstart[tid * PER + i] = run;
+    bcur[tid * PER + i] = run;
+    run += v[i];
+  }
+  if (tid == 0) {
+    bstart[NBUCKETS] = total;
+    *count = total;  // the table's distinct keys
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = std::max(mx, (uint32_t)__shfl_down((int)mx, o, 64));
+  if (lane == 0) s_m[w] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t m = 0;
+    for (int i = 0; i < 16; ++i) m = std::max(m, s_m[i]);
+    *max_bucket = m;
+  }
+}
+
 hipError_t launch_hash_insert(const TileLaunch &rows, uint64_t *hkeys, uint32_t *slots,
                               uint32_t *flags, int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_insert, dim3(grid), dim3(256), 0, s, rows, hkeys, slots, flags);
   return hipGetLastError();
+}
+
+// Bucketed placement of one table's keys, by BP_BLOCKS blocks that each own a
+// contiguous range of slots (the same ranges in both kernels):
+//   count   keys per bucket, in LDS, added to bcnt once per block and bucket
+//   place   after the scan of bcnt: each block reserves its range in every
+//           bucket it holds keys of with one atomic, then places its keys
+//           with LDS cursors (key to nodes, slot to bslot)
+constexpr int BP_BLOCKS = 128;
+constexpr int BP_THREADS = 1024;
+
+__device__ __forceinline__ void slot_range(const SegPlan &P, int64_t &s0, int64_t &s1) {
+  const int64_t per = (P.tab_cap + BP_BLOCKS - 1) / BP_BLOCKS;
+  s0 = std::min<int64_t>((int64_t)blockIdx.x * per, P.tab_cap);
+  s1 = std::min<int64_t>(s0 + per, P.tab_cap);
+}
+
+__global__ __launch_bounds__(BP_THREADS) void k_bucket_count(const SegPlan *plan,
+                                                             const uint64_t *hkeys,
+                                                             uint32_t *bcnt) {
+  __shared__ uint32_t h[NBUCKETS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NBUCKETS; i += BP_THREADS) h[i] = 0;
+  __syncthreads();
+  const SegPlan P = plan[0];
+  const uint64_t *T = hkeys + P.tab_off;
+  int64_t s0, s1;
+  slot_range(P, s0, s1);
+  constexpr int U = 8;
+  for (int64_t i0 = s0 + tid; i0 < s1; i0 += U * BP_THREADS) {
+    uint64_t k[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) k[j] = G(T)[std::min<int64_t>(i0 + j * BP_THREADS, s1 - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (i0 + j * BP_THREADS < s1 && k[j] != EMPTY_KEY)
+        atomicAdd(&h[k[j] >> (64 - BUCKET_BITS)], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < NBUCKETS; i += BP_THREADS)
+    if (h[i]) atomicAdd(&bcnt[i], h[i]);
+}
+
+__global__ __launch_bounds__(BP_THREADS) void k_bucket_place(const SegPlan *plan,
+                                                             const uint64_t *hkeys,
+                                                             uint32_t *bcur, uint64_t *nodes,
+                                                             uint32_t *bslot) {
+  __shared__ uint32_t h[NBUCKETS];  // this block's keys per bucket, then its cursors
+  __shared__ uint32_t base[NBUCKETS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NBUCKETS; i += BP_THREADS) h[i] = 0;
+  __syncthreads();
+  const SegPlan P = plan[0];
+  const uint64_t *T = hkeys + P.tab_off;
+  int64_t s0, s1;
+  slot_range(P, s0, s1);
+  constexpr int U = 8;
+  for (int64_t i0 = s0 + tid; i0 < s1; i0 += U * BP_THREADS) {
+    uint64_t k[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) k[j] = G(T)[std::min<int64_t>(i0 + j * BP_THREADS, s1 - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (i0 + j * BP_THREADS < s1 && k[j] != EMPTY_KEY)
+        atomicAdd(&h[k[j] >> (64 - BUCKET_BITS)], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < NBUCKETS; i += BP_THREADS) {
+    const uint32_t c = h[i];
+    base[i] = c ? atomicAdd(&bcur[i], c) : 0u;
+    h[i] = 0;
+  }
+  __syncthreads();
+  for (int64_t i0 = s0 + tid; i0 < s1; i0 += U * BP_THREADS) {
+    uint64_t k[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) k[j] = G(T)[std::min<int64_t>(i0 + j * BP_THREADS, s1 - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (i0 + j * BP_THREADS < s1 && k[j] != EMPTY_KEY) {
+        const uint32_t bk = (uint32_t)(k[j] >> (64 - BUCKET_BITS));
+        const uint32_t pos = base[bk] + atomicAdd(&h[bk], 1u);
+        G(nodes)[pos] = k[j];
+        G(bslot)[pos] = (uint32_t)(i0 + j * BP_THREADS);
+      }
+  }
 }
 
 // -------------------------------------------------------------- compact
@@ -288,10 +413,21 @@ __global__ void k_hash_finish(const SegPlan *plan, int S, uint64_t *nodes, const
 }
 
 hipError_t launch_hash_compact(const TileLaunch &slots, const uint64_t *hkeys, uint64_t *nodes,
-                               uint64_t *count, const uint32_t *flags, int64_t *seg_V, int grid,
-                               hipStream_t s) {
-  if (slots.total_tiles > 0)
+                               uint64_t *count, const uint32_t *flags, int64_t *seg_V,
+                               const BucketLaunch *bk, int grid, hipStream_t s) {
+  if (bk) {
+    // one table, bucketed: the scan of the bucket counts gives the count
+    if (slots.total_tiles > 0)
+      hipLaunchKernelGGL(k_bucket_count, dim3(BP_BLOCKS), dim3(BP_THREADS), 0, s, slots.plan,
+                         hkeys, bk->bcnt);
+    hipLaunchKernelGGL(k_bucket_plan, dim3(1), dim3(1024), 0, s, bk->bcnt, bk->bstart, bk->bcur,
+                       bk->max_bucket, count);
+    if (slots.total_tiles > 0)
+      hipLaunchKernelGGL(k_bucket_place, dim3(BP_BLOCKS), dim3(BP_THREADS), 0, s, slots.plan,
+                         hkeys, bk->bcur, nodes, bk->bslot);
+  } else if (slots.total_tiles > 0) {
     hipLaunchKernelGGL(k_hash_compact, dim3(grid), dim3(256), 0, s, slots, hkeys, nodes, count);
+  }
   const int S = slots.num_segs;
   hipLaunchKernelGGL(k_hash_finish, dim3((S + 255) / 256), dim3(256), 0, s, slots.plan, S, nodes,
                      count, flags, seg_V);
@@ -326,6 +462,89 @@ hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
                             const uint64_t *hkeys, uint32_t *hrank, int grid, hipStream_t s) {
   if (nodes_t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_rank, dim3(grid), dim3(256), 0, s, nodes_t, sorted, hkeys, hrank);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- bucket sort
+//
+// One workgroup per bucket of the top BUCKET_BITS key bits (at most
+// BUCKET_CAP keys, all distinct), in LDS: a counting sort on the next
+// SUB_BITS bits puts the keys in sub-bucket order, and a key's rank inside
+// the bucket is its sub-bucket's start plus the number of smaller keys in
+// its sub-bucket (few: the sub-buckets split the bucket a thousandfold).
+// Then node_ids and each key's position at its slot in hrank.  Buckets are
+// in key order, so bucket start + rank inside the bucket is the key's
+// position among all V keys.
+
+constexpr int BS_THREADS = 256;
+constexpr int SUB_BITS = 10;
+constexpr int NSUB = 1 << SUB_BITS;
+
+__global__ __launch_bounds__(BS_THREADS) void k_bucket_sort(const SegPlan *plan,
+                                                            const uint32_t *bstart,
+                                                            const uint64_t *keys,
+                                                            const uint32_t *bslot,
+                                                            const uint32_t *flags,
+                                                            uint32_t *hrank) {
+  __shared__ uint64_t s_k[BUCKET_CAP];  // the keys in sub-bucket order
+  __shared__ uint32_t s_i[BUCKET_CAP];  // their indices in the bucket
+  __shared__ uint32_t s_st[NSUB + 1];   // sub-bucket counts, then starts
+  __shared__ uint32_t s_cur[NSUB];      // placement cursors
+  __shared__ uint32_t s_w[BS_THREADS / 64];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const SegPlan P = plan[0];
+  if (b == 0 && tid == 0 && (flags[0] & HFLAG_MAX_KEY))
+    G(P.node_ids)[P.V - 1] = (int64_t)(EMPTY_KEY ^ SIGN_FLIP);  // the flagged key ~0 is last
+  const uint32_t s = bstart[b];
+  const int c = (int)(bstart[b + 1] - s);  // <= BUCKET_CAP, checked by the host
+  if (c == 0) return;
+  const __attribute__((address_space(1))) uint64_t *K = G(keys) + s;
+  constexpr int SHIFT = 64 - BUCKET_BITS - SUB_BITS;
+  for (int i = tid; i < NSUB; i += BS_THREADS) s_st[i] = 0;
+  __syncthreads();
+  for (int i = tid; i < c; i += BS_THREADS) atomicAdd(&s_st[(K[i] >> SHIFT) & (NSUB - 1)], 1u);
+  __syncthreads();
+  // exclusive scan of the NSUB counts: NSUB / BS_THREADS consecutive ones a thread
+  constexpr int PER = NSUB / BS_THREADS;
+  uint32_t v[PER], sum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    v[q] = s_st[tid * PER + q];
+    sum += v[q];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan<BS_THREADS>(sum, s_w, total);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    s_st[tid * PER + q] = run;
+    s_cur[tid * PER + q] = run;
+    run += v[q];
+  }
+  if (tid == 0) s_st[NSUB] = total;
+  __syncthreads();
+  for (int i = tid; i < c; i += BS_THREADS) {
+    const uint64_t k = K[i];
+    const uint32_t p = atomicAdd(&s_cur[(k >> SHIFT) & (NSUB - 1)], 1u);
+    s_k[p] = k;
+    s_i[p] = (uint32_t)i;
+  }
+  __syncthreads();
+  uint32_t *R = hrank + P.tab_off;
+  for (int p = tid; p < c; p += BS_THREADS) {
+    const uint64_t k = s_k[p];
+    const uint32_t sb = (uint32_t)(k >> SHIFT) & (NSUB - 1);
+    const uint32_t q0 = s_st[sb], q1 = s_st[sb + 1];
+    uint32_t r = q0;
+    for (uint32_t q = q0; q < q1; ++q) r += s_k[q] < k;
+    G(P.node_ids)[s + r] = (int64_t)(k ^ SIGN_FLIP);
+    G(R)[G(bslot)[s + s_i[p]]] = s + r;
+  }
+}
+
+hipError_t launch_bucket_sort(const SegPlan *plan, const BucketLaunch &bk, const uint64_t *keys,
+                              const uint32_t *flags, uint32_t *hrank, hipStream_t s) {
+  hipLaunchKernelGGL(k_bucket_sort, dim3(NBUCKETS), dim3(BS_THREADS), 0, s, plan, bk.bstart, keys,
+                     bk.bslot, flags, hrank);
   return hipGetLastError();
 }
 

@@ -299,14 +299,16 @@ struct Call {
   }
 
   // Read back S counts from results[off..off+S) and wait for the stream.
-  hipError_t readback(int off, std::vector<int64_t> &v) {
+  // results [off, off + count) to the host (count <= S + 1), synchronising.
+  hipError_t readback(int off, std::vector<int64_t> &v, int count = -1) {
+    if (count < 0) count = S;
     int64_t *host = (int64_t *)((char *)pin->p + kUploadSlots * meta_bytes);
-    hipError_t e = hipMemcpyAsync(host, results + off, sizeof(int64_t) * S, hipMemcpyDeviceToHost,
-                                  stream);
+    hipError_t e = hipMemcpyAsync(host, results + off, sizeof(int64_t) * count,
+                                  hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
-    v.assign(host, host + S);
+    v.assign(host, host + count);
     return hipSuccess;
   }
 
@@ -347,7 +349,7 @@ struct Call {
 enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
-  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_KINDS
+  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -356,7 +358,8 @@ const char *const kTraceNames[TK_KINDS] = {
     "remap_pack",        "sort_edge_count",   "sort_edge_scatter", "dedupe_out_csr",
     "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
-    "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables"};
+    "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
+    "hash_bucket_sort"};
 
 struct TraceRec {
   int kind;
@@ -582,7 +585,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   const int64_t max_tiles = c.total(TM_NSORT) + 1;
   const int64_t max_runs = sort_runs_bound(max_tiles);
   c.meta_bytes = align_up(align_up(sizeof(SegPlan) * S) + sizeof(int64_t) * c.tmap.size());
-  c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t) * S);
+  c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t) * (S + 1));
   if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
 
   const size_t base_words = (size_t)S * RADIX;
@@ -591,7 +594,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.status = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * status_words, st);
   c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * base_words, st);
   c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
-  c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * 2 * S, st);
+  c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * (2 * S + 1), st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
   c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
   c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_runs, st);
@@ -612,16 +615,32 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   int64_t slots = 0;
   uint64_t *hkeys = nullptr;
   uint32_t *hrank = nullptr;
+  uint32_t *hflags = nullptr;
+  // one table: its distinct keys are placed by bucket of their top bits, and
+  // sorted bucket by bucket in LDS when no bucket exceeds BUCKET_CAP keys
+  const bool bucket_place = want_hash && S == 1;
+  bool bucketed = bucket_place;
+  BucketLaunch bkl{};
   long hcompact_rec = -1;
   if (want_hash) {
     const size_t reg_bytes = align_up(sizeof(uint32_t) * HLL_M * S);
     const size_t cnt_bytes = align_up(sizeof(uint64_t) * S);
-    const size_t hm_bytes = reg_bytes + cnt_bytes + align_up(sizeof(uint32_t) * S);
+    const size_t flag_bytes = align_up(sizeof(uint32_t) * S);
+    const size_t bkt_bytes = bucketed ? align_up(sizeof(uint32_t) * (3 * NBUCKETS + 1)) : 0;
+    const size_t hm_bytes = reg_bytes + cnt_bytes + flag_bytes + bkt_bytes;
     c.hmeta = dev_alloc(c.hooks, hm_bytes, st);
     if (!c.hmeta) return RINGO_ERR_OUT_OF_MEMORY;
     uint32_t *regs = (uint32_t *)c.hmeta;
     uint64_t *hcount = (uint64_t *)((char *)c.hmeta + reg_bytes);
-    uint32_t *hflags = (uint32_t *)((char *)c.hmeta + reg_bytes + cnt_bytes);
+    hflags = (uint32_t *)((char *)c.hmeta + reg_bytes + cnt_bytes);
+    if (bucketed) {
+      uint32_t *bk = (uint32_t *)((char *)c.hmeta + reg_bytes + cnt_bytes + flag_bytes);
+      bkl.bcnt = bk;
+      bkl.bstart = bk + NBUCKETS;
+      bkl.bcur = bk + 2 * NBUCKETS + 1;
+      bkl.bslot = (uint32_t *)c.B;  // B is free until the distinct keys are sorted
+      bkl.max_bucket = c.results + S;
+    }
     HIP_TRY(launch_fill_u64((uint64_t *)c.hmeta, 0, (int64_t)(hm_bytes / 8), st));
     TRACED(TK_HLL, 2 * N, 16.0 * N,
            launch_hll(c.tiles(TM_HLL, RANGE_ROWS), regs, c.results,
@@ -650,10 +669,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     {
       TraceMark m = trace_begin(st);
       HIP_TRY(launch_hash_compact(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, c.A, hcount, hflags,
-                                  c.results, grid_for(c.total(TM_HCMP), cus * 8), st));
+                                  c.results, bucketed ? &bkl : nullptr,
+                                  grid_for(c.total(TM_HCMP), cus * 8), st));
       hcompact_rec = trace_end(m, TK_HCOMPACT, slots, 8.0 * slots, st);
     }
-    HIP_TRY(c.readback(0, V));  // sync #1
+    HIP_TRY(c.readback(0, V, S + 1));  // sync #1 (V, and the largest bucket)
+    bucketed = bucketed && V[S] <= BUCKET_CAP;
+    V.resize(S);
     hashed = true;
     for (int i = 0; i < S; ++i) hashed = hashed && V[i] >= 0;
     if (!hashed) {
@@ -706,7 +728,10 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   for (int i = 0; i < S; ++i) sumV += V[i];
   trace_set_bytes(unique_rec, 16.0 * N + 8.0 * sumV);
-  trace_set_bytes(hcompact_rec, 8.0 * slots + 8.0 * sumV);
+  // the compaction reads every slot once (bucketed: twice) and writes every
+  // key (bucketed: with its slot)
+  trace_set_bytes(hcompact_rec, (bucket_place ? 16.0 : 8.0) * slots +
+                                    (bucket_place ? 12.0 : 8.0) * sumV);
   c.owner = new Owner();
   c.owner->stream = st;
   c.owner->hooks = c.hooks;
@@ -739,7 +764,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   // ------------------------------------------------------------- phase E
   // Both methods write the packed edge keys to B; A is free afterwards.
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
-  if (hashed) {
+  if (hashed && bucketed) {
+    TRACED(TK_HBSORT, sumV, 24.0 * sumV,
+           launch_bucket_sort(c.plan_dev(), bkl, c.A, hflags, hrank, st));
+    TRACED(TK_HREMAP, N, 16.0 * N,
+           launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
+                             grid_for(c.total(TM_REMAP), cus * 8), st));
+  } else if (hashed) {
     for (int p = 0; p < NODE_PASSES; ++p) {  // 8 passes: A -> B -> ... -> A
       SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES,
                                  NODE_PASSES, p, RADIX_BITS * p);

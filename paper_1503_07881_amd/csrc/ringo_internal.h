@@ -160,11 +160,29 @@ hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, int 
 // After launch_hash_compact, seg_V[s] is the number of distinct keys of table
 // s, or -1 when its table overflowed, and the keys (unordered) are at
 // nodes + 2 * row_off.
+// Bucketed node sort (one table): buckets of the top BUCKET_BITS key bits.
+// bcnt must start at zero.  With a BucketLaunch, launch_hash_compact counts
+// the table's keys per bucket (bcnt), scans the counts (bstart, bcur),
+// writes the largest bucket to *max_bucket, and places every key in its
+// bucket's range (nodes) with its slot (bslot); launch_bucket_sort, allowed
+// when no bucket exceeds BUCKET_CAP, then writes node_ids and hrank.
+constexpr int BUCKET_BITS = 12;
+constexpr int NBUCKETS = 1 << BUCKET_BITS;
+constexpr int BUCKET_CAP = 2048;
+struct BucketLaunch {
+  uint32_t *bcnt;        // [NBUCKETS]
+  uint32_t *bstart;      // [NBUCKETS + 1]
+  uint32_t *bcur;        // [NBUCKETS]
+  uint32_t *bslot;       // [V]
+  int64_t *max_bucket;   // one value
+};
 hipError_t launch_hash_insert(const TileLaunch &rows, uint64_t *hkeys, uint32_t *slots,
                               uint32_t *flags, int grid, hipStream_t s);
 hipError_t launch_hash_compact(const TileLaunch &slot_tiles, const uint64_t *hkeys,
                                uint64_t *nodes, uint64_t *count, const uint32_t *flags,
-                               int64_t *seg_V, int grid, hipStream_t s);
+                               int64_t *seg_V, const BucketLaunch *bk, int grid, hipStream_t s);
+hipError_t launch_bucket_sort(const SegPlan *plan, const BucketLaunch &bk, const uint64_t *keys,
+                              const uint32_t *flags, uint32_t *hrank, hipStream_t s);
 // Writes node_ids from the sorted keys and each key's position into hrank at
 // its slot.
 hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,

@@ -77,6 +77,32 @@ def test_scan_paths_boundary(cuda, n):
             ringo.tune_set(1 << e, d, it, m)
 
 
+def test_hash_bucket_paths(cuda):
+    """Hash numbering of one table: identifiers spread over the 64-bit range
+    have their distinct keys sorted bucket by bucket in LDS; identifiers
+    crowded into one bucket of the top key bits (more than 2048 of them) take
+    the radix passes instead.  Both are the oracle's graph."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    try:
+        ringo.set_node_method(ringo.NODES_HASH)
+        spread = random_table(91, 200_000, 150_000)
+        crowded = (np.arange(0, 60_000, dtype=np.int64), np.arange(7, 60_007, dtype=np.int64))
+        for name, (src, dst), want, not_want in (
+                ("spread", spread, "hash_bucket_sort", "sort_vnode_count"),
+                ("crowded", crowded, "sort_vnode_count", "hash_bucket_sort")):
+            say("hash bucket path", name)
+            ringo.trace_enable(True)
+            g = gpu_graph(src, dst, cuda)
+            names = set(ringo.trace_read())
+            ringo.trace_enable(False)
+            assert want in names and not_want not in names, (name, sorted(names))
+            assert_same(g, oracle.table_to_graph(src, dst), name + ": ")
+    finally:
+        ringo.trace_enable(False)
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_small(cuda, method, seed):
     rng = np.random.default_rng(1000 + seed)
