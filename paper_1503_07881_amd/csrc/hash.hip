@@ -14,9 +14,13 @@
 //   insert     every row's two keys, lock-free compare-and-swap into the
 //              first free slot of the probe sequence; the slot of every
 //              key is written out (32-bit, src then dst per table)
-//   compact    occupied slots -> the table's distinct keys (unordered)
-//   (sort)     the V keys, with the radix passes of kernels.hip
-//   rank       position of every sorted key, stored beside its slot; node ids
+//   compact    occupied slots -> the table's distinct keys (unordered; for
+//              one table, grouped by bucket of their top 12 bits)
+//   (sort)     the V keys: bucket by bucket in LDS when no bucket is over
+//              BUCKET_CAP keys (node ids and ranks written directly), else
+//              with the radix passes of kernels.hip
+//   rank       after the radix passes: position of every sorted key, stored
+//              beside its slot; node ids
 //   remap      every row's (src, dst) slots -> positions (a gather from the
 //              rank array), packed (s << b) | d
 //
