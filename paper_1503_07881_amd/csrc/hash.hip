@@ -556,8 +556,14 @@ hipError_t launch_bucket_sort(const SegPlan *plan, const BucketLaunch &bk, const
 
 __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t *slots,
                                                     const uint32_t *hrank, uint64_t *ekeys,
-                                                    int sym) {
+                                                    int sym, uint32_t *counts0, int sort_tile,
+                                                    const int64_t *esort_tmap) {
+  constexpr int MAX_SUB = REMAP_TILE / 2048;  // sort tiles of at least 2048 keys
+  __shared__ uint32_t s_c[MAX_SUB * RADIX];   // first-digit counts of the tile's sort tiles
   const int tid = threadIdx.x;
+  const int nsub = counts0 ? REMAP_TILE / sort_tile : 0;
+  for (int i = tid; i < nsub * RADIX; i += 256) s_c[i] = 0;
+  __syncthreads();
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
@@ -583,21 +589,41 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
         if (r0 + j * 256 < end) {
           const uint32_t rs = q[j] == NO_SLOT ? last : rk[j];
           const uint32_t rd = q[U + j] == NO_SLOT ? last : rk[U + j];
+          const uint64_t key = ((uint64_t)rs << b) | rd;
           if (sym) {  // both orientations, 2n keys at 2 * row_off
-            G(ekeys)[2 * P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+            G(ekeys)[2 * P.row_off + r0 + j * 256] = key;
             G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rd << b) | rs;
           } else {
-            G(ekeys)[P.row_off + r0 + j * 256] = ((uint64_t)rs << b) | rd;
+            G(ekeys)[P.row_off + r0 + j * 256] = key;
+            if (counts0)
+              atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * RADIX +
+                             (uint32_t)(key & (RADIX - 1))], 1u);
           }
         }
+    }
+    if (counts0) {
+      __syncthreads();
+      // sort tiles of this remap tile that hold rows of the table
+      const int64_t first = (tile - t.tmap[seg]) * nsub;
+      for (int i = tid; i < nsub * RADIX; i += 256) {
+        const int st = i / RADIX;
+        if ((first + st) * sort_tile < P.n)
+          G(counts0)[(esort_tmap[seg] + first + st) * RADIX + i % RADIX] = s_c[i];
+        s_c[i] = 0;
+      }
+      __syncthreads();
     }
   }
 }
 
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
-                             uint64_t *ekeys, int sym, int grid, hipStream_t s) {
+                             uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
+                             const int64_t *esort_tmap, int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_remap, dim3(grid), dim3(256), 0, s, rows, slots, hrank, ekeys, sym);
+  if (counts0 && (sym || sort_tile < 2048 || REMAP_TILE % sort_tile != 0))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hash_remap, dim3(grid), dim3(256), 0, s, rows, slots, hrank, ekeys, sym,
+                     counts0, sort_tile, esort_tmap);
   return hipGetLastError();
 }
 

@@ -310,6 +310,17 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
   a.bsum[(int64_t)blockIdx.x * RADIX + tid] = v;
 }
 
+// Run sums from tile counts written elsewhere (SORT_PART_PREFIX): one block
+// per run of run_tiles tiles, one thread per digit.
+__global__ __launch_bounds__(RADIX) void k_run_sums(SortLaunch a, int run_tiles) {
+  const int d = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * run_tiles;
+  const int64_t t1 = std::min<int64_t>(t0 + run_tiles, a.total_tiles);
+  uint32_t sum = 0;
+  for (int64_t t = t0; t < t1; ++t) sum += a.counts[t * RADIX + d];
+  a.bsum[(int64_t)blockIdx.x * RADIX + d] = sum;
+}
+
 // Exclusive scan of the run counts over all runs, one block per digit.
 __global__ __launch_bounds__(1024) void k_block_scan(SortLaunch a, int64_t runs) {
   __shared__ uint32_t s_w[16];
@@ -646,11 +657,14 @@ static int resident_t() {
 
 template <int ITEMS, int MODE>
 static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
-  if (parts & SORT_PART_COUNT) {
+  if (parts & (SORT_PART_COUNT | SORT_PART_PREFIX)) {
     const int rt = run_tiles_for(a.total_tiles);
     const int64_t runs = (a.total_tiles + rt - 1) / rt;
-    hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS,
-                       rt);
+    if (parts & SORT_PART_COUNT)
+      hipLaunchKernelGGL((k_upsweep<MODE>), dim3((unsigned)runs), dim3(256), 0, s, a, 256 * ITEMS,
+                         rt);
+    else if (a.total_tiles > SMALL_SCAN_TILES)
+      hipLaunchKernelGGL(k_run_sums, dim3((unsigned)runs), dim3(RADIX), 0, s, a, rt);
     if (a.total_tiles <= SMALL_SCAN_TILES) {
       hipLaunchKernelGGL(k_scan_small, dim3(RADIX), dim3(256), 0, s, a);
     } else {

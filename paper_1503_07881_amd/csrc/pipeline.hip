@@ -6,11 +6,14 @@
 //   phase N  node numbering, by one of two methods (same result):
 //            sort   8 radix passes over the 2n node keys, unique
 //            hash   distinct-count estimate (sync #0 sizes the tables),
-//                   node hash table insert, compaction of the V keys
+//                   node hash table insert, compaction of the V keys (for
+//                   one table, grouped by bucket of their top bits)
 //   sync #1  read back V of every table, size the node-sized outputs
-//   phase E  sort: directory + remap; hash: radix passes over the V keys,
-//            rank + remap; then radix passes over the packed edge keys,
-//            dedupe + out-offsets
+//   phase E  sort: directory + remap; hash: the V keys sorted bucket by
+//            bucket in LDS (one table, no crowded bucket) or by radix
+//            passes and ranked, then the remap (which also counts the first
+//            edge pass's digits); then radix passes over the packed edge
+//            keys, dedupe + out-offsets
 //   sync #2  read back E of every table, size the edge-sized outputs
 //   phase I  radix passes over the (d, s) keys (the first one also writes
 //            the out-neighbours), in-CSR
@@ -761,6 +764,12 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.set_tiles(TM_DEDUP, erange, SCAN_TILE);
   HIP_TRY(c.upload());
 
+  // The hash remap also counts the first edge pass's digits of every sort
+  // tile (directed and multigraph keys, sort tiles that divide its tiles);
+  // that pass then starts from its prefixes.
+  uint32_t *counts0 =
+      hashed && !undirected && REMAP_TILE % c.sort_tile == 0 ? c.counts : nullptr;
+
   // ------------------------------------------------------------- phase E
   // Both methods write the packed edge keys to B; A is free afterwards.
   HIP_TRY(launch_empty_offsets(c.plan_dev(), S, st));
@@ -769,6 +778,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
            launch_bucket_sort(c.plan_dev(), bkl, c.A, hflags, hrank, st));
     TRACED(TK_HREMAP, N, 16.0 * N,
            launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
+                             counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else if (hashed) {
     for (int p = 0; p < NODE_PASSES; ++p) {  // 8 passes: A -> B -> ... -> A
@@ -781,6 +791,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                             grid_for(c.total(TM_DIR), cus * 8), st));
     TRACED(TK_HREMAP, N, 16.0 * N,
            launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
+                             counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else {
     TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
@@ -809,8 +820,14 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
         a.vin = vbuf[p & 1];
         a.vout = vbuf[(p + 1) & 1];
       }
-      TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0,
-                  multi ? SORT_EDGE_KV : SORT_EDGE, a);
+      const int mode = multi ? SORT_EDGE_KV : SORT_EDGE;
+      if (p == 0 && counts0) {  // tile counts written by the remap
+        TRACED(TK_EDGE_COUNT, NE, 0.0, launch_sort_part(a, mode, c.items, SORT_PART_PREFIX, st));
+        TRACED(TK_EDGE_SCATTER, NE, (16.0 + (multi ? 8.0 : 0.0)) * NE,
+               launch_sort_part(a, mode, c.items, SORT_PART_SCATTER, st));
+      } else {
+        TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a);
+      }
     }
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];

@@ -108,7 +108,7 @@ enum SortMode : int {
   // out_off at the de-duplicated positions (dedupe folded into the pass)
   SORT_IN_FIRST_DEDUP = 10
 };
-enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2 };
+enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2, SORT_PART_PREFIX = 4 };
 
 struct TileLaunch {
   const SegPlan *plan;
@@ -121,7 +121,9 @@ struct TileLaunch {
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
 // One part of a pass: SORT_PART_COUNT (digit counts of every tile and their
-// prefixes) or SORT_PART_SCATTER (the stable scatter), or both.
+// prefixes) or SORT_PART_SCATTER (the stable scatter), or both;
+// SORT_PART_PREFIX instead of SORT_PART_COUNT when the tile counts
+// (counts [tile][RADIX]) were written by the kernel that produced the keys.
 hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts, hipStream_t s);
 int sort_tile(int items);
 int64_t sort_runs(int64_t tiles);
@@ -189,8 +191,13 @@ hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
                             const uint64_t *hkeys, uint32_t *hrank, int grid, hipStream_t s);
 // Every row's (src, dst) slots -> dense positions, packed edge keys (sym as
 // for launch_remap).
+// counts0 (directed and multigraph keys, sort tiles of sort_tile rows that
+// divide REMAP_TILE, tile map esort_tmap): the remap also writes the digit
+// counts of the first edge pass (bits [0, RADIX_BITS)) of every sort tile,
+// counts0 [tile][RADIX]; null otherwise.
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
-                             uint64_t *ekeys, int sym, int grid, hipStream_t s);
+                             uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
+                             const int64_t *esort_tmap, int grid, hipStream_t s);
 
 // keep_all: every sorted key is its own edge (multigraph), offsets only.
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
