@@ -401,16 +401,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kind", default="directed", choices=("directed", "undirected", "multi"),
                     help="graph kind of the table-to-graph conversion")
+    ap.add_argument("--node-method", default="auto", choices=("auto", "sort", "hash"),
+                    help="node numbering: the schedule table's choice per size, or one method")
     ap.add_argument("--op", default="to_graph", choices=("to_graph", "to_table", "pagerank"),
                     help="to_graph: table-to-graph conversion (default); to_table: graph-to-table; "
                          "pagerank: ten PageRank iterations on the converted graph")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the conversion runs on a single MI355X).",
               file=sys.stderr)
         sys.exit(2)
 
+    if args.node_method != "auto":
+        from paper_1503_07881_amd import ringo
+        ringo.set_node_method(ringo.NODES_HASH if args.node_method == "hash" else ringo.NODES_SORT)
     if args.op == "to_table":
         bench_to_table(args)
         return
