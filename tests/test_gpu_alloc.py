@@ -1,0 +1,111 @@
+"""Caller-supplied device allocator (ringo_set_allocator) and the
+out-of-memory path: a counting allocator that refuses its k-th request makes
+the conversion fail with RINGO_ERR_OUT_OF_MEMORY, every block handed out
+before is returned, the outputs are zeroed, and conversions work again
+afterwards (with the hook and with the built-in allocator)."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import assert_same
+from paper_1503_07881_amd import ringo
+
+pytestmark = pytest.mark.gpu
+
+ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class CountingAllocator:
+    """torch's caching allocator behind the hook; refuses request number
+    `fail_at` (1-based; 0 never) and records the live blocks."""
+
+    def __init__(self, dev):
+        import torch
+        self.torch = torch
+        self.dev = dev
+        self.fail_at = 0
+        self.requests = 0
+        self.live = {}
+        self.c_alloc = ALLOC(self._alloc)
+        self.c_free = FREE(self._free)
+
+    def _alloc(self, nbytes, stream, ctx):
+        self.requests += 1
+        if self.fail_at and self.requests == self.fail_at:
+            return None
+        ptr = self.torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), self.dev.index, stream)
+        self.live[ptr] = nbytes
+        return ptr
+
+    def _free(self, ptr, stream, ctx):
+        if ptr:
+            self.live.pop(ptr)
+            self.torch.cuda.caching_allocator_delete(ptr)
+
+    def install(self):
+        assert ringo.lib().ringo_set_allocator(ctypes.cast(self.c_alloc, ctypes.c_void_p),
+                                               ctypes.cast(self.c_free, ctypes.c_void_p), None) == 0
+
+
+def convert_raw(src, dst, kind=ringo.GRAPH_DIRECTED):
+    import torch
+    g = ringo.RawGraph()
+    sh = torch.cuda.current_stream().cuda_stream
+    rc = ringo.lib().ringo_table_to_graph_ex(src.data_ptr(), dst.data_ptr(), src.numel(), kind,
+                                             ctypes.byref(g), sh)
+    torch.cuda.synchronize()
+    return rc, g
+
+
+@pytest.mark.parametrize("method", ["sort", "hash"])
+def test_allocator_hook_and_out_of_memory(cuda, method):
+    import torch
+    rng = np.random.default_rng(5)
+    n = 300_000  # above the small-table size: the pass pipeline
+    src_h = rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
+    dst_h = src_h[rng.permutation(n)]
+    src, dst = (torch.from_numpy(a).to(cuda) for a in (src_h, dst_h))
+    want = oracle.table_to_graph(src_h, dst_h)
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    al = CountingAllocator(cuda)
+    try:
+        ringo.set_node_method(ringo.NODES_HASH if method == "hash" else ringo.NODES_SORT)
+        al.install()
+        # a full conversion through the hook: how many requests it makes
+        rc, g = convert_raw(src, dst)
+        assert rc == 0
+        total = al.requests
+        assert total > 3 and al.live
+        ringo.graph_free(g)
+        assert not al.live, "blocks left after graph_free"
+        # refuse every request in turn (a sample of them for speed)
+        for k in sorted({1, 2, 3, total // 2, total - 1, total}):
+            say("allocator refuses request", k, "of", total, method)
+            al.requests, al.fail_at = 0, k
+            rc, g = convert_raw(src, dst)
+            assert rc == 3, (k, rc)  # RINGO_ERR_OUT_OF_MEMORY
+            assert g.num_nodes == 0 and g.node_ids is None and g.out_nbrs is None
+            assert not al.live, f"blocks leaked after a failure at request {k}"
+        al.fail_at = 0
+        rc, g = convert_raw(src, dst)
+        assert rc == 0
+        got = ringo._wrap(g, cuda)
+        assert_same(got, want, "through the hook after failures: ")
+        del got
+    finally:
+        assert ringo.lib().ringo_set_allocator(None, None, None) == 0
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
+    # the built-in allocator again
+    g2 = ringo.to_graph(src, dst)
+    torch.cuda.synchronize()
+    assert_same(g2, want, "built-in allocator: ")
