@@ -66,22 +66,29 @@ def convert_raw(src, dst, kind=ringo.GRAPH_DIRECTED):
     return rc, g
 
 
+KINDS = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
+         "multi": ringo.GRAPH_MULTI}
+
+
+@pytest.mark.parametrize("kname", list(KINDS))
 @pytest.mark.parametrize("method", ["sort", "hash"])
-def test_allocator_hook_and_out_of_memory(cuda, method):
+def test_allocator_hook_and_out_of_memory(cuda, method, kname):
     import torch
     rng = np.random.default_rng(5)
     n = 300_000  # above the small-table size: the pass pipeline
     src_h = rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
     dst_h = src_h[rng.permutation(n)]
     src, dst = (torch.from_numpy(a).to(cuda) for a in (src_h, dst_h))
-    want = oracle.table_to_graph(src_h, dst_h)
+    kind = KINDS[kname]
+    want = oracle.table_to_graph_kind(src_h, dst_h, {"directed": oracle.DIRECTED, "undirected": oracle.UNDIRECTED,
+                                                     "multi": oracle.MULTIGRAPH}[kname])
     saved = [ringo.tune_get(1 << e) for e in range(63)]
     al = CountingAllocator(cuda)
     try:
         ringo.set_node_method(ringo.NODES_HASH if method == "hash" else ringo.NODES_SORT)
         al.install()
         # a full conversion through the hook: how many requests it makes
-        rc, g = convert_raw(src, dst)
+        rc, g = convert_raw(src, dst, kind)
         assert rc == 0
         total = al.requests
         assert total > 3 and al.live
@@ -89,14 +96,14 @@ def test_allocator_hook_and_out_of_memory(cuda, method):
         assert not al.live, "blocks left after graph_free"
         # refuse every request in turn (a sample of them for speed)
         for k in sorted({1, 2, 3, total // 2, total - 1, total}):
-            say("allocator refuses request", k, "of", total, method)
+            say("allocator refuses request", k, "of", total, method, kname)
             al.requests, al.fail_at = 0, k
-            rc, g = convert_raw(src, dst)
+            rc, g = convert_raw(src, dst, kind)
             assert rc == 3, (k, rc)  # RINGO_ERR_OUT_OF_MEMORY
             assert g.num_nodes == 0 and g.node_ids is None and g.out_nbrs is None
             assert not al.live, f"blocks leaked after a failure at request {k}"
         al.fail_at = 0
-        rc, g = convert_raw(src, dst)
+        rc, g = convert_raw(src, dst, kind)
         assert rc == 0
         got = ringo._wrap(g, cuda)
         assert_same(got, want, "through the hook after failures: ")
@@ -106,6 +113,6 @@ def test_allocator_hook_and_out_of_memory(cuda, method):
         for e, (d, it, m) in enumerate(saved):
             ringo.tune_set(1 << e, d, it, m)
     # the built-in allocator again
-    g2 = ringo.to_graph(src, dst)
+    g2 = ringo.to_graph(src, dst, kind=kind)
     torch.cuda.synchronize()
     assert_same(g2, want, "built-in allocator: ")
