@@ -155,9 +155,10 @@ ringo_status_t ringo_table_to_graph_batched_ex(int32_t num_tables, const int64_t
 /*
  * Stable least-significant-digit radix sort of uint64 keys: the sort the
  * conversion runs on its column copies (Section 2.4), exposed as a primitive.
- * It takes ceil(bits / 8) passes of 8-bit digits, so keys are ordered by
- * their low 8 * ceil(bits / 8) bits (all of them for bits = 64); keys equal
- * in those bits keep their input order, and the higher bits travel with the
+ * It takes ceil(bits / d) passes of d-bit digits, d being the digit width of
+ * the schedule for n rows (ringo_tune_get), so keys are ordered by their low
+ * min(64, d * ceil(bits / d)) bits (all of them for bits = 64); keys equal in
+ * those bits keep their input order, and the higher bits travel with the
  * keys.  For keys below 2^b, bits = b gives the full ascending order.
  *   in, out : DEVICE arrays of n keys; they must not overlap.
  *   n       : 0 <= n <= 2 * RINGO_MAX_ROWS.
@@ -238,7 +239,9 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
  * the schedule the library will use for a table of num_rows rows (for a
  * batch: of the batch's total rows); ringo_tune_set overrides it for the
  * size bucket holding num_rows (powers of two; used by the autotuner).
- * Valid digit widths: 8; valid items per thread: 8, 12, 16.
+ * Valid digit widths: 8 to 11 bits (a pass sorts on that many bits, so a
+ * key of k bits takes ceil(k / digit_bits) passes); valid items per thread:
+ * 8, 12, 16.
  *
  * Node numbering (both give the same graph, bit for bit):
  *   RINGO_NODES_SORT  radix sort of all 2n identifiers, then unique.
@@ -250,7 +253,7 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
  *                     bound (an estimate far too low), the call falls back to
  *                     RINGO_NODES_SORT by itself.
  * Built-in defaults (measured on an MI355X): RINGO_NODES_SORT up to 2^23 rows,
- * RINGO_NODES_HASH above; 8 items per thread.
+ * RINGO_NODES_HASH above; 8 items per thread; 8-bit digits.
  */
 #define RINGO_NODES_SORT 0
 #define RINGO_NODES_HASH 1

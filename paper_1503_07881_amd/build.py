@@ -26,7 +26,8 @@ FLAGS = [
 ]
 
 LIBS = {
-    "libringo.so": ["kernels.hip", "hash.hip", "to_table.hip", "pagerank.hip", "small.hip", "pipeline.hip", "serve.hip"],
+    "libringo.so": ["kernels.hip", "lsd_d8.hip", "lsd_d9.hip", "lsd_d10.hip", "lsd_d11.hip", "hash.hip",
+                    "to_table.hip", "pagerank.hip", "small.hip", "pipeline.hip", "serve.hip"],
     "libringo_gen.so": ["workloads.hip"],
 }
 

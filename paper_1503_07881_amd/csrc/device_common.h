@@ -8,6 +8,8 @@ namespace ringo {
 
 // --------------------------------------------------------------- helpers
 
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
 // Pointers read from the plan are generic to the compiler; G() marks them as
 // global-memory pointers so that accesses compile to global (not flat)
 // instructions, which keep LDS waits independent of outstanding loads.

@@ -559,10 +559,10 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
                                                     int sym, uint32_t *counts0, int sort_tile,
                                                     const int64_t *esort_tmap) {
   constexpr int MAX_SUB = REMAP_TILE / 2048;  // sort tiles of at least 2048 keys
-  __shared__ uint32_t s_c[MAX_SUB * RADIX];   // first-digit counts of the tile's sort tiles
+  __shared__ uint32_t s_c[MAX_SUB * FUSED_RADIX];   // first-digit counts of the tile's sort tiles
   const int tid = threadIdx.x;
   const int nsub = counts0 ? REMAP_TILE / sort_tile : 0;
-  for (int i = tid; i < nsub * RADIX; i += 256) s_c[i] = 0;
+  for (int i = tid; i < nsub * FUSED_RADIX; i += 256) s_c[i] = 0;
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
@@ -596,8 +596,8 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
           } else {
             G(ekeys)[P.row_off + r0 + j * 256] = key;
             if (counts0)
-              atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * RADIX +
-                             (uint32_t)(key & (RADIX - 1))], 1u);
+              atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * FUSED_RADIX +
+                             (uint32_t)(key & (FUSED_RADIX - 1))], 1u);
           }
         }
     }
@@ -605,10 +605,10 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
       __syncthreads();
       // sort tiles of this remap tile that hold rows of the table
       const int64_t first = (tile - t.tmap[seg]) * nsub;
-      for (int i = tid; i < nsub * RADIX; i += 256) {
-        const int st = i / RADIX;
+      for (int i = tid; i < nsub * FUSED_RADIX; i += 256) {
+        const int st = i / FUSED_RADIX;
         if ((first + st) * sort_tile < P.n)
-          G(counts0)[(esort_tmap[seg] + first + st) * RADIX + i % RADIX] = s_c[i];
+          G(counts0)[(esort_tmap[seg] + first + st) * FUSED_RADIX + i % FUSED_RADIX] = s_c[i];
         s_c[i] = 0;
       }
       __syncthreads();

@@ -1,0 +1,6 @@
+// LSD radix sort passes on 10-bit digits (the pass kernels are in lsd.h).
+#include "lsd.h"
+
+namespace ringo {
+template hipError_t launch_sort_part_rb<10>(const SortLaunch &, int, int, int, hipStream_t);
+}  // namespace ringo

@@ -145,12 +145,14 @@ void pinned_release(Pinned *b, hipStream_t s) {
 
 // ------------------------------------------------------------- schedule
 
-// Items per thread of the scatter tile and node-numbering method by table
-// size (log2 buckets of rows).  Built-in defaults, from the autotuner's
-// measurements on an MI355X (R-MAT tables, 2^10 to 2^26 rows): the sort
-// numbering up to 2^23 rows and the hash numbering above; 8 items per
-// thread (within measurement noise of 16 at 2^26 rows).
+// Items per thread of the scatter tile, digit bits of the radix passes and
+// node-numbering method by table size (log2 buckets of rows).  Built-in
+// defaults, from the autotuner's measurements on an MI355X (R-MAT tables,
+// 2^10 to 2^26 rows): the sort numbering up to 2^23 rows and the hash
+// numbering above; 8 items per thread (within measurement noise of 16 at
+// 2^26 rows); 8-bit digits.
 int g_items[64];
+int g_bits[64];
 int g_method[64];
 bool g_items_init = false;
 constexpr int HASH_DEFAULT_LOG2 = 24;
@@ -159,6 +161,7 @@ void schedule_init_locked() {
   if (g_items_init) return;
   for (int i = 0; i < 64; ++i) {
     g_items[i] = 8;
+    g_bits[i] = DEFAULT_DIGIT_BITS;
     g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
   }
   g_items_init = true;
@@ -168,6 +171,12 @@ int items_for(int64_t rows) {
   std::lock_guard<std::mutex> lk(g_mu);
   schedule_init_locked();
   return g_items[ceil_log2(std::max<int64_t>(rows, 1))];
+}
+
+int digit_bits_for(int64_t rows) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  schedule_init_locked();
+  return g_bits[ceil_log2(std::max<int64_t>(rows, 1))];
 }
 
 int method_for(int64_t rows) {
@@ -208,6 +217,7 @@ struct Call {
   AllocHooks hooks;
   int items = 16;
   int sort_tile = 4096;
+  int rb = DEFAULT_DIGIT_BITS;  // digit bits of the radix passes
   std::vector<SegPlan> plan;
   std::vector<int64_t> tmap;  // TM_KINDS x (S + 1)
 
@@ -430,9 +440,10 @@ void trace_set_bytes(long idx, double bytes) {
 // scatter (reads and writes every key, plus extra bytes per key).
 #define TRACED_PASS(kcount, kscatter, keys, extra, mode, a)                                     \
   do {                                                                                        \
-    TRACED(kcount, keys, 8.0 * (keys), launch_sort_part(a, mode, c.items, SORT_PART_COUNT, st)); \
+    TRACED(kcount, keys, 8.0 * (keys),                                                        \
+           launch_sort_part(a, mode, c.items, c.rb, SORT_PART_COUNT, st));                    \
     TRACED(kscatter, keys, (16.0 + (extra)) * (keys),                                         \
-           launch_sort_part(a, mode, c.items, SORT_PART_SCATTER, st));                        \
+           launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                  \
   } while (0)
 
 int grid_for(int64_t tiles, int cap) {
@@ -576,6 +587,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     max_rows = std::max(max_rows, p.n);
   }
   c.items = items_for(S == 1 ? max_rows : N);
+  c.rb = digit_bits_for(S == 1 ? max_rows : N);
+  const int R = 1 << c.rb;
   const bool want_hash = method_for(S == 1 ? max_rows : N) == RINGO_NODES_HASH;
   c.sort_tile = sort_tile(c.items);
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
@@ -583,7 +596,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.set_tiles(TM_HLL, RANGE_ROWS, HLL_TILE);
   c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
 
-  const int64_t status_words = c.total(TM_UNIQ) + RADIX;  // one word per unique/dedupe tile
+  const int64_t status_words = c.total(TM_UNIQ) + 256;  // one word per unique/dedupe tile
   // the node pass has the most tiles: 2n keys per table
   const int64_t max_tiles = c.total(TM_NSORT) + 1;
   const int64_t max_runs = sort_runs_bound(max_tiles);
@@ -591,7 +604,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t) * (S + 1));
   if (!c.pin) return RINGO_ERR_OUT_OF_MEMORY;
 
-  const size_t base_words = (size_t)S * RADIX;
+  const size_t base_words = (size_t)S * R;
   c.A = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
   c.B = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
   c.status = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * status_words, st);
@@ -599,8 +612,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
   c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * (2 * S + 1), st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
-  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
-  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_runs, st);
+  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * max_tiles, st);
+  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * max_runs, st);
   if (!c.A || !c.B || !c.status || !c.base || !c.counters || !c.results || !c.meta ||
       !c.counts || !c.bsum)
     return RINGO_ERR_OUT_OF_MEMORY;
@@ -692,13 +705,16 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   uint64_t *buf[2] = {c.A, c.B};
   if (!hashed) {
-    for (int p = 0; p < NODE_PASSES; ++p) {
-      SortLaunch a = c.sort_args(p == 0 ? nullptr : buf[(p - 1) & 1], buf[p & 1], TM_NSORT,
-                                 RANGE_NODE_KEYS, NODE_PASSES, p, RADIX_BITS * p);
+    const int P_n = lsd_passes(64, c.rb);
+    // the passes alternate between A and B so that the last one lands in B
+    uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
+    for (int p = 0; p < P_n; ++p) {
+      SortLaunch a = c.sort_args(p == 0 ? nullptr : nbuf[(p - 1) & 1], nbuf[p & 1], TM_NSORT,
+                                 RANGE_NODE_KEYS, P_n, p, c.rb * p);
       TRACED_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * N, 0.0, p == 0 ? SORT_NODE_FIRST : SORT_NODE,
                   a);
     }
-    // 8 passes end in B; the distinct keys go to A
+    // the sorted keys are in B; the distinct keys go to A
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
     HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.status,
@@ -751,8 +767,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     p.out_off = (int64_t *)(a1 + off1[3 * i + 1]);
     p.in_off = (int64_t *)(a1 + off1[3 * i + 2]);
   }
-  const int P_e = (2 * b_max + RADIX_BITS - 1) / RADIX_BITS;
-  const int P_in = (b_max + RADIX_BITS - 1) / RADIX_BITS;
+  const int P_e = lsd_passes(2 * b_max, c.rb);
+  const int P_in = lsd_passes(b_max, c.rb);
   c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
   c.set_tiles(TM_VSORT, RANGE_NODES, c.sort_tile);
   // edge keys: n per table at row_off, or both orientations (2n at
@@ -767,8 +783,10 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   // The hash remap also counts the first edge pass's digits of every sort
   // tile (directed and multigraph keys, sort tiles that divide its tiles);
   // that pass then starts from its prefixes.
-  uint32_t *counts0 =
-      hashed && !undirected && REMAP_TILE % c.sort_tile == 0 ? c.counts : nullptr;
+  uint32_t *counts0 = hashed && !undirected && c.rb == FUSED_RADIX_BITS &&
+                              REMAP_TILE % c.sort_tile == 0
+                          ? c.counts
+                          : nullptr;
 
   // ------------------------------------------------------------- phase E
   // Both methods write the packed edge keys to B; A is free afterwards.
@@ -781,13 +799,14 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                              counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else if (hashed) {
-    for (int p = 0; p < NODE_PASSES; ++p) {  // 8 passes: A -> B -> ... -> A
-      SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES,
-                                 NODE_PASSES, p, RADIX_BITS * p);
+    const int P_n = lsd_passes(64, c.rb);
+    for (int p = 0; p < P_n; ++p) {  // A -> B -> ...; an odd count ends in B
+      SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES, P_n, p,
+                                 c.rb * p);
       TRACED_PASS(TK_VNODE_COUNT, TK_VNODE_SCATTER, sumV, 0.0, SORT_VNODE, a);
     }
     TRACED(TK_HRANK, sumV, 20.0 * sumV,
-           launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), c.A, hkeys, hrank,
+           launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), buf[P_n & 1], hkeys, hrank,
                             grid_for(c.total(TM_DIR), cus * 8), st));
     TRACED(TK_HREMAP, N, 16.0 * N,
            launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
@@ -815,16 +834,17 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   {
     for (int p = 0; p < P_e; ++p) {
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, erange, P_e, p,
-                                 RADIX_BITS * p);
+                                 c.rb * p);
       if (multi) {
         a.vin = vbuf[p & 1];
         a.vout = vbuf[(p + 1) & 1];
       }
       const int mode = multi ? SORT_EDGE_KV : SORT_EDGE;
       if (p == 0 && counts0) {  // tile counts written by the remap
-        TRACED(TK_EDGE_COUNT, NE, 0.0, launch_sort_part(a, mode, c.items, SORT_PART_PREFIX, st));
+        TRACED(TK_EDGE_COUNT, NE, 0.0,
+               launch_sort_part(a, mode, c.items, c.rb, SORT_PART_PREFIX, st));
         TRACED(TK_EDGE_SCATTER, NE, (16.0 + (multi ? 8.0 : 0.0)) * NE,
-               launch_sort_part(a, mode, c.items, SORT_PART_SCATTER, st));
+               launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));
       } else {
         TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a);
       }
@@ -841,7 +861,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
     in0.seg_total = c.results + S;
     TRACED(TK_IN_COUNT, N, 8.0 * N,
-           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, SORT_PART_COUNT, st));
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
   } else {
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
@@ -892,11 +912,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     // first in-pass: sorted edge keys with repeats -> distinct (d, s) keys,
     // out_nbr and out_off at the de-duplicated positions
     TRACED(TK_IN_SCATTER, N, 8.0 * N + 12.0 * sumE + 8.0 * (sumV + S),
-           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, SORT_PART_SCATTER, st));
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
     uint64_t *ib[2] = {ukeys, sorted_edges};
     for (int p = 1; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ib[(p - 1) & 1], ib[p & 1], TM_ISORT, RANGE_EDGES, P_in, p,
-                                 32 + RADIX_BITS * p);
+                                 32 + c.rb * p);
       TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a);
     }
     TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
@@ -907,7 +927,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     uint32_t *ivb[2] = {uvals, multi ? vbuf[(P_e + 1) & 1] : nullptr};
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
-                                 32 + RADIX_BITS * p);
+                                 32 + c.rb * p);
       int mode = p == 0 ? SORT_IN_FIRST : SORT_IN;
       if (multi) {
         a.vin = ivb[p & 1];
@@ -946,7 +966,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
 }
 
 // Stable LSD sort of n keys by their low `bits` bits with the conversion's
-// radix passes (one table, plain mode); the last pass writes `out`.
+// radix passes (one table, plain mode, the schedule's digit width for n
+// rows); the last pass writes `out`.
 ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits, hipStream_t st) {
   prepare_pool();
   Call c;
@@ -957,15 +978,17 @@ ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits,
   c.plan[0].n = n;
   c.tmap.assign((size_t)TM_KINDS * 2, 0);
   c.items = items_for(n);
+  c.rb = digit_bits_for(n);
+  const int R = 1 << c.rb;
   c.sort_tile = sort_tile(c.items);
   c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
   const int64_t max_tiles = c.total(TM_ESORT) + 1;
-  const int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  const int passes = lsd_passes(bits, c.rb);
   c.meta_bytes = align_up(align_up(sizeof(SegPlan)) + sizeof(int64_t) * c.tmap.size());
   c.pin = pinned_acquire(Call::kUploadSlots * c.meta_bytes + sizeof(int64_t));
-  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * max_tiles, st);
-  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * RADIX * sort_runs_bound(max_tiles), st);
-  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * RADIX, st);
+  c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * max_tiles, st);
+  c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * sort_runs_bound(max_tiles), st);
+  c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * R, st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
   c.A = passes > 1 ? (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * n, st) : nullptr;
   ringo_status_t rc = RINGO_OK;
@@ -979,9 +1002,9 @@ ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits,
     const uint64_t *src_p = in;
     for (int p = 0; p < passes && rc == RINGO_OK; ++p) {
       uint64_t *dst_p = dst_of[p & 1];
-      const SortLaunch a = c.sort_args(src_p, dst_p, TM_ESORT, RANGE_ROWS, passes, p, RADIX_BITS * p);
-      if (launch_sort_part(a, SORT_PLAIN, c.items, SORT_PART_COUNT | SORT_PART_SCATTER, st) !=
-          hipSuccess)
+      const SortLaunch a = c.sort_args(src_p, dst_p, TM_ESORT, RANGE_ROWS, passes, p, c.rb * p);
+      if (launch_sort_part(a, SORT_PLAIN, c.items, c.rb, SORT_PART_COUNT | SORT_PART_SCATTER,
+                           st) != hipSuccess)
         rc = RINGO_ERR_HIP;
       src_p = dst_p;
     }
@@ -1098,14 +1121,16 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t, hipStream_t, void *),
 
 ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out) {
   if (!out || num_rows < 0) return RINGO_ERR_INVALID_ARG;
-  out->digit_bits = RADIX_BITS;
+  out->digit_bits = digit_bits_for(num_rows);
   out->items_per_thread = items_for(num_rows);
   out->node_method = method_for(num_rows);
   return RINGO_OK;
 }
 
 ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched) {
-  if (!sched || num_rows < 0 || sched->digit_bits != RADIX_BITS) return RINGO_ERR_INVALID_ARG;
+  if (!sched || num_rows < 0 || sched->digit_bits < MIN_DIGIT_BITS ||
+      sched->digit_bits > MAX_DIGIT_BITS)
+    return RINGO_ERR_INVALID_ARG;
   const int it = sched->items_per_thread;
   if (it != 8 && it != 12 && it != 16) return RINGO_ERR_INVALID_ARG;
   const int m = sched->node_method;
@@ -1114,6 +1139,7 @@ ringo_status_t ringo_tune_set(int64_t num_rows, const ringo_schedule_t *sched) {
   schedule_init_locked();
   const int k = ceil_log2(std::max<int64_t>(num_rows, 1));
   g_items[k] = it;
+  g_bits[k] = sched->digit_bits;
   g_method[k] = m;
   return RINGO_OK;
 }

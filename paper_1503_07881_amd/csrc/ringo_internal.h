@@ -6,9 +6,14 @@
 
 namespace ringo {
 
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
-constexpr int NODE_PASSES = 64 / RADIX_BITS;    // node identifiers are 64-bit keys
+// Radix digits of the LSD passes: 8 to 11 bits, chosen per table size by
+// the schedule table.
+constexpr int MIN_DIGIT_BITS = 8, MAX_DIGIT_BITS = 11, DEFAULT_DIGIT_BITS = 8;
+// LSD passes over the low `bits` bits of the keys with digits of rb bits.
+inline int lsd_passes(int bits, int rb) { return (bits + rb - 1) / rb; }
+// The remap's fused counts of the first edge pass are for 8-bit digits.
+constexpr int FUSED_RADIX_BITS = 8;
+constexpr int FUSED_RADIX = 1 << FUSED_RADIX_BITS;
 constexpr uint64_t SIGN_FLIP = 0x8000000000000000ull;  // unsigned order == signed order
 
 // Tile sizes (elements per tile) of the non-sorting kernels.
@@ -85,9 +90,10 @@ struct SortLaunch {
   int32_t range_kind;
   int64_t total_tiles;
   int32_t shift;
-  int64_t *digit_base;        // [S][RADIX] first output position of each digit's run
-  uint32_t *counts;           // [tiles + 1][RADIX] digit counts, then their prefixes
-  uint32_t *bsum;             // [runs][RADIX] counts of runs of tiles, then prefixes
+  // R = 2^digit bits of the pass
+  int64_t *digit_base;        // [S][R] first output position of each digit's run
+  uint32_t *counts;           // [tiles + 1][R] digit counts, then their prefixes
+  uint32_t *bsum;             // [runs][R] counts of runs of tiles, then prefixes
   const uint32_t *vin;        // values carried with the keys (key-value modes), else null
   uint32_t *vout;
   int64_t *seg_total;         // if set, the count part writes each table's key total
@@ -120,11 +126,26 @@ struct TileLaunch {
 
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t count, hipStream_t s);
-// One part of a pass: SORT_PART_COUNT (digit counts of every tile and their
-// prefixes) or SORT_PART_SCATTER (the stable scatter), or both;
-// SORT_PART_PREFIX instead of SORT_PART_COUNT when the tile counts
-// (counts [tile][RADIX]) were written by the kernel that produced the keys.
-hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int parts, hipStream_t s);
+// One part of a pass on digits of digit_bits bits (MIN_DIGIT_BITS to
+// MAX_DIGIT_BITS; anything else is hipErrorInvalidValue): SORT_PART_COUNT
+// (digit counts of every tile and their prefixes) or SORT_PART_SCATTER (the
+// stable scatter), or both; SORT_PART_PREFIX instead of SORT_PART_COUNT
+// when the tile counts (counts [tile][R]) were written by the kernel that
+// produced the keys.
+hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int digit_bits, int parts,
+                            hipStream_t s);
+// The same for one digit width (lsd.h, instantiated in lsd_d8.hip to
+// lsd_d11.hip).
+template <int RB>
+hipError_t launch_sort_part_rb(const SortLaunch &a, int mode, int items, int parts, hipStream_t s);
+// Tiles per upsweep run: the power of two in [4, 32] that gives about 2048
+// runs (blocks), so that small inputs still spread over the device.
+inline int run_tiles_for(int64_t tiles) {
+  const int64_t r = tiles / 2048;
+  int rt = 4;
+  while (rt < 32 && 2 * rt <= r) rt *= 2;
+  return rt;
+}
 int sort_tile(int items);
 int64_t sort_runs(int64_t tiles);
 int64_t sort_runs_bound(int64_t max_tiles);  // >= sort_runs(t) for every t <= max_tiles
@@ -193,8 +214,8 @@ hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
 // for launch_remap).
 // counts0 (directed and multigraph keys, sort tiles of sort_tile rows that
 // divide REMAP_TILE, tile map esort_tmap): the remap also writes the digit
-// counts of the first edge pass (bits [0, RADIX_BITS)) of every sort tile,
-// counts0 [tile][RADIX]; null otherwise.
+// counts of the first edge pass (8-bit digits, bits [0, FUSED_RADIX_BITS))
+// of every sort tile, counts0 [tile][FUSED_RADIX]; null otherwise.
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
                              uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
                              const int64_t *esort_tmap, int grid, hipStream_t s);

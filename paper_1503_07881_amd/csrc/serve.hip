@@ -52,11 +52,16 @@ struct Request {
 };
 
 // Bytes a request may need while it is converted: its input columns, the
-// workspace (two key buffers of 2n keys, per-tile counts, directory) and an
-// upper bound of its outputs (V <= 2n nodes, E <= n edges).
+// workspace (two key buffers of 2n keys, slot indices or directory, per-tile
+// digit counts of the schedule's tiles and digit width) and an upper bound
+// of its outputs (V <= 2n nodes, E <= n edges).
 int64_t footprint(int64_t n) {
   const int64_t input = 16 * n;
-  const int64_t workspace = 32 * n + 8 * n + (int64_t)(1 << 20);
+  ringo_schedule_t sc;
+  if (ringo_tune_get(n, &sc) != RINGO_OK) sc.digit_bits = 11, sc.items_per_thread = 8;
+  const int64_t tiles = 2 * n / (256 * sc.items_per_thread) + 2;
+  const int64_t counts = 4 * tiles * ((int64_t)1 << sc.digit_bits);
+  const int64_t workspace = 32 * n + 8 * n + counts + (int64_t)(1 << 20);
   const int64_t outputs = 8 * (2 * n) + 16 * (2 * n + 1) + 8 * n;
   return input + workspace + outputs;
 }

@@ -96,10 +96,16 @@ def test_tune_schedule_roundtrip():
     ringo.tune_set(1 << 20, 8, 8, ringo.NODES_SORT)         # back to the built-in default
     with pytest.raises(ringo.RingoError):
         ringo.tune_set(1000, 8, 16, 2)
-    with pytest.raises(ringo.RingoError):
-        ringo.tune_set(1000, 9, 16)
+    for bits in (9, 10, 11, 8):                                # digit widths 8 to 11
+        ringo.tune_set(1000, bits, 16)
+        assert ringo.tune_get(1000)[:2] == (bits, 16)
+    for bits in (0, 7, 12, 16):
+        with pytest.raises(ringo.RingoError):
+            ringo.tune_set(1000, bits, 16)
+    assert ringo.tune_get(1000)[0] == 8
     with pytest.raises(ringo.RingoError):
         ringo.tune_set(1000, 8, 7)
+    ringo.tune_set(1000, d, it, m)
 
 
 def test_generators_deterministic_and_shaped():

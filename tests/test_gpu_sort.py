@@ -1,7 +1,8 @@
 """The radix sort primitive (ringo_sort_keys) on the GPU through the C ABI:
 the conversion's LSD passes (Section 2.4 sorts the column copies) against a
 stable sort by the same key bits (numpy's stable argsort), bit-exact, across
-tile and run boundaries, digit counts and key distributions."""
+tile and run boundaries, digit counts, digit widths and key distributions."""
+import contextlib
 import sys
 
 import numpy as np
@@ -19,12 +20,26 @@ def say(*a):
     sys.stdout.flush()
 
 
-def expected(keys: np.ndarray, bits: int) -> np.ndarray:
-    """Stable sort by the low 8 * ceil(bits / 8) bits; higher bits ride along."""
-    width = 8 * ((bits + 7) // 8)
+def expected(keys: np.ndarray, bits: int, digit: int = 8) -> np.ndarray:
+    """Stable sort by the low digit * ceil(bits / digit) bits (at most 64);
+    higher bits ride along."""
+    width = min(64, digit * ((bits + digit - 1) // digit))
     u = keys.view(np.uint64)
     k = u if width == 64 else u & np.uint64((1 << width) - 1)
     return keys[np.argsort(k, kind="stable")]
+
+
+@contextlib.contextmanager
+def digit_bits(bits):
+    """Every size bucket's radix passes on `bits`-bit digits, restored after."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    try:
+        for e, (_, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, bits, it, m)
+        yield
+    finally:
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
 
 
 def run(keys: np.ndarray, bits: int, dev) -> np.ndarray:
@@ -116,3 +131,30 @@ def test_empty_and_invalid(cuda):
         ringo.sort_keys_raw(t.data_ptr(), t.data_ptr() + 8, 4, 64, 0)  # overlapping
     with pytest.raises(ringo.RingoError):
         ringo.sort_keys(t, 0)
+
+
+@pytest.mark.parametrize("digit", [9, 10, 11])
+def test_digit_widths(cuda, digit):
+    """Digits of 9 to 11 bits: ceil(bits / digit) passes, so the keys are
+    ordered by the low digit * ceil(bits / digit) bits."""
+    rng = np.random.default_rng(6000 + digit)
+    with digit_bits(digit):
+        for n in (1, TILE - 1, TILE + 1, 3 * TILE * 8 + 11, 300_007):
+            for bits in (1, digit, digit + 1, 22, 33, 44, 63, 64):
+                for kind in ("uniform", "few"):
+                    say("sort_keys digit", digit, "n", n, "bits", bits, kind)
+                    keys = keys_of(kind, n, bits, rng)
+                    assert np.array_equal(run(keys, bits, cuda), expected(keys, bits, digit)), (n, bits, kind)
+        # equal in the sorted bits (four digits): a stable sort keeps the order
+        keys = keys_of("equal", 100_003, 4 * digit, rng)
+        assert np.array_equal(run(keys, 4 * digit, cuda), keys)
+
+
+@pytest.mark.parametrize("n", [4096 * TILE - 1, 4096 * TILE + 1])
+def test_digit_widths_scan_paths(cuda, n):
+    """Both scan kernels with 2048 digits per tile."""
+    rng = np.random.default_rng(7000 + n % 7)
+    with digit_bits(11):
+        say("sort_keys 11-bit digits, scan boundary n", n)
+        keys = keys_of("few", n, 30, rng)
+        assert np.array_equal(run(keys, 30, cuda), expected(keys, 30, 11))
