@@ -35,8 +35,10 @@ ROCPROF_NAME = {
     "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
     "unique": "k_unique",
     "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe", "in_csr": "k_in_csr",
-    "sort_node_scatter": "k_downsweep<256, {items}, 1|3>", "sort_vnode_scatter": "k_downsweep<256, {items}, 4>",
-    "sort_edge_scatter": "k_downsweep<256, {items}, 5>", "sort_in_scatter": "k_downsweep<256, {items}, 2|6>",
+    "sort_node_scatter": "k_downsweep<256, {items}, 1|3, {bits}>",
+    "sort_vnode_scatter": "k_downsweep<256, {items}, 4, {bits}>",
+    "sort_edge_scatter": "k_downsweep<256, {items}, 5, {bits}>",
+    "sort_in_scatter": "k_downsweep<256, {items}, 2|6, {bits}>",
 }
 
 
@@ -47,6 +49,8 @@ def log(*a):
 def kernel_source_file(kernel: str) -> str:
     if kernel == "edge_table":
         return "to_table.hip"
+    if kernel.startswith("sort_"):
+        return "lsd.h"
     return "hash.hip" if kernel.startswith("hash_") else "kernels.hip"
 
 
@@ -84,7 +88,7 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
-CONVERSION_SOURCES = ("kernels.hip", "hash.hip", "pipeline.hip", "device_common.h")
+CONVERSION_SOURCES = ("kernels.hip", "lsd.h", "hash.hip", "pipeline.hip", "device_common.h")
 
 
 def conversion_source_sha() -> str:
@@ -518,7 +522,7 @@ def main():
     traffic = read_traffic(dom, workload)
     conv_bytes = read_conversion_traffic(workload) if args.kind == "directed" else None
     io_min = 16 * n + 24 * V + 8 + 8 * E
-    items = ringo.tune_get(n)[1]
+    bits, items = ringo.tune_get(n)[:2]
 
     out = {
         "metric": ("edges/s converted (input rows per second, table to directed simple graph, 1 GPU)"
@@ -537,10 +541,10 @@ def main():
         "data": "synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)",
         "config": {"workload": workload, "graph_kind": args.kind,
                    "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
-                   "digit_bits": 8, "items_per_thread": items,
+                   "digit_bits": bits, "items_per_thread": items,
                    "node_method": "hash" if ringo.tune_get(n)[2] == ringo.NODES_HASH else "sort"},
         "roofline": {"bound": "hbm", "kernel": dom,
-                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items),
+                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items, bits=bits),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      # the counter-measured bytes over the same launch time (line-granular

@@ -2,12 +2,13 @@
 
 For every table-size bucket (powers of two of rows), the conversion is timed
 on the device with each supported tile shape (items per thread of the
-scatter tile; digit width is 8 bits) and each node-numbering method (radix
-sort of all identifiers, or the node hash table), and the fastest is kept.  Results are
-cached as JSON (RINGO_TUNE_CACHE, else the in-tree tuned_schedules.json
-measured on an MI355X) and applied to the library through ringo_tune_set.
-The schedule changes only the tiling: the output is the same bit for bit
-whichever schedule runs.
+scatter tile), each radix digit width (8 to 11 bits) and each node-numbering
+method (radix sort of all identifiers, or the node hash table), and the
+fastest is kept.  Results are cached as JSON (RINGO_TUNE_CACHE, else the
+in-tree tuned_schedules.json measured on an MI355X) and applied to the
+library through ringo_tune_set.  The schedule changes only the tiling and
+the number of passes: the output is the same bit for bit whichever schedule
+runs.
 
     python -m paper_1503_07881_amd.autotune            # tune and save
     from paper_1503_07881_amd import autotune; autotune.apply()   # load and apply
@@ -22,7 +23,7 @@ from . import ringo, workloads
 
 ITEMS = (8, 12, 16)
 METHODS = (ringo.NODES_SORT, ringo.NODES_HASH)
-DIGIT_BITS = 8
+DIGIT_BITS = (8, 9, 10, 11)
 
 
 def cache_path() -> str:
@@ -37,11 +38,12 @@ def _device_name() -> str:
 
 def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> dict:
     """Times every schedule for R-MAT tables of 2^k rows; returns
-    {"device": ..., "buckets": {str(rows): {"items": i, "node_method": m, "ms": {...}}}}."""
+    {"device": ..., "buckets": {str(rows): {"items": i, "digit_bits": d, "node_method": m,
+    "ms": {...}}}}."""
     import torch
     dev = torch.device("cuda:0")
     sh = torch.cuda.current_stream().cuda_stream
-    out = {"device": _device_name(), "digit_bits": DIGIT_BITS, "buckets": {}}
+    out = {"device": _device_name(), "buckets": {}}
     for k in log2_sizes:
         n = 1 << k
         spec = workloads.TableSpec("rmat", n, seed=99, table=k, scale=workloads.rmat_scale_for(n))
@@ -50,23 +52,28 @@ def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> d
         workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
         times = {}
         for method in METHODS:
-            for items in ITEMS:
-                ringo.tune_set(n, DIGIT_BITS, items, method)
-                ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
-                torch.cuda.synchronize()
-                ts = []
-                for _ in range(reps):
+            for bits in DIGIT_BITS:
+                for items in ITEMS:
+                    ringo.tune_set(n, bits, items, method)
                     t0 = time.perf_counter()
                     ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
                     torch.cuda.synchronize()
-                    ts.append(time.perf_counter() - t0)
-                times[(method, items)] = sorted(ts)[len(ts) // 2] * 1e3
-        method, items = min(times, key=times.get)
-        out["buckets"][str(n)] = {"items": items, "node_method": method,
-                                  "ms": {f"{'hash' if m else 'sort'}/{i}": round(v, 4)
-                                         for (m, i), v in times.items()}}
+                    # small tables take milliseconds or less and vary from call
+                    # to call: enough repetitions for about 50 ms each
+                    first = time.perf_counter() - t0
+                    ts = []
+                    for _ in range(max(reps, min(50, int(0.05 / max(first, 1e-6))))):
+                        t0 = time.perf_counter()
+                        ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
+                        torch.cuda.synchronize()
+                        ts.append(time.perf_counter() - t0)
+                    times[(method, bits, items)] = sorted(ts)[len(ts) // 2] * 1e3
+        method, bits, items = min(times, key=times.get)
+        out["buckets"][str(n)] = {"items": items, "digit_bits": bits, "node_method": method,
+                                  "ms": {f"{'hash' if m else 'sort'}/d{d}/{i}": round(v, 4)
+                                         for (m, d, i), v in times.items()}}
         if verbose:
-            print(f"rows 2^{k}: best {'hash' if method else 'sort'}/{items}  "
+            print(f"rows 2^{k}: best {'hash' if method else 'sort'}/d{bits}/{items}  "
                   f"{out['buckets'][str(n)]['ms']}", flush=True)
         del src, dst
     apply(out)
@@ -93,21 +100,25 @@ def apply(cache: dict | None = None) -> int:
     """Sets the library's schedule for every size bucket from the cache;
     buckets between two tuned sizes take the schedule of the nearest tuned
     size below (the smallest tuned size for buckets below it).  A cached
-    bucket without a node method keeps the library's."""
+    bucket without a node method keeps the library's; one without a digit
+    width takes the cache's top-level "digit_bits", else 8.  Buckets with an
+    unsupported entry are ignored."""
     cache = cache if cache is not None else load()
-    if not cache or cache.get("digit_bits", DIGIT_BITS) != DIGIT_BITS:
+    if not cache:
         return 0
-    buckets = sorted((int(k), v["items"], v.get("node_method"))
+    default_bits = cache.get("digit_bits", 8)
+    buckets = sorted((int(k), v.get("digit_bits", default_bits), v["items"], v.get("node_method"))
                      for k, v in cache.get("buckets", {}).items()
-                     if v.get("items") in ITEMS and v.get("node_method", 0) in METHODS)
+                     if v.get("items") in ITEMS and v.get("node_method", 0) in METHODS
+                     and v.get("digit_bits", default_bits) in DIGIT_BITS)
     if not buckets:
         return 0
     applied = 0
     for e in range(0, 63):
         rows = 1 << e
-        below = [(it, m) for n, it, m in buckets if n <= rows]
-        items, method = below[-1] if below else buckets[0][1:]
-        ringo.tune_set(rows, DIGIT_BITS, items, method)
+        below = [(d, it, m) for n, d, it, m in buckets if n <= rows]
+        bits, items, method = below[-1] if below else buckets[0][1:]
+        ringo.tune_set(rows, bits, items, method)
         applied += 1
     return applied
 

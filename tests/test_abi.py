@@ -138,18 +138,24 @@ def test_config4_sizes():
 
 def test_autotune_cache_roundtrip(tmp_path):
     from paper_1503_07881_amd import autotune
-    cache = {"device": "test", "digit_bits": 8,
-             "buckets": {str(1 << 10): {"items": 8, "node_method": 0}, str(1 << 20): {"items": 12, "node_method": 1},
+    cache = {"device": "test",
+             "buckets": {str(1 << 10): {"items": 8, "digit_bits": 9, "node_method": 0},
+                         str(1 << 20): {"items": 12, "digit_bits": 11, "node_method": 1},
                          str(1 << 24): {"items": 16}}}
     path = autotune.save(cache, str(tmp_path / "tune.json"))
     assert autotune.load(path) == cache
     assert autotune.apply(autotune.load(path)) == 63
-    assert ringo.tune_get(1 << 5)[1] == 8      # below the first tuned size: nearest
-    assert ringo.tune_get(1 << 15)[1] == 8
-    assert ringo.tune_get(1 << 21)[1:] == (12, 1)
-    assert ringo.tune_get(1 << 30)[1] == 16
+    assert ringo.tune_get(1 << 5)[:2] == (9, 8)      # below the first tuned size: nearest
+    assert ringo.tune_get(1 << 15)[:2] == (9, 8)
+    assert ringo.tune_get(1 << 21) == (11, 12, 1)
+    assert ringo.tune_get(1 << 30)[:2] == (8, 16)     # no digit width in the bucket: 8
     assert ringo.tune_get(1 << 15)[2] == 0
     assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
+    # an unsupported digit width or tile shape is ignored
+    assert autotune.apply({"buckets": {"1": {"items": 8, "digit_bits": 12}, "2": {"items": 10}}}) == 0
+    # a cache whose top-level width covers every bucket
+    assert autotune.apply({"digit_bits": 10, "buckets": {"1": {"items": 12, "node_method": 0}}}) == 63
+    assert ringo.tune_get(1 << 40)[:2] == (10, 12)
     # restore the built-in default
     autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 8, "node_method": 0},
                                                   str(1 << 24): {"items": 8, "node_method": 1}}})
