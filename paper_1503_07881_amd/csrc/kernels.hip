@@ -7,7 +7,7 @@
 // tables of a batch at once:
 //
 //   node keys   2n (id ^ 2^63) keys per table, least-significant-digit radix
-//               sort, 8-bit digits, 8 passes
+//               sort, ceil(64 / d) passes of d-bit digits (8 by default)
 //   unique      head flags on the sorted keys + stream compaction -> nodes
 //   directory   bucket index over the sorted nodes for the remap lookups
 //   remap       every row's (src, dst) -> dense positions, packed into
@@ -20,8 +20,9 @@
 //   dedupe      adjacent compare + compaction (undirected graphs,
 //               multigraph offsets)
 //
-// (hash.hip holds the alternative node numbering through a node hash table,
-// small.hip the single-workgroup conversion of small tables.)
+// (lsd.h holds the radix pass kernels, hash.hip the alternative node
+// numbering through a node hash table, small.hip the single-workgroup
+// conversion of small tables.)
 //
 // Each radix pass is a tile-granular reduce-then-scan: an upsweep counts the
 // digits of every tile, a scan over tiles turns the counts into per-tile
