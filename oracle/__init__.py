@@ -35,7 +35,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 def build(source: str = SRC_PATH, out: str = LIB_PATH) -> str:
     """Compile the oracle with the host C++ compiler (no GPU code)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out, source]
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", out, source]
     subprocess.run(cmd, check=True)
     return out
 
@@ -62,6 +62,7 @@ class OracleError(RuntimeError):
 
 
 _libs: dict[str, ctypes.CDLL] = {}
+last_threads = 1  # host threads the last table_to_graph call used
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         L.oracle_table_to_graph.argtypes = [p, p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.oracle_table_to_graph.restype = ctypes.c_int
+        L.oracle_table_to_graph_par.argtypes = L.oracle_table_to_graph.argtypes + [ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_table_to_graph_par.restype = ctypes.c_int
         L.oracle_copy.argtypes = [p, p, p, p, p, p]
         L.oracle_copy.restype = None
         L.oracle_free.argtypes = [p]
@@ -86,7 +89,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     return _libs[path]
 
 
-def table_to_graph(src, dst, lib_path: str = LIB_PATH) -> Graph:
+def table_to_graph(src, dst, lib_path: str = LIB_PATH, all_cores: bool = False) -> Graph:
+    """The directed conversion. all_cores: the same steps with a parallel sort
+    on every host thread (for timing; the result is identical); the thread
+    count used is then in the module's last_threads."""
+    global last_threads
     src = np.ascontiguousarray(src, dtype=np.int64)
     dst = np.ascontiguousarray(dst, dtype=np.int64)
     if src.shape != dst.shape or src.ndim != 1:
@@ -95,8 +102,15 @@ def table_to_graph(src, dst, lib_path: str = LIB_PATH) -> Graph:
     h = ctypes.c_void_p()
     V = ctypes.c_int64()
     E = ctypes.c_int64()
-    rc = L.oracle_table_to_graph(src.ctypes.data, dst.ctypes.data, src.size, ctypes.byref(h),
-                                 ctypes.byref(V), ctypes.byref(E))
+    if all_cores:
+        t = ctypes.c_int32()
+        rc = L.oracle_table_to_graph_par(src.ctypes.data, dst.ctypes.data, src.size, ctypes.byref(h),
+                                         ctypes.byref(V), ctypes.byref(E), ctypes.byref(t))
+        last_threads = t.value
+    else:
+        rc = L.oracle_table_to_graph(src.ctypes.data, dst.ctypes.data, src.size, ctypes.byref(h),
+                                     ctypes.byref(V), ctypes.byref(E))
+        last_threads = 1
     if rc != 0:
         raise OracleError({1: "invalid argument", 2: "too many nodes", 3: "out of memory"}.get(rc, str(rc)))
     try:

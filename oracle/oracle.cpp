@@ -29,6 +29,11 @@
 // Parity: pinned by hand-worked fixtures, brute force over Python sets,
 // an independent numpy/scipy route, closed forms and invariants (tests/).
 //
+// oracle_table_to_graph_par is the same computation with libstdc++'s
+// parallel-mode sort (OpenMP, all host threads) in place of std::sort, for
+// timing the oracle on every core; sorting values of a total order gives
+// the same sequence either way, so the result is identical.
+//
 // Two further graph kinds (oracle_table_to_graph_kind), the same definition
 // with another edge rule (the paper limits its discussion to directed graphs,
 // Section 2.4; these are the readings taken for the other two):
@@ -38,10 +43,12 @@
 //   * multigraph: every row is its own edge, identified by its row index;
 //     out-lists ascend by (destination, row), in-lists by (source, row).
 
+#include <omp.h>
 #include <stdint.h>
 
 #include <algorithm>
 #include <new>
+#include <parallel/algorithm>
 #include <utility>
 #include <vector>
 
@@ -89,14 +96,18 @@ void build_direction(const std::vector<std::pair<int32_t, int32_t>> &pairs, int6
   for (size_t i = 0; i < pairs.size(); ++i) nbr[i] = pairs[i].second;
 }
 
-}  // namespace
-
-extern "C" {
+struct SerialSort {
+  template <class It> void operator()(It b, It e) const { std::sort(b, e); }
+};
+struct ParallelSort {
+  template <class It> void operator()(It b, It e) const { __gnu_parallel::sort(b, e); }
+};
 
 // Returns 0 on success, 1 on invalid arguments, 2 when V > 2^31 - 1,
 // 3 when host memory runs out.  On success *handle owns the result.
-int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **handle,
-                          int64_t *num_nodes, int64_t *num_edges) {
+template <class Sort>
+int table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **handle,
+                   int64_t *num_nodes, int64_t *num_edges, Sort sort) {
   if (!handle || !num_nodes || !num_edges || n < 0 || n > INT32_MAX) return 1;
   if (n > 0 && (!src || !dst)) return 1;
   *handle = nullptr;
@@ -107,7 +118,7 @@ int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, voi
     all.reserve((size_t)2 * n);
     all.insert(all.end(), src, src + n);
     all.insert(all.end(), dst, dst + n);
-    std::sort(all.begin(), all.end());
+    sort(all.begin(), all.end());
     all.erase(std::unique(all.begin(), all.end()), all.end());
     g->nodes.swap(all);
     const int64_t V = (int64_t)g->nodes.size();
@@ -122,12 +133,12 @@ int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, voi
     // repeated pairs removed.
     std::vector<std::pair<int32_t, int32_t>> e((size_t)n);
     for (int64_t r = 0; r < n; ++r) e[(size_t)r] = {index_of(src[r]), index_of(dst[r])};
-    std::sort(e.begin(), e.end());
+    sort(e.begin(), e.end());
     e.erase(std::unique(e.begin(), e.end()), e.end());
     build_direction(e, V, g->out_off, g->out_nbr);
     // In-direction: the same edges keyed by destination.
     for (auto &p : e) std::swap(p.first, p.second);
-    std::sort(e.begin(), e.end());
+    sort(e.begin(), e.end());
     build_direction(e, V, g->in_off, g->in_nbr);
     *num_nodes = V;
     *num_edges = (int64_t)e.size();
@@ -136,6 +147,23 @@ int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, voi
   } catch (const std::bad_alloc &) {
     return 3;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **handle,
+                          int64_t *num_nodes, int64_t *num_edges) {
+  return table_to_graph(src, dst, n, handle, num_nodes, num_edges, SerialSort());
+}
+
+// The same on all host threads (timing only); returns the thread count
+// used in *threads.
+int oracle_table_to_graph_par(const int64_t *src, const int64_t *dst, int64_t n, void **handle,
+                              int64_t *num_nodes, int64_t *num_edges, int32_t *threads) {
+  if (threads) *threads = omp_get_max_threads();
+  return table_to_graph(src, dst, n, handle, num_nodes, num_edges, ParallelSort());
 }
 
 // Copies the result into caller-owned arrays of sizes V, V+1, E, V+1, E.

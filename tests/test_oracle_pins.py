@@ -147,6 +147,21 @@ def test_errors():
     assert L.oracle_table_to_graph(None, None, 5, ctypes.byref(h), ctypes.byref(V), ctypes.byref(E)) == 1
 
 
+@pytest.mark.parametrize("seed,n,pool", [(11, 0, 1), (12, 1, 1), (13, 64, 5), (14, 50_000, 2_000),
+                                         (15, 400_000, 1 << 40)])
+def test_all_cores_mode_same_result(seed, n, pool):
+    """The timing mode on every host thread (a parallel sort in place of
+    std::sort) gives the serial oracle's graph."""
+    rng = np.random.default_rng(seed)
+    src, dst = tiny_table(rng, n, min(pool, 1 << 20))
+    serial = oracle.table_to_graph(src, dst)
+    assert_same(oracle.table_to_graph(src, dst, all_cores=True), serial)
+    assert oracle.last_threads >= 1
+    for ex in load_examples():
+        s, d = np.array(ex["src"], np.int64), np.array(ex["dst"], np.int64)
+        assert_same(oracle.table_to_graph(s, d, all_cores=True), as_np(ex), ex["name"] + ": ")
+
+
 def test_config1_full_invariants():
     """The 1M-row workload: oracle vs the scipy route, plus the invariants."""
     src, dst = workloads.generate_host(workloads.config1())
@@ -167,14 +182,14 @@ def test_config1_full_invariants():
 MUTANTS = {
     "no_edge_dedupe": ("e.erase(std::unique(e.begin(), e.end()), e.end());", ""),
     "no_node_dedupe": ("all.erase(std::unique(all.begin(), all.end()), all.end());", ""),
-    "unsigned_node_order": ("    std::sort(all.begin(), all.end());",
+    "unsigned_node_order": ("    sort(all.begin(), all.end());",
                             "    std::sort(all.begin(), all.end(), [](int64_t a, int64_t b) { return (uint64_t)a < (uint64_t)b; });"),
     "swapped_columns": ("e[(size_t)r] = {index_of(src[r]), index_of(dst[r])};",
                         "e[(size_t)r] = {index_of(dst[r]), index_of(src[r])};"),
     "offset_off_by_one": ("for (const auto &p : pairs) off[(size_t)p.first + 1] += 1;",
                           "for (const auto &p : pairs) off[(size_t)p.first] += 1;"),
     "in_not_transposed": ("for (auto &p : e) std::swap(p.first, p.second);", ""),
-    "in_unsorted": ("std::swap(p.first, p.second);\n    std::sort(e.begin(), e.end());",
+    "in_unsorted": ("std::swap(p.first, p.second);\n    sort(e.begin(), e.end());",
                     "std::swap(p.first, p.second);"),
     "only_src_nodes": ("all.insert(all.end(), dst, dst + n);", ""),
     "prefix_sum_skips_last": ("for (int64_t v = 0; v < V; ++v) off[(size_t)v + 1] += off[(size_t)v];",
@@ -209,7 +224,7 @@ def test_pins_catch_planted_mistakes(name, tmp_path):
     src = tmp_path / "mutant.cpp"
     src.write_text(text.replace(old, new))
     lib = str(tmp_path / "libmutant.so")
-    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", lib, str(src)], check=True)
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", lib, str(src)], check=True)
     assert run_pins(lib) is not None, f"mutant {name} passed every pin"
 
 
