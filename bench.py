@@ -121,6 +121,25 @@ def read_conversion_traffic(workload: str):
         return None
 
 
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, CPU model, memory."""
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["mem_GiB"] = round(int(line.split()[1]) / (1 << 20), 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(rows: int):
     import numpy as np  # noqa: F401
     import oracle
@@ -143,6 +162,7 @@ def cpu_baseline(rows: int):
     par = {"value": rows / dp, "unit": "edges/s", "cores": oracle.last_threads, "kind": "oracle",
            "sample": f"{what}; the oracle with a parallel sort (libstdc++ parallel mode) on "
                      f"{oracle.last_threads} threads, {dp:.2f} s"}
+    single["host"] = par["host"] = host_info()
     return single, par
 
 
