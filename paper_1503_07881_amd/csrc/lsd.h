@@ -325,8 +325,8 @@ constexpr int ds_waves(int items, int mode, int rb) {
   return mode == SORT_IN_FIRST_DEDUP
              ? (items <= 8 ? (rb <= 9 ? 3 : 2) : items <= 12 ? 2 : (rb <= 9 ? 2 : 1))
          : (mode == SORT_EDGE_KV || mode == SORT_IN_FIRST_KV || mode == SORT_IN_KV)
-             ? (items <= 8 ? (rb <= 9 ? 4 : 3) : items <= 12 ? 3 : 2)
-             : (items <= 8 ? (rb <= 10 ? 4 : 3) : 3);
+             ? (items <= 8 ? (rb <= 9 ? 4 : 3) : items <= 12 ? (rb <= 9 ? 3 : 2) : 2)
+             : (items <= 8 ? (rb <= 10 ? 4 : 3) : items <= 12 || rb == 8 ? 3 : 2);
 }
 
 template <int BLOCK, int ITEMS, int MODE, int RB>
