@@ -202,7 +202,8 @@ def sort_keys_raw(in_ptr: int, out_ptr: int, n: int, bits: int, stream: int) -> 
 
 def sort_keys(keys: torch.Tensor, bits: int = 64, stream=None) -> torch.Tensor:
     """Stable radix sort of int64 keys (as uint64 bit patterns) by their low
-    8 * ceil(bits / 8) bits (whole 8-bit digits); returns a new tensor."""
+    min(64, d * ceil(bits / d)) bits, d being the schedule's digit width for
+    that many keys (tune_get; 8 by default); returns a new tensor."""
     if not isinstance(keys, torch.Tensor) or keys.dtype != torch.int64 or keys.dim() != 1 or not keys.is_cuda:
         raise TypeError("keys must be a 1-D int64 tensor on the GPU")
     keys = keys.contiguous()
