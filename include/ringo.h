@@ -253,7 +253,8 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
  *                     bound (an estimate far too low), the call falls back to
  *                     RINGO_NODES_SORT by itself.
  * Built-in defaults (measured on an MI355X): RINGO_NODES_SORT up to 2^23 rows,
- * RINGO_NODES_HASH above; 8 items per thread; 8-bit digits.
+ * RINGO_NODES_HASH above; 8 items per thread and 8-bit digits up to 2^26
+ * rows, 16 items above, and 9-bit digits from 2^29 rows.
  */
 #define RINGO_NODES_SORT 0
 #define RINGO_NODES_HASH 1

@@ -147,21 +147,25 @@ void pinned_release(Pinned *b, hipStream_t s) {
 
 // Items per thread of the scatter tile, digit bits of the radix passes and
 // node-numbering method by table size (log2 buckets of rows).  Built-in
-// defaults, from the autotuner's measurements on an MI355X (R-MAT tables,
-// 2^10 to 2^26 rows): the sort numbering up to 2^23 rows and the hash
-// numbering above; 8 items per thread (within measurement noise of 16 at
-// 2^26 rows); 8-bit digits.
+// defaults, from measurements on an MI355X (R-MAT tables, 2^10 to 1.5e9
+// rows): the sort numbering up to 2^23 rows and the hash numbering above;
+// 8 items per thread and 8-bit digits up to 2^26 rows (16 items within
+// noise there); above, 16 items (full 128-byte digit runs), and from 2^29
+// rows 9-bit digits, which save an edge pass and an in-pass once node
+// indices need 25 bits or more (3-4% faster at 2^29 and 1.5e9 rows).
 int g_items[64];
 int g_bits[64];
 int g_method[64];
 bool g_items_init = false;
 constexpr int HASH_DEFAULT_LOG2 = 24;
+constexpr int WIDE_TILE_LOG2 = 27;   // 16 items per thread from 2^27 rows
+constexpr int WIDE_DIGIT_LOG2 = 29;  // 9-bit digits from 2^29 rows
 
 void schedule_init_locked() {
   if (g_items_init) return;
   for (int i = 0; i < 64; ++i) {
-    g_items[i] = 8;
-    g_bits[i] = DEFAULT_DIGIT_BITS;
+    g_items[i] = i >= WIDE_TILE_LOG2 ? 16 : 8;
+    g_bits[i] = i >= WIDE_DIGIT_LOG2 ? 9 : DEFAULT_DIGIT_BITS;
     g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
   }
   g_items_init = true;

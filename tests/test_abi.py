@@ -86,6 +86,10 @@ def test_invalid_arguments_rejected_on_host():
 def test_tune_schedule_roundtrip():
     d, it, m = ringo.tune_get(1000)
     assert d == 8 and it in (8, 12, 16) and m == ringo.NODES_SORT
+    # built-in tile shape and digit width by table size
+    assert ringo.tune_get(1 << 26)[:2] == (8, 8)
+    assert ringo.tune_get(1 << 28)[:2] == (8, 16)
+    assert ringo.tune_get(1_500_000_000)[:2] == (9, 16)
     assert ringo.tune_get(1 << 24)[2] == ringo.NODES_HASH   # built-in default for large tables
     assert ringo.tune_get(1 << 20)[2] == ringo.NODES_SORT   # built-in default below 2^24 rows
     ringo.tune_set(1 << 20, 8, 12)
@@ -138,6 +142,7 @@ def test_config4_sizes():
 
 def test_autotune_cache_roundtrip(tmp_path):
     from paper_1503_07881_amd import autotune
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
     cache = {"device": "test",
              "buckets": {str(1 << 10): {"items": 8, "digit_bits": 9, "node_method": 0},
                          str(1 << 20): {"items": 12, "digit_bits": 11, "node_method": 1},
@@ -156,6 +161,6 @@ def test_autotune_cache_roundtrip(tmp_path):
     # a cache whose top-level width covers every bucket
     assert autotune.apply({"digit_bits": 10, "buckets": {"1": {"items": 12, "node_method": 0}}}) == 63
     assert ringo.tune_get(1 << 40)[:2] == (10, 12)
-    # restore the built-in default
-    autotune.apply({"digit_bits": 8, "buckets": {str(1): {"items": 8, "node_method": 0},
-                                                  str(1 << 24): {"items": 8, "node_method": 1}}})
+    # restore the library's schedule
+    for e, (d, it, m) in enumerate(saved):
+        ringo.tune_set(1 << e, d, it, m)

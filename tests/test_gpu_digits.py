@@ -85,7 +85,7 @@ def test_kinds_and_methods(cuda, bits, kname):
 
 
 @pytest.mark.parametrize("items", [8, 12, 16])
-@pytest.mark.parametrize("bits", [8, 11])
+@pytest.mark.parametrize("bits", [8, 9, 11])
 def test_items_with_digit_bits(cuda, items, bits):
     spec = workloads.TableSpec("rmat", 1 << 19, seed=71, scale=16)
     src, dst = workloads.generate_host(spec)
