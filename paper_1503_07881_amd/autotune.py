@@ -97,12 +97,13 @@ def load(path: str | None = None) -> dict | None:
 
 
 def apply(cache: dict | None = None) -> int:
-    """Sets the library's schedule for every size bucket from the cache;
+    """Sets the library's schedule for the size buckets the cache covers;
     buckets between two tuned sizes take the schedule of the nearest tuned
-    size below (the smallest tuned size for buckets below it).  A cached
-    bucket without a node method keeps the library's; one without a digit
-    width takes the cache's top-level "digit_bits", else 8.  Buckets with an
-    unsupported entry are ignored."""
+    size below (the smallest tuned size for buckets below it), and buckets
+    above the largest tuned size keep the library's.  A cached bucket
+    without a node method keeps the library's; one without a digit width
+    takes the cache's top-level "digit_bits", else 8.  Buckets with an
+    unsupported entry are ignored.  Returns the number of buckets set."""
     cache = cache if cache is not None else load()
     if not cache:
         return 0
@@ -114,8 +115,11 @@ def apply(cache: dict | None = None) -> int:
     if not buckets:
         return 0
     applied = 0
+    largest = buckets[-1][0]
     for e in range(0, 63):
         rows = 1 << e
+        if rows > largest:
+            break
         below = [(d, it, m) for n, d, it, m in buckets if n <= rows]
         bits, items, method = below[-1] if below else buckets[0][1:]
         ringo.tune_set(rows, bits, items, method)

@@ -149,17 +149,19 @@ def test_autotune_cache_roundtrip(tmp_path):
                          str(1 << 24): {"items": 16}}}
     path = autotune.save(cache, str(tmp_path / "tune.json"))
     assert autotune.load(path) == cache
-    assert autotune.apply(autotune.load(path)) == 63
+    assert autotune.apply(autotune.load(path)) == 25  # buckets 2^0 .. 2^24
     assert ringo.tune_get(1 << 5)[:2] == (9, 8)      # below the first tuned size: nearest
     assert ringo.tune_get(1 << 15)[:2] == (9, 8)
     assert ringo.tune_get(1 << 21) == (11, 12, 1)
-    assert ringo.tune_get(1 << 30)[:2] == (8, 16)     # no digit width in the bucket: 8
+    assert ringo.tune_get(1 << 24)[:2] == (8, 16)     # no digit width in the bucket: 8
+    assert ringo.tune_get(1 << 30)[:2] == (9, 16)     # above the largest tuned size: the library's
     assert ringo.tune_get(1 << 15)[2] == 0
     assert autotune.apply({"digit_bits": 11, "buckets": {}}) == 0
     # an unsupported digit width or tile shape is ignored
     assert autotune.apply({"buckets": {"1": {"items": 8, "digit_bits": 12}, "2": {"items": 10}}}) == 0
-    # a cache whose top-level width covers every bucket
-    assert autotune.apply({"digit_bits": 10, "buckets": {"1": {"items": 12, "node_method": 0}}}) == 63
+    # a cache whose top-level width covers every bucket it sets
+    assert autotune.apply({"digit_bits": 10, "buckets": {"1": {"items": 12, "node_method": 0},
+                                                         str(1 << 40): {"items": 12, "node_method": 1}}}) == 41
     assert ringo.tune_get(1 << 40)[:2] == (10, 12)
     # restore the library's schedule
     for e, (d, it, m) in enumerate(saved):
