@@ -580,13 +580,17 @@ def main():
                      # traffic of random accesses included), against the same peak
                      "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None,
                      "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBPS, 4) if traffic else None,
+                     "traffic_frac_of_copy": round(traffic / avg_s / 1e9 / copy_gbps, 4) if traffic else None,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_s * 1e3, 5)},
         "ms_per_step_untraced": ms_untraced,
         # every kernel of one conversion together: counter-measured HBM bytes
         # over the untraced conversion time
+        # (frac: of the 8 TB/s peak; frac_of_copy: of what the copy kernel
+        # measured in this run)
         "conversion_traffic": ({"bytes": conv_bytes, "GBps": round(conv_bytes / (ms_untraced / 1e3) / 1e9, 1),
-                                "frac": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                                "frac": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                "frac_of_copy": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / copy_gbps, 4)}
                                if conv_bytes else None),
         # reading the table once and writing the graph once: 16n + 24V + 8 + 8E bytes
         "io_minimum": {"bytes": io_min, "GBps": round(io_min / (ms_untraced / 1e3) / 1e9, 1),
