@@ -540,21 +540,43 @@ hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
 
 __global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in,
                                                 const uint32_t *vals) {
+  constexpr int U = 4;  // keys per thread in flight
+  const int lane = threadIdx.x & 63;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
-    const uint64_t *K = in + P.row_off;
+    const __attribute__((address_space(1))) uint64_t *K = G(in) + P.row_off;
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
     const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.E);
-    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
-      const uint64_t k = K[j];
-      G(P.in_nbr)[j] = (int32_t)(uint32_t)k;
-      if (vals) G(P.in_eid)[j] = (int32_t)G(vals)[P.row_off + j];
-      const int64_t h = std::min<int64_t>((int64_t)(k >> 32), P.V - 1);
-      const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(K[j - 1] >> 32), P.V - 1);
-      for (int64_t v = hp + 1; v <= h; ++v) G(P.in_off)[v] = j;
-      if (j == P.E - 1)
-        for (int64_t v = h + 1; v <= P.V; ++v) G(P.in_off)[v] = P.E;
+    const int64_t last = P.V - 1;
+    for (int64_t j0 = base + threadIdx.x; j0 < end; j0 += U * 256) {
+      // A wave's lanes hold consecutive keys, so each key's predecessor is
+      // the lane below's key; lane 0 loads its own.
+      uint64_t k[U], kp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = std::min<int64_t>(j0 + u * 256, end - 1);
+        k[u] = K[j];
+        kp[u] = (lane == 0 && j > 0) ? K[j - 1] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t below = __shfl_up(k[u], 1, 64);
+        if (lane != 0) kp[u] = below;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + u * 256;
+        if (j < end) {
+          G(P.in_nbr)[j] = (int32_t)(uint32_t)k[u];
+          if (vals) G(P.in_eid)[j] = (int32_t)G(vals)[P.row_off + j];
+          const int64_t h = std::min<int64_t>((int64_t)(k[u] >> 32), last);
+          const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(kp[u] >> 32), last);
+          for (int64_t v = hp + 1; v <= h; ++v) G(P.in_off)[v] = j;
+          if (j == P.E - 1)
+            for (int64_t v = h + 1; v <= P.V; ++v) G(P.in_off)[v] = P.E;
+        }
+      }
     }
   }
 }
