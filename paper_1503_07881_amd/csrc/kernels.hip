@@ -524,6 +524,60 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
   }
 }
 
+// Multigraph: every sorted key is its own edge, so an edge's position is its
+// index and only the out-offsets need writing (a boundary fill over the
+// sources of neighbouring keys, as k_in_csr does for the destinations); the
+// table's edge count is its key count.
+__global__ __launch_bounds__(256) void k_multi_offsets(TileLaunch t, const uint64_t *in,
+                                                       int64_t *seg_count) {
+  constexpr int U = 4;  // keys per thread in flight
+  const int lane = threadIdx.x & 63;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const __attribute__((address_space(1))) uint64_t *K = G(in) + range_start(P, t.range_kind);
+    const int64_t count = range_count(P, t.range_kind);
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
+    const int64_t end = std::min<int64_t>(base + SCAN_TILE, count);
+    const int64_t last = P.V - 1;
+    const int b = P.b;
+    for (int64_t j0 = base + threadIdx.x; j0 < end; j0 += U * 256) {
+      uint64_t k[U], kp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = std::min<int64_t>(j0 + u * 256, end - 1);
+        k[u] = K[j];
+        kp[u] = (lane == 0 && j > 0) ? K[j - 1] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t below = __shfl_up(k[u], 1, 64);
+        if (lane != 0) kp[u] = below;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + u * 256;
+        if (j < end) {
+          const int64_t h = std::min<int64_t>((int64_t)(k[u] >> b), last);
+          const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(kp[u] >> b), last);
+          for (int64_t v = hp + 1; v <= h; ++v) G(P.out_off)[v] = j;
+          if (j == count - 1) {
+            for (int64_t v = h + 1; v <= P.V; ++v) G(P.out_off)[v] = count;
+            seg_count[seg] = count;
+          }
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_multi_offsets(const TileLaunch &t, const uint64_t *in, int64_t *seg_count,
+                                int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_multi_offsets, dim3(grid), dim3(256), 0, s, t, in, seg_count);
+  return hipGetLastError();
+}
+
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
                          uint32_t epoch, int keep_all, int grid, hipStream_t s) {

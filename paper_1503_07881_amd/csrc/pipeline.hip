@@ -866,12 +866,19 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     in0.seg_total = c.results + S;
     TRACED(TK_IN_COUNT, N, 8.0 * N,
            launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
+  } else if (multi) {
+    // every row is an edge: offsets only, and the in-sort reads the sorted
+    // keys in place
+    TraceMark m = trace_begin(st);
+    HIP_TRY(launch_multi_offsets(c.tiles(TM_DEDUP, erange), sorted_edges, c.results + S,
+                                 grid_for(c.total(TM_DEDUP), cus * 8), st));
+    dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   } else {
     const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
     HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
-                          c.status, c.counters + ep, ep, multi,
-                          grid_for(c.total(TM_DEDUP), cus * 4), st));
+                          c.status, c.counters + ep, ep, 0, grid_for(c.total(TM_DEDUP), cus * 4),
+                          st));
     dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   }
 
@@ -891,7 +898,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     }
   }
   for (int i = 0; i < S; ++i) sumE += E[i];
-  trace_set_bytes(dedupe_rec, 8.0 * NE + 8.0 * sumE + 8.0 * (sumV + S));
+  trace_set_bytes(dedupe_rec, 8.0 * NE + (multi ? 0.0 : 8.0 * sumE) + 8.0 * (sumV + S));
   c.owner->blocks[1] = dev_alloc(c.hooks, arena2, st);
   if (!c.owner->blocks[1]) return RINGO_ERR_OUT_OF_MEMORY;
   char *a2 = (char *)c.owner->blocks[1];
@@ -927,7 +934,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
            launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ib[(P_in - 1) & 1], nullptr,
                          grid_for(c.total(TM_ICSR), cus * 8), st));
   } else {
-    uint64_t *ibuf[2] = {ukeys, sorted_edges};
+    // the multigraph's first in-pass reads the sorted keys themselves
+    uint64_t *ibuf[2] = {multi ? sorted_edges : ukeys, multi ? ukeys : sorted_edges};
     uint32_t *ivb[2] = {uvals, multi ? vbuf[(P_e + 1) & 1] : nullptr};
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,

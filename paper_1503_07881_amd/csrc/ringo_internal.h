@@ -220,6 +220,10 @@ hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, cons
                              uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
                              const int64_t *esort_tmap, int grid, hipStream_t s);
 
+// Multigraph: out-offsets of the sorted keys (every key its own edge) and
+// each table's edge count (its key count) into seg_count.
+hipError_t launch_multi_offsets(const TileLaunch &t, const uint64_t *in, int64_t *seg_count,
+                                int grid, hipStream_t s);
 // keep_all: every sorted key is its own edge (multigraph), offsets only.
 hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
                          int64_t *seg_count, uint64_t *status, uint32_t *counter,
