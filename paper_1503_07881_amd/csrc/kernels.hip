@@ -437,76 +437,121 @@ hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEnt
 // Adjacent compare of the sorted edge keys, compaction of the first copy of
 // every edge, and out-offsets by boundary fill (out_off[v] = position of
 // the first edge whose source is >= v).
+//
+// Undirected graphs: the sorted keys of both orientations keep the first
+// copy of every key (stream compaction) and give the out-offsets, in three
+// launches: head counts per tile, one scan over the tiles, then the
+// compacted keys and the offsets (each tile recomputes its heads).  Tiles
+// never wait on each other; a single pass with decoupled look-back was
+// slower on this device.
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint64_t *in,
-                                                       uint64_t *out, int64_t *seg_count,
-                                                       uint64_t *status, uint32_t *counter,
-                                                       uint32_t epoch, int keep_all) {
-  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
-  __shared__ uint64_t s_k[TILE];
-  __shared__ uint32_t s_cnt[64];
-  __shared__ int64_t s_tile, s_prefix, s_total;
-  __shared__ int32_t s_seg;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (;;) {
-    if (tid == 0) {
-      const int64_t tt = (int64_t)atomicAdd(counter, 1u);
-      s_tile = tt;
-      s_seg = tt < t.total_tiles ? find_seg(t.tmap, t.num_segs, tt) : 0;
+// Head flags of ITEMS rows of a tile of sorted keys (ballot per row).
+__device__ __forceinline__ void dedupe_heads(const uint64_t *in, int64_t start, int64_t base,
+                                             int cnt, uint64_t *s_k, uint64_t &before,
+                                             uint64_t heads[SCAN_ITEMS]) {
+  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS;
+  const int tid = threadIdx.x;
+  for (int i = 0; i < ITEMS; ++i) {
+    const int idx = i * BLOCK + tid;
+    if (idx < cnt) s_k[idx] = G(in)[start + base + idx];
+  }
+  before = base > 0 ? G(in)[start + base - 1] : 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int idx = i * BLOCK + tid;
+    bool h = false;
+    if (idx < cnt) h = (base + idx == 0) || s_k[idx] != (idx > 0 ? s_k[idx - 1] : before);
+    heads[i] = __ballot(h);
+  }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_count(TileLaunch t, const uint64_t *in,
+                                                             uint32_t *tcnt) {
+  constexpr int WAVES = SCAN_BLOCK / 64;
+  __shared__ uint64_t s_k[SCAN_TILE];
+  __shared__ uint32_t s_w[WAVES];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
+    const int cnt = (int)std::min<int64_t>(SCAN_TILE, range_count(P, t.range_kind) - base);
+    uint64_t before, heads[SCAN_ITEMS];
+    dedupe_heads(in, range_start(P, t.range_kind), base, cnt, s_k, before, heads);
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) c += (uint32_t)__popcll(heads[i]);
+    if (lane == 0) s_w[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < WAVES; ++w) tot += s_w[w];
+      tcnt[tile] = tot;
     }
     __syncthreads();
-    const int64_t tile = s_tile;
-    if (tile >= t.total_tiles) break;
-    const int seg = s_seg;
+  }
+}
+
+// Exclusive scan of the tile counts in place (one block), the grand total
+// after the last tile; 32-bit and wrapping (only differences inside one
+// table are used).
+__global__ __launch_bounds__(1024) void k_dedupe_scan(uint32_t *tcnt, int64_t tiles) {
+  __shared__ uint32_t s_w[16];
+  const int tid = threadIdx.x;
+  const int64_t per = (tiles + 1023) / 1024;
+  const int64_t t0 = std::min<int64_t>(tid * per, tiles), t1 = std::min<int64_t>(t0 + per, tiles);
+  uint32_t sum = 0;
+  for (int64_t t = t0; t < t1; ++t) sum += tcnt[t];
+  uint32_t total;
+  uint32_t run = block_excl_scan<1024>(sum, s_w, total);
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = tcnt[t];
+    tcnt[t] = run;
+    run += v;
+  }
+  if (tid == 0) tcnt[tiles] = total;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const uint64_t *in,
+                                                             uint64_t *out, int64_t *seg_count,
+                                                             const uint32_t *tpre) {
+  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64;
+  __shared__ uint64_t s_k[SCAN_TILE];
+  __shared__ uint32_t s_cnt[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
     const int64_t first = t.tmap[seg];
-    const int64_t base = (tile - first) * (int64_t)TILE;
+    const int64_t base = (tile - first) * (int64_t)SCAN_TILE;
     const int64_t start = range_start(P, t.range_kind);
     const int64_t count = range_count(P, t.range_kind);
-    const int cnt = (int)std::min<int64_t>(TILE, count - base);
+    const int cnt = (int)std::min<int64_t>(SCAN_TILE, count - base);
     const int b = P.b;
-    for (int i = 0; i < ITEMS; ++i) {
-      const int idx = i * BLOCK + tid;
-      if (idx < cnt) s_k[idx] = in[start + base + idx];
-    }
-    const uint64_t before = base > 0 ? in[start + base - 1] : 0;
-    __syncthreads();
-    uint64_t heads[ITEMS];
+    uint64_t before, heads[ITEMS];
+    dedupe_heads(in, start, base, cnt, s_k, before, heads);
+    if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const int idx = i * BLOCK + tid;
-      bool h = false;
-      if (idx < cnt) {
-        const uint64_t k = s_k[idx];
-        h = keep_all || (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
-      }
-      heads[i] = __ballot(h);
-      if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
-    }
+      for (int i = 0; i < ITEMS; ++i) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
     __syncthreads();
     if (wave == 0) {
       const uint32_t v = s_cnt[lane];
       const uint32_t inc = wave_incl_scan(v, lane);
       s_cnt[lane] = inc - v;
-      const uint32_t tot = __shfl(inc, 63, 64);
-      if (lane == 0) {
-        uint64_t ex;
-        if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
-          ex = lb_resolve(status, tile, first, 1, 0, epoch, tot);
-        s_prefix = (int64_t)ex;
-        s_total = (int64_t)ex + tot;
-      }
     }
     __syncthreads();
-    const int64_t prefix = s_prefix;
+    // keys of this table in its earlier tiles, and the table's total
+    const int64_t prefix = (int64_t)(uint32_t)(tpre[tile] - tpre[first]);
     const bool last_tile = base + cnt == count;
+    const int64_t E = (int64_t)(uint32_t)(tpre[t.tmap[seg + 1]] - tpre[first]);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = i * BLOCK + tid;
       if ((heads[i] >> lane) & 1ull) {
         const uint64_t k = s_k[idx];
         const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
-        if (j < count) out[start + j] = k;
+        if (j < count) G(out)[start + j] = k;
         const int64_t hsrc = std::min<int64_t>((int64_t)(k >> b), P.V - 1);
         const int64_t hp =
             (base + idx == 0) ? -1 : (int64_t)((idx > 0 ? s_k[idx - 1] : before) >> b);
@@ -514,14 +559,23 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe(TileLaunch t, const uint6
       }
       if (last_tile && idx == cnt - 1) {
         // the last row of the table closes the offsets
-        const int64_t E = s_total;
         for (int64_t v = std::min<int64_t>((int64_t)(s_k[idx] >> b), P.V - 1) + 1; v <= P.V; ++v)
           G(P.out_off)[v] = E;
       }
     }
-    if (tid == 0 && last_tile) seg_count[seg] = s_total;
+    if (tid == 0 && last_tile) seg_count[seg] = E;
     __syncthreads();
   }
+}
+
+hipError_t launch_dedupe_scan(const TileLaunch &t, const uint64_t *in, uint64_t *out,
+                              int64_t *seg_count, uint32_t *tcnt, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dedupe_count, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, tcnt);
+  hipLaunchKernelGGL(k_dedupe_scan, dim3(1), dim3(1024), 0, s, tcnt, t.total_tiles);
+  hipLaunchKernelGGL(k_dedupe_write, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count,
+                     (const uint32_t *)tcnt);
+  return hipGetLastError();
 }
 
 // Multigraph: every sorted key is its own edge, so an edge's position is its
@@ -575,15 +629,6 @@ hipError_t launch_multi_offsets(const TileLaunch &t, const uint64_t *in, int64_t
                                 int grid, hipStream_t s) {
   if (t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_multi_offsets, dim3(grid), dim3(256), 0, s, t, in, seg_count);
-  return hipGetLastError();
-}
-
-hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
-                         int64_t *seg_count, uint64_t *status, uint32_t *counter,
-                         uint32_t epoch, int keep_all, int grid, hipStream_t s) {
-  if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dedupe, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count,
-                     status, counter, epoch, keep_all);
   return hipGetLastError();
 }
 

@@ -874,11 +874,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                                  grid_for(c.total(TM_DEDUP), cus * 8), st));
     dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   } else {
-    const uint32_t ep = ++c.epoch;
+    // undirected: compaction by per-tile counts and a scan (the digit counts
+    // of the edge sort are free now)
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_dedupe(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
-                          c.status, c.counters + ep, ep, 0, grid_for(c.total(TM_DEDUP), cus * 4),
-                          st));
+    HIP_TRY(launch_dedupe_scan(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
+                               c.counts, grid_for(c.total(TM_DEDUP), cus * 4), st));
     dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   }
 

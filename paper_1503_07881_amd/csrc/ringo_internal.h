@@ -224,10 +224,11 @@ hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, cons
 // each table's edge count (its key count) into seg_count.
 hipError_t launch_multi_offsets(const TileLaunch &t, const uint64_t *in, int64_t *seg_count,
                                 int grid, hipStream_t s);
-// keep_all: every sorted key is its own edge (multigraph), offsets only.
-hipError_t launch_dedupe(const TileLaunch &t, const uint64_t *in, uint64_t *out,
-                         int64_t *seg_count, uint64_t *status, uint32_t *counter,
-                         uint32_t epoch, int keep_all, int grid, hipStream_t s);
+// Undirected graphs: first copy of every sorted key (compaction into out)
+// and the out-offsets, by per-tile head counts and a scan (tcnt:
+// total_tiles + 1 words of workspace).
+hipError_t launch_dedupe_scan(const TileLaunch &t, const uint64_t *in, uint64_t *out,
+                              int64_t *seg_count, uint32_t *tcnt, int grid, hipStream_t s);
 // vals (multigraph): the row of every (d, s)-sorted edge, copied to in_eid.
 hipError_t launch_in_csr(const TileLaunch &t, const uint64_t *in, const uint32_t *vals, int grid,
                          hipStream_t s);
