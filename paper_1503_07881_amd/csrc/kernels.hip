@@ -445,31 +445,34 @@ hipError_t launch_remap(const TileLaunch &t, const uint64_t *nodes, const DirEnt
 // never wait on each other; a single pass with decoupled look-back was
 // slower on this device.
 
-// Head flags of ITEMS rows of a tile of sorted keys (ballot per row).
+// Keys of ITEMS rows of a tile (row i = keys i * BLOCK + tid, coalesced),
+// each key's predecessor (from the lane below; lane 0 loads its own), and
+// the ballot of the heads (first copies) of every row.
 __device__ __forceinline__ void dedupe_heads(const uint64_t *in, int64_t start, int64_t base,
-                                             int cnt, uint64_t *s_k, uint64_t &before,
+                                             int cnt, uint64_t k[SCAN_ITEMS],
+                                             uint64_t kp[SCAN_ITEMS],
                                              uint64_t heads[SCAN_ITEMS]) {
   constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS;
-  const int tid = threadIdx.x;
-  for (int i = 0; i < ITEMS; ++i) {
-    const int idx = i * BLOCK + tid;
-    if (idx < cnt) s_k[idx] = G(in)[start + base + idx];
-  }
-  before = base > 0 ? G(in)[start + base - 1] : 0;
-  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const __attribute__((address_space(1))) uint64_t *K = G(in) + start;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
+    const int idx = std::min(i * BLOCK + tid, cnt - 1);
+    k[i] = K[base + idx];
+    kp[i] = (lane == 0 && base + idx > 0) ? K[base + idx - 1] : 0ull;
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint64_t below = __shfl_up(k[i], 1, 64);
+    if (lane != 0) kp[i] = below;
     const int idx = i * BLOCK + tid;
-    bool h = false;
-    if (idx < cnt) h = (base + idx == 0) || s_k[idx] != (idx > 0 ? s_k[idx - 1] : before);
-    heads[i] = __ballot(h);
+    heads[i] = __ballot(idx < cnt && (base + idx == 0 || k[i] != kp[i]));
   }
 }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_count(TileLaunch t, const uint64_t *in,
                                                              uint32_t *tcnt) {
   constexpr int WAVES = SCAN_BLOCK / 64;
-  __shared__ uint64_t s_k[SCAN_TILE];
   __shared__ uint32_t s_w[WAVES];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
@@ -477,8 +480,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_count(TileLaunch t, const
     const SegPlan P = t.plan[seg];
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
     const int cnt = (int)std::min<int64_t>(SCAN_TILE, range_count(P, t.range_kind) - base);
-    uint64_t before, heads[SCAN_ITEMS];
-    dedupe_heads(in, range_start(P, t.range_kind), base, cnt, s_k, before, heads);
+    uint64_t k[SCAN_ITEMS], kp[SCAN_ITEMS], heads[SCAN_ITEMS];
+    dedupe_heads(in, range_start(P, t.range_kind), base, cnt, k, kp, heads);
     uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) c += (uint32_t)__popcll(heads[i]);
@@ -517,7 +520,6 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const
                                                              uint64_t *out, int64_t *seg_count,
                                                              const uint32_t *tpre) {
   constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64;
-  __shared__ uint64_t s_k[SCAN_TILE];
   __shared__ uint32_t s_cnt[64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
@@ -529,8 +531,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const
     const int64_t count = range_count(P, t.range_kind);
     const int cnt = (int)std::min<int64_t>(SCAN_TILE, count - base);
     const int b = P.b;
-    uint64_t before, heads[ITEMS];
-    dedupe_heads(in, start, base, cnt, s_k, before, heads);
+    uint64_t k[ITEMS], kp[ITEMS], heads[ITEMS];
+    dedupe_heads(in, start, base, cnt, k, kp, heads);
     if (lane == 0)
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
@@ -549,17 +551,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = i * BLOCK + tid;
       if ((heads[i] >> lane) & 1ull) {
-        const uint64_t k = s_k[idx];
         const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
-        if (j < count) G(out)[start + j] = k;
-        const int64_t hsrc = std::min<int64_t>((int64_t)(k >> b), P.V - 1);
-        const int64_t hp =
-            (base + idx == 0) ? -1 : (int64_t)((idx > 0 ? s_k[idx - 1] : before) >> b);
+        if (j < count) G(out)[start + j] = k[i];
+        const int64_t hsrc = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1);
+        const int64_t hp = (base + idx == 0) ? -1 : (int64_t)(kp[i] >> b);
         for (int64_t v = hp + 1; v <= hsrc; ++v) G(P.out_off)[v] = j;
       }
       if (last_tile && idx == cnt - 1) {
         // the last row of the table closes the offsets
-        for (int64_t v = std::min<int64_t>((int64_t)(s_k[idx] >> b), P.V - 1) + 1; v <= P.V; ++v)
+        for (int64_t v = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1) + 1; v <= P.V; ++v)
           G(P.out_off)[v] = E;
       }
     }
