@@ -28,100 +28,14 @@
 // digits of every tile, a scan over tiles turns the counts into per-tile
 // digit offsets, and a downsweep ranks every key stably inside its tile with
 // 64-lane wavefront ballots and writes each digit run of the tile as one
-// contiguous LDS-staged store.  Stream compaction (unique, dedupe) uses a
-// single pass with decoupled look-back (Merrill & Garland 2016).
+// contiguous LDS-staged store.  Stream compaction (unique, dedupe) counts
+// the heads of every tile, scans the counts, then writes; no block waits on
+// another.
 
 #include "device_common.h"
 #include "ringo_internal.h"
 
 namespace ringo {
-
-// ----------------------------------------------------- decoupled look-back
-//
-// Status word of (tile, digit): [63:56] launch epoch, [55:54] flag
-// (1 = tile aggregate, 2 = inclusive prefix), [53:0] value.  A word whose
-// epoch differs from the current launch's is "not yet published", so the
-// buffer is cleared once per call rather than once per pass.
-
-constexpr uint64_t ST_AGG = 1, ST_INC = 2;
-constexpr uint64_t ST_VMASK = (1ull << 54) - 1;
-
-__device__ __forceinline__ uint64_t st_pack(uint32_t epoch, uint64_t flag, uint64_t v) {
-  return ((uint64_t)epoch << 56) | (flag << 54) | v;
-}
-__device__ __forceinline__ void st_store(uint64_t *p, uint64_t w) {
-  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-#ifndef RINGO_SPIN_SLEEP
-#define RINGO_SPIN_SLEEP 1
-#endif
-__device__ __forceinline__ uint64_t st_wait(const uint64_t *p, uint32_t epoch) {
-  uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  while ((uint32_t)(w >> 56) != epoch) {
-    __builtin_amdgcn_s_sleep(RINGO_SPIN_SLEEP);
-    w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return w;
-}
-
-// First half of the look-back: publish this tile's aggregate, or its
-// inclusive prefix straight away when it opens its table or when the
-// predecessor's inclusive prefix is already visible.  Returns true with
-// *excl set when the prefix is resolved.
-__device__ __forceinline__ bool lb_publish(uint64_t *status, int64_t tile, int64_t first,
-                                           int stride, int d, uint32_t epoch, uint64_t total,
-                                           uint64_t *excl) {
-  uint64_t *own = status + tile * stride + d;
-  if (tile == first) {
-    st_store(own, st_pack(epoch, ST_INC, total));
-    *excl = 0;
-    return true;
-  }
-  const uint64_t w = __hip_atomic_load(status + (tile - 1) * stride + d, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  if ((uint32_t)(w >> 56) == epoch && ((w >> 54) & 3) == ST_INC) {
-    *excl = w & ST_VMASK;
-    st_store(own, st_pack(epoch, ST_INC, *excl + total));
-    return true;
-  }
-  st_store(own, st_pack(epoch, ST_AGG, total));
-  return false;
-}
-
-// Second half: walk back over predecessors until an inclusive prefix is
-// found (the first tile of a table always publishes one), then publish ours.
-// The status words of LB_WINDOW predecessors are requested together, so a
-// walk over k published aggregates costs k / LB_WINDOW dependent round trips.
-#ifndef RINGO_LB_WINDOW
-#define RINGO_LB_WINDOW 8
-#endif
-constexpr int LB_WINDOW = RINGO_LB_WINDOW;
-
-__device__ __forceinline__ uint64_t lb_resolve(uint64_t *status, int64_t tile, int64_t first,
-                                               int stride, int d, uint32_t epoch, uint64_t total) {
-  uint64_t acc = 0;
-  bool done = false;
-  for (int64_t p = tile - 1; !done; p -= LB_WINDOW) {
-    uint64_t w[LB_WINDOW];
-#pragma unroll
-    for (int k = 0; k < LB_WINDOW; ++k)
-      w[k] = p - k >= first ? __hip_atomic_load(status + (p - k) * stride + d, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
-                            : 0;
-#pragma unroll
-    for (int k = 0; k < LB_WINDOW; ++k) {
-      if (done) break;
-      uint64_t x = w[k];
-      // the walk ends at the table's first tile at the latest, which always
-      // publishes an inclusive prefix, so p - k >= first here
-      if ((uint32_t)(x >> 56) != epoch) x = st_wait(status + (p - k) * stride + d, epoch);
-      acc += x & ST_VMASK;
-      done = ((x >> 54) & 3) == ST_INC;
-    }
-  }
-  st_store(status + tile * stride + d, st_pack(epoch, ST_INC, acc + total));
-  return acc;
-}
 
 // ------------------------------------------------------------------ fills
 
@@ -185,98 +99,8 @@ hipError_t launch_sort_part(const SortLaunch &a, int mode, int items, int digit_
 // ------------------------------------------------------ unique (node set)
 //
 // Head flags on the sorted node keys, stream compaction of the heads into
-// the node list, per-table node count.  A tile is processed as ITEMS rows
-// of BLOCK keys; the head count of each (row, wave) pair is a ballot, and
-// the pairs are scanned in index order by one wave.
-
-template <int BLOCK, int ITEMS>
-struct CompactTile {
-  static constexpr int WAVES = BLOCK / 64;
-  static constexpr int TILE = BLOCK * ITEMS;
-  static_assert(ITEMS * WAVES <= 64, "one wave scans the row counts");
-};
-
-__global__ __launch_bounds__(SCAN_BLOCK) void k_unique(TileLaunch t, const uint64_t *in,
-                                                       uint64_t *out, int64_t *seg_count,
-                                                       uint64_t *status, uint32_t *counter,
-                                                       uint32_t epoch) {
-  constexpr int BLOCK = SCAN_BLOCK, ITEMS = SCAN_ITEMS, WAVES = BLOCK / 64, TILE = SCAN_TILE;
-  __shared__ uint64_t s_k[TILE];
-  __shared__ uint32_t s_cnt[64];
-  __shared__ int64_t s_tile, s_prefix, s_total;
-  __shared__ int32_t s_seg;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (;;) {
-    if (tid == 0) {
-      const int64_t tt = (int64_t)atomicAdd(counter, 1u);
-      s_tile = tt;
-      s_seg = tt < t.total_tiles ? find_seg(t.tmap, t.num_segs, tt) : 0;
-    }
-    __syncthreads();
-    const int64_t tile = s_tile;
-    if (tile >= t.total_tiles) break;
-    const int seg = s_seg;
-    const SegPlan P = t.plan[seg];
-    const int64_t first = t.tmap[seg];
-    const int64_t base = (tile - first) * (int64_t)TILE;
-    const int64_t start = range_start(P, t.range_kind);
-    const int64_t count = range_count(P, t.range_kind);
-    const int cnt = (int)std::min<int64_t>(TILE, count - base);
-    for (int i = 0; i < ITEMS; ++i) {
-      const int idx = i * BLOCK + tid;
-      if (idx < cnt) s_k[idx] = in[start + base + idx];
-    }
-    const uint64_t before = base > 0 ? in[start + base - 1] : 0;
-    __syncthreads();
-    uint64_t heads[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const int idx = i * BLOCK + tid;
-      bool h = false;
-      if (idx < cnt) {
-        const uint64_t k = s_k[idx];
-        h = (base + idx == 0) || k != (idx > 0 ? s_k[idx - 1] : before);
-      }
-      heads[i] = __ballot(h);
-      if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(heads[i]);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const uint32_t v = s_cnt[lane];
-      const uint32_t inc = wave_incl_scan(v, lane);
-      s_cnt[lane] = inc - v;
-      const uint32_t tot = __shfl(inc, 63, 64);
-      if (lane == 0) {
-        uint64_t ex;
-        if (!lb_publish(status, tile, first, 1, 0, epoch, tot, &ex))
-          ex = lb_resolve(status, tile, first, 1, 0, epoch, tot);
-        s_prefix = (int64_t)ex;
-        s_total = (int64_t)ex + tot;
-      }
-    }
-    __syncthreads();
-    const int64_t prefix = s_prefix;
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-      const int idx = i * BLOCK + tid;
-      if ((heads[i] >> lane) & 1ull) {
-        const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
-        if (j < count) out[start + j] = s_k[idx];
-      }
-    }
-    if (tid == 0 && base + cnt == count) seg_count[seg] = s_total;
-    __syncthreads();
-  }
-}
-
-hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
-                         uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
-                         hipStream_t s) {
-  if (t.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unique, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count, status,
-                     counter, epoch);
-  return hipGetLastError();
-}
+// the node list, per-table node count: launch_unique, with the compaction
+// kernels of the dedupe section below.
 
 // ------------------------------------------------------- node directory
 //
@@ -516,6 +340,9 @@ __global__ __launch_bounds__(1024) void k_dedupe_scan(uint32_t *tcnt, int64_t ti
   if (tid == 0) tcnt[tiles] = total;
 }
 
+// OFFSETS: also the out-offsets by boundary fill (edge keys); without, the
+// compaction alone (the distinct node keys).
+template <bool OFFSETS>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const uint64_t *in,
                                                              uint64_t *out, int64_t *seg_count,
                                                              const uint32_t *tpre) {
@@ -553,11 +380,13 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const
       if ((heads[i] >> lane) & 1ull) {
         const int64_t j = prefix + s_cnt[i * WAVES + wave] + lanes_below(heads[i]);
         if (j < count) G(out)[start + j] = k[i];
-        const int64_t hsrc = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1);
-        const int64_t hp = (base + idx == 0) ? -1 : (int64_t)(kp[i] >> b);
-        for (int64_t v = hp + 1; v <= hsrc; ++v) G(P.out_off)[v] = j;
+        if (OFFSETS) {
+          const int64_t hsrc = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1);
+          const int64_t hp = (base + idx == 0) ? -1 : (int64_t)(kp[i] >> b);
+          for (int64_t v = hp + 1; v <= hsrc; ++v) G(P.out_off)[v] = j;
+        }
       }
-      if (last_tile && idx == cnt - 1) {
+      if (OFFSETS && last_tile && idx == cnt - 1) {
         // the last row of the table closes the offsets
         for (int64_t v = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1) + 1; v <= P.V; ++v)
           G(P.out_off)[v] = E;
@@ -573,8 +402,20 @@ hipError_t launch_dedupe_scan(const TileLaunch &t, const uint64_t *in, uint64_t 
   if (t.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_dedupe_count, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, tcnt);
   hipLaunchKernelGGL(k_dedupe_scan, dim3(1), dim3(1024), 0, s, tcnt, t.total_tiles);
-  hipLaunchKernelGGL(k_dedupe_write, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out, seg_count,
-                     (const uint32_t *)tcnt);
+  hipLaunchKernelGGL(k_dedupe_write<true>, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out,
+                     seg_count, (const uint32_t *)tcnt);
+  return hipGetLastError();
+}
+
+// Unique node keys: the same compaction of the sorted node keys, without
+// offsets; each table's count is its V.
+hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
+                         uint32_t *tcnt, int grid, hipStream_t s) {
+  if (t.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dedupe_count, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, tcnt);
+  hipLaunchKernelGGL(k_dedupe_scan, dim3(1), dim3(1024), 0, s, tcnt, t.total_tiles);
+  hipLaunchKernelGGL(k_dedupe_write<false>, dim3(grid), dim3(SCAN_BLOCK), 0, s, t, in, out,
+                     seg_count, (const uint32_t *)tcnt);
   return hipGetLastError();
 }
 

@@ -227,9 +227,7 @@ struct Call {
 
   // device workspace
   uint64_t *A = nullptr, *B = nullptr;
-  uint64_t *status = nullptr;
   int64_t *base = nullptr;
-  uint32_t *counters = nullptr;
   int64_t *results = nullptr;
   uint8_t *meta = nullptr;
   DirEntry *dir = nullptr;
@@ -249,13 +247,12 @@ struct Call {
   size_t meta_bytes = 0;
   Pinned *pin = nullptr;
   int upload_slot = 0;
-  uint32_t epoch = 0;
   Owner *owner = nullptr;
 
   ~Call() { release_workspace(); }
 
   void release_workspace() {
-    void *bufs[] = {A, B, status, base, counters, results, meta, dir, tab, hslots, hmeta, counts,
+    void *bufs[] = {A, B, base, results, meta, dir, tab, hslots, hmeta, counts,
                     bsum, vals, small_ws, small_arena};
     for (void *b : bufs) dev_free(hooks, b, stream);
     small_ws = nullptr;
@@ -267,9 +264,7 @@ struct Call {
     vals = nullptr;
     hmeta = nullptr;
     A = B = nullptr;
-    status = nullptr;
     base = nullptr;
-    counters = nullptr;
     results = nullptr;
     meta = nullptr;
     dir = nullptr;
@@ -600,7 +595,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.set_tiles(TM_HLL, RANGE_ROWS, HLL_TILE);
   c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
 
-  const int64_t status_words = c.total(TM_UNIQ) + 256;  // one word per unique/dedupe tile
   // the node pass has the most tiles: 2n keys per table
   const int64_t max_tiles = c.total(TM_NSORT) + 1;
   const int64_t max_runs = sort_runs_bound(max_tiles);
@@ -611,20 +605,16 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   const size_t base_words = (size_t)S * R;
   c.A = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
   c.B = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * N, st);
-  c.status = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * status_words, st);
   c.base = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * base_words, st);
-  c.counters = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 256, st);
   c.results = (int64_t *)dev_alloc(c.hooks, sizeof(int64_t) * (2 * S + 1), st);
   c.meta = (uint8_t *)dev_alloc(c.hooks, c.meta_bytes, st);
   c.counts = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * max_tiles, st);
   c.bsum = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * R * max_runs, st);
-  if (!c.A || !c.B || !c.status || !c.base || !c.counters || !c.results || !c.meta ||
+  if (!c.A || !c.B || !c.base || !c.results || !c.meta ||
       !c.counts || !c.bsum)
     return RINGO_ERR_OUT_OF_MEMORY;
 
   HIP_TRY(c.upload());
-  HIP_TRY(launch_fill_u64(c.status, 0, status_words, st));
-  HIP_TRY(launch_fill_u64((uint64_t *)c.counters, 0, 128, st));
   HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
 
   // ------------------------------------------------------------- phase N
@@ -719,10 +709,9 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                   a);
     }
     // the sorted keys are in B; the distinct keys go to A
-    const uint32_t ep = ++c.epoch;
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.status,
-                          c.counters + ep, ep, grid_for(c.total(TM_UNIQ), cus * 4), st));
+    HIP_TRY(launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.counts,
+                          grid_for(c.total(TM_UNIQ), cus * 4), st));
     unique_rec = trace_end(m, TK_UNIQUE, 2 * N, 16.0 * N, st);
     HIP_TRY(c.readback(0, V));  // sync #1
   }

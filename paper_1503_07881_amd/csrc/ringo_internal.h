@@ -149,9 +149,10 @@ inline int run_tiles_for(int64_t tiles) {
 int sort_tile(int items);
 int64_t sort_runs(int64_t tiles);
 int64_t sort_runs_bound(int64_t max_tiles);  // >= sort_runs(t) for every t <= max_tiles
+// Distinct sorted node keys of every table into out, their count into
+// seg_count (tcnt: total_tiles + 1 words of workspace).
 hipError_t launch_unique(const TileLaunch &t, const uint64_t *in, uint64_t *out, int64_t *seg_count,
-                         uint64_t *status, uint32_t *counter, uint32_t epoch, int grid,
-                         hipStream_t s);
+                         uint32_t *tcnt, int grid, hipStream_t s);
 // Node directory entry: the bucket's first key and its position range.
 struct alignas(16) DirEntry {
   uint64_t key;
