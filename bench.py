@@ -34,7 +34,7 @@ ROCPROF_NAME = {
     "hash_estimate": "k_hll", "hash_insert": "k_hash_insert", "hash_compact": "k_hash_compact",
     "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
     "unique": "k_dedupe_write<false>",
-    "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe_write", "in_csr": "k_in_csr",
+    "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe_write<true>", "in_csr": "k_in_csr",
     "sort_node_scatter": "k_downsweep<256, {items}, 1|3, {bits}>",
     "sort_vnode_scatter": "k_downsweep<256, {items}, 4, {bits}>",
     "sort_edge_scatter": "k_downsweep<256, {items}, 5, {bits}>",
