@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the table-to-graph conversion (Section 2.4) on one MI355X.
 
-A step is one full conversion of the 2^26-row R-MAT scale-22 edge table
-(the LiveJournal-shaped stand-in): node-key sort, unique, remap, edge-key
-sort, dedupe, out-CSR, in-key sort, in-CSR, output allocation and both
-size read-backs.  The input columns are generated on the device and are
-resident in HBM before the timed region starts.
+A step is one full conversion of the 1.5e9-row R-MAT scale-26 edge table
+(the Twitter2010-shaped stand-in of Table 2, the largest single-GPU
+workload): node numbering, edge-key sort, dedupe, out-CSR, in-key sort,
+in-CSR, output allocation and the size read-backs.  The input columns are
+generated on the device and are resident in HBM before the timed region
+starts.
 
 Prints one JSON line: edges/s (input rows per second, the paper's "Edges/s"
 of Table 5), the roofline position of the dominant kernel measured with HIP
-events on the conversion's stream inside the timed region, and the CPU
-oracle timed on a bounded sample of the same workload.
+events on the conversion's stream inside the timed region, the whole
+conversion's algorithmic-byte and counter-traffic fractions of HBM peak, the
+CPU oracle timed on a bounded prefix of the same workload, and as extra keys
+the 2^26-row (LiveJournal-shaped) workload, the batched speedup over 4096
+tables, and the oracle's time on the whole 2^26-row table.
+
+--config 1|2 time the 1e6-row or 2^26-row workload instead; --config 4 the
+batched form alone; --config 5 the served form (p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -140,26 +147,27 @@ def host_info() -> dict:
     return info
 
 
-def cpu_baseline(rows: int):
+def cpu_baseline(spec, rows: int):
+    """The oracle as it stands, on the first `rows` rows of the benchmarked
+    workload (generated on the host with the same seeded generator)."""
     import numpy as np  # noqa: F401
     import oracle
     from paper_1503_07881_amd import workloads
-    spec = workloads.config2()
-    sample = workloads.TableSpec("rmat", rows, seed=spec.seed, scale=spec.scale)
+    sample = workloads.TableSpec(spec.kind, min(rows, spec.n), seed=spec.seed, scale=spec.scale)
     src, dst = workloads.generate_host(sample)
     t0 = time.perf_counter()
     oracle.table_to_graph(src, dst)
     dt = time.perf_counter() - t0
-    what = (f"first {rows:,} rows of the R-MAT scale-22 workload (rows are i.i.d., so a prefix "
+    what = (f"first {sample.n:,} rows of the {_workload_name(spec)} workload (rows are i.i.d., so a prefix "
             f"is a sample of the same distribution)")
-    single = {"value": rows / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+    single = {"value": sample.n / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
               "sample": f"{what}; single-threaded std::sort oracle, {dt:.2f} s"}
     # the same oracle with its sorts on every host thread (the rest of its
     # steps stay serial)
     t0 = time.perf_counter()
     oracle.table_to_graph(src, dst, all_cores=True)
     dp = time.perf_counter() - t0
-    par = {"value": rows / dp, "unit": "edges/s", "cores": oracle.last_threads, "kind": "oracle",
+    par = {"value": sample.n / dp, "unit": "edges/s", "cores": oracle.last_threads, "kind": "oracle",
            "sample": f"{what}; the oracle with a parallel sort (libstdc++ parallel mode) on "
                      f"{oracle.last_threads} threads, {dp:.2f} s"}
     single["host"] = par["host"] = host_info()
@@ -418,20 +426,233 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_bandwidth(dev, sh):
+    """Achievable-bandwidth reference: a plain 16-byte copy of 2 GiB (five
+    launches timed with events on the stream they run on)."""
+    import torch
+    from paper_1503_07881_amd import workloads
+    cbytes = 1 << 31
+    ca = torch.empty(cbytes // 8, dtype=torch.int64, device=dev)
+    cb = torch.empty_like(ca)
+    for _ in range(2):
+        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
+    e1.record()
+    torch.cuda.synchronize()
+    del ca, cb
+    return 2 * cbytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
+def measure_conversion(spec, args, kind, copy_gbps, steps, warmup):
+    """Times `steps` conversions of `spec` (generated on the device, resident
+    before the timed region): untraced, per step, and traced with the
+    library's HIP events on the conversion's stream. Returns the pieces of
+    the benchmark line."""
+    import torch
+    from paper_1503_07881_amd import ringo
+    dev = torch.device("cuda:0")
+    n = spec.n
+    log(f"bench: generating {spec.kind} n={n:,} on the device")
+    src, dst = _device_table(spec, dev)
+    torch.cuda.synchronize()
+    sh = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        g = ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh, kind)
+        V, E = g.num_nodes, g.num_edges
+        ringo.graph_free(g)
+        return V, E
+
+    V = E = 0
+    for i in range(warmup):
+        V, E = step()
+        log(f"bench: warmup {i + 1}/{warmup} V={V:,} E={E:,}")
+    torch.cuda.synchronize()
+    # untraced: K steps back to back, then each step alone (median)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms_untraced = (time.perf_counter() - t0) * 1e3 / steps
+    per = []
+    for _ in range(min(steps, 5)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t1) * 1e3)
+    log(f"bench: untraced {ms_untraced:.3f} ms/step (median of {len(per)} single steps "
+        f"{sorted(per)[len(per) // 2]:.3f})")
+    # timed region, with per-kernel HIP events on the conversion's stream
+    ringo.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        V, E = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    trace = ringo.trace_read()
+    ringo.trace_enable(False)
+    log(f"bench: timed {steps} steps: {ms:.3f} ms/step")
+    del src, dst
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    kernels = {}
+    for name, t in trace.items():
+        avg_ms = t["ms"] / t["launches"]
+        bpl = t["bytes"] / t["launches"]
+        kernels[name] = {"launches_per_step": t["launches"] // steps,
+                         "ms_per_step": round(t["ms"] / steps, 4),
+                         "avg_launch_ms": round(avg_ms, 5),
+                         "GBps": round(bpl / (avg_ms / 1e3) / 1e9, 1)}
+    # the dominant kernel: most time per step among entries that are one kernel
+    dom = max((k for k in trace if not k.endswith("_count")), key=lambda k: trace[k]["ms"])
+    t = trace[dom]
+    avg_s = t["ms"] / t["launches"] / 1e3
+    bytes_per_launch = t["bytes"] / t["launches"]
+    achieved = bytes_per_launch / avg_s / 1e9
+    workload = _workload_name(spec)
+    traffic = read_traffic(dom, workload)
+    bits, items, method = ringo.tune_get(n)
+    # the library's byte model of one whole conversion (every kernel's
+    # algorithmic bytes, summed), over the untraced step time
+    alg_bytes = sum(t2["bytes"] for t2 in trace.values()) / steps
+    conv_bytes = read_conversion_traffic(workload) if kind == ringo.GRAPH_DIRECTED else None
+    io_min = 16 * n + 24 * V + 8 + 8 * E
+    sec = ms_untraced / 1e3
+    return {
+        "value": n / (ms / 1e3), "ms_per_step": ms, "ms_per_step_untraced": ms_untraced,
+        "ms_single_step_median": sorted(per)[len(per) // 2],
+        "workload": workload, "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
+        "digit_bits": bits, "items_per_thread": items,
+        "node_method": "hash" if method == ringo.NODES_HASH else "sort",
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items, bits=bits),
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     # the counter-measured bytes over the same launch time (line-granular
+                     # traffic of random accesses included: raw traffic, not useful bytes)
+                     "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBPS, 4) if traffic else None,
+                     "traffic_over_algorithmic": round(traffic / bytes_per_launch, 2) if traffic else None,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": round(avg_s * 1e3, 5)},
+        # every kernel's algorithmic bytes (the library's byte model) over the
+        # untraced conversion time: the useful-bandwidth fraction of the
+        # whole conversion
+        "conversion_alg": {"bytes": alg_bytes, "GBps": round(alg_bytes / sec / 1e9, 1),
+                           "frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBPS, 4)},
+        # every kernel's counter-measured HBM bytes (FETCH_SIZE + WRITE_SIZE,
+        # scaled) over the same time: raw traffic, wasted lines of the random
+        # probes and gathers included
+        "conversion_traffic": ({"bytes": conv_bytes, "GBps": round(conv_bytes / sec / 1e9, 1),
+                                "frac": round(conv_bytes / sec / 1e9 / HBM_PEAK_GBPS, 4),
+                                "frac_of_copy": round(conv_bytes / sec / 1e9 / copy_gbps, 4)}
+                               if conv_bytes else None),
+        # reading the table once and writing the graph once: 16n + 24V + 8 + 8E bytes
+        "io_minimum": {"bytes": io_min, "GBps": round(io_min / sec / 1e9, 1),
+                       "frac": round(io_min / sec / 1e9 / HBM_PEAK_GBPS, 4)},
+        "kernels": kernels,
+    }
+
+
+def batched_extra(steps):
+    """The batched workload's speedup for the headline line (fewer repetitions
+    than --config 4): median batched call, median of one call per table,
+    tables whose outputs differ."""
+    import torch
+    from paper_1503_07881_amd import ringo, workloads
+    dev = torch.device("cuda:0")
+    specs = workloads.config4()
+    total = sum(s.n for s in specs)
+    src = torch.empty(total, dtype=torch.int64, device=dev)
+    dst = torch.empty(total, dtype=torch.int64, device=dev)
+    sh = torch.cuda.current_stream().cuda_stream
+    offs, off = [], 0
+    for s in specs:
+        workloads.generate_device(s, src.data_ptr() + 8 * off, dst.data_ptr() + 8 * off, sh)
+        offs.append((off, s.n))
+        off += s.n
+    torch.cuda.synchronize()
+    sp = [src.data_ptr() + 8 * o for o, _ in offs]
+    dp = [dst.data_ptr() + 8 * o for o, _ in offs]
+    ns = [n for _, n in offs]
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gs = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            for g in gs:
+                ringo.graph_free(g)
+        return sorted(ts)[len(ts) // 2]
+
+    def batched():
+        return ringo.table_to_graph_batched_raw(sp, dp, ns, sh)
+
+    def singles():
+        return [ringo.table_to_graph_raw(a, b, c, sh) for a, b, c in zip(sp, dp, ns)]
+
+    for g in batched():
+        ringo.graph_free(g)
+    t_b = timed(batched, max(3, min(steps, 7)))
+    t_s = timed(singles, 3)
+    gb = [ringo._wrap(r, dev) for r in batched()]
+    differing = 0
+    for i, (a, b, c) in enumerate(zip(sp, dp, ns)):
+        g1 = ringo._wrap(ringo.table_to_graph_raw(a, b, c, sh), dev)
+        for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs"):
+            if not torch.equal(getattr(gb[i], f), getattr(g1, f)):
+                differing += 1
+                break
+    del gb, src, dst
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"bench: batched {t_b * 1e3:.1f} ms, one call per table {t_s * 1e3:.1f} ms, differing {differing}")
+    return {"workload": "batch_4096_tables_rows_1e3_to_2e6", "tables": len(specs), "rows": total,
+            "speedup": t_s / t_b, "batched_ms": t_b * 1e3, "single_calls_ms": t_s * 1e3,
+            "batched_edges_per_s": total / t_b, "single_calls_edges_per_s": total / t_s,
+            "tables_differing": differing}
+
+
+def cpu_oracle_full(spec):
+    """The oracle (single-threaded, as it stands) over a whole table."""
+    import oracle
+    from paper_1503_07881_amd import workloads
+    src, dst = workloads.generate_host(spec)
+    t0 = time.perf_counter()
+    oracle.table_to_graph(src, dst)
+    dt = time.perf_counter() - t0
+    return {"value": spec.n / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"the whole {_workload_name(spec)} table ({spec.n:,} rows), single-threaded std::sort oracle"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--config", type=int, default=3, choices=(1, 2, 3, 4, 5),
+                    help="3 (default): the 1.5e9-row R-MAT headline, with the 2^26-row workload and the "
+                         "batched speedup as extra keys")
     ap.add_argument("--serve-pool", type=int, default=128)
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-streams", type=int, default=3)
     ap.add_argument("--serve-batch-rows", type=int, default=8 << 20,
                     help="rows a batch may hold (a larger request runs alone)")
+    ap.add_argument("--serve-budget-gib", type=float, default=200.0)
     ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: skip the 2^26-row and batched extra keys")
     ap.add_argument("--kind", default="directed", choices=("directed", "undirected", "multi"),
                     help="graph kind of the table-to-graph conversion")
     ap.add_argument("--node-method", default="auto", choices=("auto", "sort", "hash"),
@@ -467,140 +688,49 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    spec = {1: workloads.config1, 2: workloads.config2, 3: workloads.config3}[args.config]()
-    n = spec.n
-    log(f"bench: generating {spec.kind} n={n:,} on the device")
-    src = torch.empty(n, dtype=torch.int64, device=dev)
-    dst = torch.empty(n, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
-    if spec.kind == "rmat" or (spec.ndup == 0 and not spec.shuffle):
-        workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
-    else:
-        hs, hd = workloads.generate_host(spec)
-        src.copy_(torch.from_numpy(hs))
-        dst.copy_(torch.from_numpy(hd))
-    torch.cuda.synchronize()
-
-    # achievable-bandwidth reference: a plain 16-byte copy of 2 GiB
-    cbytes = 1 << 31
-    ca = torch.empty(cbytes // 8, dtype=torch.int64, device=dev)
-    cb = torch.empty_like(ca)
-    for _ in range(2):
-        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        workloads.copy_device(cb.data_ptr(), ca.data_ptr(), cbytes, sh)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 2 * cbytes * 5 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del ca, cb
+    sh = torch.cuda.current_stream().cuda_stream
+    copy_gbps = copy_bandwidth(dev, sh)
     log(f"bench: copy kernel {copy_gbps:.0f} GB/s")
-
     kind = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
             "multi": ringo.GRAPH_MULTI}[args.kind]
-
-    def step():
-        g = ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh, kind)
-        V, E = g.num_nodes, g.num_edges
-        ringo.graph_free(g)
-        return V, E
-
-    for i in range(args.warmup):
-        V, E = step()
-        log(f"bench: warmup {i + 1}/{args.warmup} V={V:,} E={E:,}")
-    torch.cuda.synchronize()
-
-    # untraced timing (reported beside the traced one to show the overhead)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    ms_untraced = (time.perf_counter() - t0) * 1e3 / args.steps
-    log(f"bench: untraced {ms_untraced:.3f} ms/step")
-
-    # timed region, with per-kernel HIP events on the conversion's stream
-    ringo.trace_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        V, E = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    trace = ringo.trace_read()
-    ringo.trace_enable(False)
-    log(f"bench: timed {args.steps} steps: {ms:.3f} ms/step")
-
-    kernels = {}
-    for name, t in trace.items():
-        avg_ms = t["ms"] / t["launches"]
-        bpl = t["bytes"] / t["launches"]
-        kernels[name] = {"launches_per_step": t["launches"] // args.steps,
-                         "ms_per_step": round(t["ms"] / args.steps, 4),
-                         "avg_launch_ms": round(avg_ms, 5),
-                         "GBps": round(bpl / (avg_ms / 1e3) / 1e9, 1)}
-    # the dominant kernel: most time per step among entries that are one kernel
-    dom = max((k for k in trace if not k.endswith("_count")), key=lambda k: trace[k]["ms"])
-    t = trace[dom]
-    avg_s = t["ms"] / t["launches"] / 1e3
-    bytes_per_launch = t["bytes"] / t["launches"]
-    achieved = bytes_per_launch / avg_s / 1e9
-    workload = (f"{spec.kind}_scale{spec.scale}_rows{n}" if spec.kind == "rmat"
-                else f"uniform_rows{n}_pool{spec.pool}")
-    traffic = read_traffic(dom, workload)
-    conv_bytes = read_conversion_traffic(workload) if args.kind == "directed" else None
-    io_min = 16 * n + 24 * V + 8 + 8 * E
-    bits, items = ringo.tune_get(n)[:2]
-
+    spec = {1: workloads.config1, 2: workloads.config2, 3: workloads.config3}[args.config]()
+    m = measure_conversion(spec, args, kind, copy_gbps, args.steps, args.warmup)
     out = {
         "metric": ("edges/s converted (input rows per second, table to directed simple graph, 1 GPU)"
                    if args.kind == "directed" else
                    f"edges/s converted (input rows per second, table to {args.kind} graph, 1 GPU)"),
-        "value": n / (ms / 1e3),
-        "unit": "edges/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "value": m["value"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64",
-        "data": "synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)",
-        "config": {"workload": workload, "graph_kind": args.kind,
-                   "rows": n, "nodes": V, "edges": E, "seed": spec.seed,
-                   "digit_bits": bits, "items_per_thread": items,
-                   "node_method": "hash" if ringo.tune_get(n)[2] == ringo.NODES_HASH else "sort"},
-        "roofline": {"bound": "hbm", "kernel": dom,
-                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items, bits=bits),
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     # the counter-measured bytes over the same launch time (line-granular
-                     # traffic of random accesses included), against the same peak
-                     "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None,
-                     "traffic_frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBPS, 4) if traffic else None,
-                     "traffic_frac_of_copy": round(traffic / avg_s / 1e9 / copy_gbps, 4) if traffic else None,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": round(avg_s * 1e3, 5)},
-        "ms_per_step_untraced": ms_untraced,
-        # every kernel of one conversion together: counter-measured HBM bytes
-        # over the untraced conversion time
-        # (frac: of the 8 TB/s peak; frac_of_copy: of what the copy kernel
-        # measured in this run)
-        "conversion_traffic": ({"bytes": conv_bytes, "GBps": round(conv_bytes / (ms_untraced / 1e3) / 1e9, 1),
-                                "frac": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                "frac_of_copy": round(conv_bytes / (ms_untraced / 1e3) / 1e9 / copy_gbps, 4)}
-                               if conv_bytes else None),
-        # reading the table once and writing the graph once: 16n + 24V + 8 + 8E bytes
-        "io_minimum": {"bytes": io_min, "GBps": round(io_min / (ms_untraced / 1e3) / 1e9, 1),
-                       "frac": round(io_min / (ms_untraced / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "data": ("synthetic (seeded R-MAT on the device, hashed 64-bit identifiers)" if spec.kind == "rmat"
+                 else "synthetic (seeded uniform table, hashed 64-bit identifiers)"),
+        "config": {"workload": m["workload"], "graph_kind": args.kind, "rows": m["rows"], "nodes": m["nodes"],
+                   "edges": m["edges"], "seed": m["seed"], "digit_bits": m["digit_bits"],
+                   "items_per_thread": m["items_per_thread"], "node_method": m["node_method"]},
+        "roofline": m["roofline"],
+        "ms_per_step_untraced": m["ms_per_step_untraced"],
+        "ms_single_step_median": m["ms_single_step_median"],
+        "conversion_alg": m["conversion_alg"],
+        "conversion_traffic": m["conversion_traffic"],
+        "io_minimum": m["io_minimum"],
         "copy_kernel_GBps": round(copy_gbps, 1),
-        "kernels": kernels,
+        "kernels": m["kernels"],
     }
-    if not args.no_cpu_baseline and args.config == 2:
-        log(f"bench: CPU oracle on {args.cpu_rows:,} rows")
-        out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(args.cpu_rows)
+    if args.config == 3 and not args.no_extras and args.kind == "directed":
+        # the LiveJournal-shaped 2^26-row workload and the batched speedup
+        c2 = measure_conversion(workloads.config2(), args, kind, copy_gbps, args.steps, min(args.warmup, 2))
+        out["config2"] = {k: c2[k] for k in ("workload", "value", "ms_per_step", "ms_per_step_untraced",
+                                             "ms_single_step_median", "nodes", "edges", "conversion_alg",
+                                             "conversion_traffic")}
+        out["config2"]["roofline"] = {k: c2["roofline"][k] for k in ("kernel", "frac", "achieved", "traffic",
+                                                                      "avg_launch_ms")}
+        out["batched"] = batched_extra(args.steps)
+    if not args.no_cpu_baseline and args.config in (2, 3):
+        log(f"bench: CPU oracle on the first {args.cpu_rows:,} rows")
+        out["cpu_baseline"], out["cpu_baseline_all_cores"] = cpu_baseline(spec, args.cpu_rows)
+        if args.config == 3 and not args.no_extras:
+            log("bench: CPU oracle on the whole 2^26-row table")
+            out["cpu_oracle_config2_whole_table"] = cpu_oracle_full(workloads.config2())
     print(json.dumps(out), flush=True)
 
 

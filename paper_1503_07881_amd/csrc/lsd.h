@@ -26,6 +26,7 @@
 // schedule table picks it.
 #pragma once
 
+#include <atomic>
 #include <type_traits>
 
 #include "device_common.h"
@@ -567,14 +568,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   }
 }
 
-// Blocks of the downsweep that fit on the device at once.
+// Blocks of the downsweep that fit on the device at once.  The occupancy
+// query is host work on the launch path of small tables, so its answer is
+// kept (per instantiation; the blocks per CU do not depend on the device
+// among gfx950 parts, the CU count is itself cached per device).
 template <int ITEMS, int RB>
 static int resident_t() {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_downsweep<256, ITEMS, SORT_PLAIN, RB>,
-                                                   256, 0) != hipSuccess ||
-      nb < 1)
-    nb = 1;
+  static std::atomic<int> per_cu{0};
+  int nb = per_cu.load(std::memory_order_relaxed);
+  if (nb == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_downsweep<256, ITEMS, SORT_PLAIN, RB>,
+                                                     256, 0) != hipSuccess ||
+        nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    per_cu.store(nb, std::memory_order_relaxed);
+  }
   return nb * device_cu_count();
 }
 

@@ -1,0 +1,98 @@
+"""Element-by-element parity with the CPU oracle at the benchmark's sizes and
+in the exact launch configurations the benchmark times (Section 2.4's
+conversion; bit-exact, since it is integer work).
+
+- the 2^26-row R-MAT workload, whole, under the built-in schedule (hash
+  numbering, 8-bit digits, 8 items: the remap's fused first-pass counts,
+  per-run sums and the two-kernel scan at 32,768 edge-sort tiles)
+- a 2^24-row R-MAT table under the built-in schedule, and under the
+  schedule of the 1.5e9-row workload (9-bit digits, 16 items per thread)
+- every one of the 4096 tables of the batched workload (in
+  test_gpu_parity.test_config4_batched_full)
+
+The oracle runs on the host with its sorts in parallel mode where a table is
+large (the same steps, identical result, tested in the oracle's pins).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import assert_same
+from paper_1503_07881_amd import ringo, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _host_graph(g):
+    return {f: getattr(g, f).cpu().numpy() for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets",
+                                                      "in_nbrs")}
+
+
+def _device_rmat(spec, dev):
+    import torch
+    src = torch.empty(spec.n, dtype=torch.int64, device=dev)
+    dst = torch.empty(spec.n, dtype=torch.int64, device=dev)
+    workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return src, dst
+
+
+def test_config2_whole_table_vs_oracle(cuda):
+    """The whole 2^26-row table, converted exactly as the benchmark converts
+    it (built-in schedule), equals the oracle's graph element by element."""
+    import torch
+    spec = workloads.config2()
+    d, it, m = ringo.tune_get(spec.n)
+    say("config 2 whole table: 2^26 rows, schedule digit bits", d, "items", it, "method", m)
+    assert m == ringo.NODES_HASH and d == 8 and it == 8, "the benchmark's schedule for 2^26 rows"
+    src, dst = _device_rmat(spec, cuda)
+    ringo.trace_enable(True)
+    g = ringo.to_graph(src, dst)
+    torch.cuda.synchronize()
+    names = set(ringo.trace_read())
+    ringo.trace_enable(False)
+    # the hash numbering with the bucketed distinct-key sort ran
+    assert {"hash_insert", "hash_remap_pack", "hash_bucket_sort"} <= names, sorted(names)
+    got = _host_graph(g)
+    del g
+    hs, hd = src.cpu().numpy(), dst.cpu().numpy()
+    del src, dst
+    say("config 2 whole table: V", got["node_ids"].size, "E", got["out_nbrs"].size, "- oracle on the host")
+    want = oracle.table_to_graph(hs, hd, all_cores=True)
+    assert_same(got, want, "config 2 whole table: ")
+
+
+@pytest.mark.parametrize("sched", ["builtin", "large_table"])
+def test_rmat_2e24_vs_oracle(cuda, sched):
+    """2^24 rows (8,192 edge-sort tiles of 2048 keys): the built-in schedule
+    (hash numbering, 8-bit digits, remap-fused first-pass counts, per-run
+    sums, two-kernel scan), and the large-table schedule of the 1.5e9-row
+    workload (9-bit digits, 16 items per thread)."""
+    import torch
+    spec = workloads.TableSpec("rmat", 1 << 24, seed=24, scale=20)
+    src, dst = _device_rmat(spec, cuda)
+    hs, hd = src.cpu().numpy(), dst.cpu().numpy()
+    saved = ringo.tune_get(spec.n)
+    try:
+        if sched == "large_table":
+            ringo.tune_set(spec.n, 9, 16, ringo.NODES_HASH)
+        say("R-MAT 2^24 rows, schedule", sched, ringo.tune_get(spec.n))
+        ringo.trace_enable(True)
+        g = ringo.to_graph(src, dst)
+        torch.cuda.synchronize()
+        names = set(ringo.trace_read())
+        ringo.trace_enable(False)
+        assert "hash_insert" in names, sorted(names)
+        got = _host_graph(g)
+    finally:
+        ringo.trace_enable(False)
+        ringo.tune_set(spec.n, *saved)
+    want = oracle.table_to_graph(hs, hd, all_cores=True)
+    assert_same(got, want, f"2^24 rows {sched}: ")
