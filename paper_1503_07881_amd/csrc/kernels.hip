@@ -66,6 +66,67 @@ hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
   return hipGetLastError();
 }
 
+// --------------------------------------------- sync-free single table
+//
+// A call whose sizes all follow from n (worst-case tile maps, outputs sized
+// V <= 2n and E <= n) enqueues every kernel at once: the metadata is
+// written by a kernel from its arguments, and V and E pass from the kernels
+// that count them into the plan on the device.
+
+__global__ void k_meta_init(MetaWords m, int32_t nwords, uint64_t *dst, int64_t *results,
+                            int32_t nres) {
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = m.w[i];
+  for (int i = threadIdx.x; i < nres; i += blockDim.x) results[i] = 0;
+}
+
+// V (results[0]) into the plan, and the directory's bucket bits from it.
+__global__ void k_plan_nodes(SegPlan *plan, const int64_t *results, int32_t dirk_cap) {
+  if (threadIdx.x != 0) return;
+  const int64_t V = results[0];
+  plan->V = V;
+  plan->dirk = std::min(V > 0 ? ceil_log2(V) : 0, (int)dirk_cap);
+}
+
+// E (results[1]) into the plan; V and E to the caller's pair.
+__global__ void k_plan_edges(SegPlan *plan, const int64_t *results, int64_t *ve) {
+  if (threadIdx.x != 0) return;
+  plan->E = results[1];
+  ve[0] = plan->V;
+  ve[1] = results[1];
+}
+
+// A table with no rows: both offset arrays are {0}, V = E = 0.
+__global__ void k_fixed_empty(int64_t *out_off, int64_t *in_off, int64_t *ve) {
+  if (threadIdx.x != 0) return;
+  out_off[0] = 0;
+  in_off[0] = 0;
+  ve[0] = 0;
+  ve[1] = 0;
+}
+
+hipError_t launch_meta_init(const MetaWords &m, int32_t nwords, uint64_t *dst, int64_t *results,
+                            int32_t nres, hipStream_t s) {
+  if (nwords < 0 || nwords > META_WORDS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(64), 0, s, m, nwords, dst, results, nres);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_nodes(SegPlan *plan, const int64_t *results, int32_t dirk_cap,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_nodes, dim3(1), dim3(64), 0, s, plan, results, dirk_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_edges(SegPlan *plan, const int64_t *results, int64_t *ve, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan_edges, dim3(1), dim3(64), 0, s, plan, results, ve);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixed_empty(int64_t *out_off, int64_t *in_off, int64_t *ve, hipStream_t s) {
+  hipLaunchKernelGGL(k_fixed_empty, dim3(1), dim3(64), 0, s, out_off, in_off, ve);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ LSD pass
 //
 // The pass kernels are in lsd.h, one translation unit per digit width.

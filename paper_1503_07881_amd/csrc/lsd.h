@@ -128,7 +128,9 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
     __builtin_amdgcn_wave_barrier();
     H.at(a, t);
     const int64_t k0 = (t - H.first) * tile_keys;
-    const int64_t k1 = std::min<int64_t>(k0 + tile_keys, H.count);
+    // a tile past the table's key count (tile maps sized for the worst case,
+    // the count set on the device) is empty
+    const int64_t k1 = std::max<int64_t>(k0, std::min<int64_t>(k0 + tile_keys, H.count));
     if (!FIRST && ((uintptr_t)(a.in + H.start + k0) & 15) == 0) {
       // keys read in place, two per lane (16-byte loads); an odd last key
       // on its own
@@ -383,7 +385,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       }
     }
     const int64_t base = (tile - H.first) * (int64_t)TILE;
-    const int cnt = (int)std::min<int64_t>(TILE, H.count - base);
+    // a tile past the key count (worst-case tile maps) is empty: its loads
+    // read the tile's first slot, inside the buffer, and nothing is written
+    const int cnt = (int)std::max<int64_t>(0, std::min<int64_t>(TILE, H.count - base));
 
     // Wave w owns the contiguous run [w * ITEMS * 64, (w + 1) * ITEMS * 64)
     // of the tile, one coalesced 64-key row per item.  Lanes past the end

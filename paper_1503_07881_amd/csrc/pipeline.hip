@@ -361,7 +361,7 @@ struct Call {
 enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
-  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_KINDS
+  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -371,7 +371,7 @@ const char *const kTraceNames[TK_KINDS] = {
     "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
-    "hash_bucket_sort"};
+    "hash_bucket_sort", "plan_device"};
 
 struct TraceRec {
   int kind;
@@ -966,6 +966,277 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   return RINGO_OK;
 }
 
+// ------------------------------------------------ sync-free single table
+//
+// A directed table of at most FIXED_MAX_ROWS rows, numbered by sorting,
+// converted with nothing read back in between: every kernel is enqueued at
+// once.  All sizes follow from n.  The tile maps are those of the worst
+// case (V = 2n nodes, E = n edges); the kernels that count V and E move
+// them into the plan on the device, so the later kernels walk the real
+// ranges and their extra tiles are empty.  The packed edge key takes
+// b = ceil(log2 2n) bits per index whatever V turns out to be: (s << b) | d
+// orders the edges the same way for every b >= ceil(log2 V), so the graph is
+// identical (at most one edge pass more than the exact b would need).  The
+// outputs are sized for the worst case: node_ids [2n], out_off and in_off
+// [2n + 1], out_nbr and in_nbr [n].
+constexpr int64_t FIXED_MAX_ROWS = (int64_t)1 << 20;
+
+struct FixedOut {
+  int64_t *node_ids;
+  int64_t *out_off;
+  int32_t *out_nbr;
+  int64_t *in_off;
+  int32_t *in_nbr;
+};
+
+// Workspace of the sync-free path: offsets of its buffers in one block.
+struct FixedLayout {
+  int rb = DEFAULT_DIGIT_BITS, items = 8, sort_tile = 2048, b = 1, dirk_cap = 0;
+  size_t off_A = 0, off_B = 0, off_counts = 0, off_bsum = 0, off_base = 0, off_results = 0,
+         off_meta = 0, off_dir = 0, bytes = 0;
+};
+
+FixedLayout fixed_layout(int64_t n, int rb, int items) {
+  FixedLayout L;
+  L.rb = rb;
+  L.items = items;
+  L.sort_tile = sort_tile(items);
+  L.b = std::max(1, ceil_log2(2 * std::max<int64_t>(n, 1)));
+  L.dirk_cap = ceil_log2(std::max<int64_t>(n, 1));
+  const int64_t R = (int64_t)1 << rb;
+  const int64_t node_tiles = (2 * n + L.sort_tile - 1) / L.sort_tile;
+  const int64_t row_tiles = (n + L.sort_tile - 1) / L.sort_tile;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 8));
+    return o;
+  };
+  L.off_A = take(sizeof(uint64_t) * 2 * n);
+  L.off_B = take(sizeof(uint64_t) * 2 * n);
+  // tile counts of the largest pass (also the unique's tile counts, fewer)
+  L.off_counts = take(sizeof(uint32_t) * R * (node_tiles + 1));
+  L.off_bsum = take(sizeof(uint32_t) * R * std::max(sort_runs(node_tiles), sort_runs(row_tiles)));
+  L.off_base = take(sizeof(int64_t) * R);
+  L.off_results = take(sizeof(int64_t) * 2);
+  L.off_meta = take(sizeof(uint64_t) * META_WORDS);
+  L.off_dir = take(sizeof(DirEntry) * (((size_t)1 << L.dirk_cap) + 1));
+  L.bytes = off;
+  return L;
+}
+
+// Enqueues the whole conversion of one table on st, in the workspace ws
+// (L.bytes bytes, laid out by L); ve receives {V, E} on the device.  No
+// allocation, no synchronisation; traced only when `traced` is set.
+ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, const FixedOut &o,
+                             int64_t *ve, char *ws, const FixedLayout &L, bool traced,
+                             hipStream_t st) {
+  if (n == 0) {
+    HIP_TRY(launch_fixed_empty(o.out_off, o.in_off, ve, st));
+    return RINGO_OK;
+  }
+  Call c;
+  // the workspace is the caller's: the call's own release must not free it
+  struct Detach {
+    Call &c;
+    ~Detach() {
+      c.A = c.B = nullptr;
+      c.base = c.results = nullptr;
+      c.meta = nullptr;
+      c.dir = nullptr;
+      c.counts = c.bsum = nullptr;
+    }
+  } detach{c};
+  c.S = 1;
+  c.stream = st;
+  c.items = L.items;
+  c.rb = L.rb;
+  c.sort_tile = L.sort_tile;
+  c.plan.assign(1, SegPlan{});
+  c.tmap.assign((size_t)TM_KINDS * 2, 0);
+  SegPlan &p = c.plan[0];
+  p.src = src;
+  p.dst = dst;
+  p.n = n;
+  p.row_off = 0;
+  p.V = 2 * n;  // the worst case, for the tile maps; the device sets V and E
+  p.E = n;
+  p.b = L.b;
+  p.dirk = L.dirk_cap;
+  p.dir_off = 0;
+  p.node_ids = o.node_ids;
+  p.out_off = o.out_off;
+  p.out_nbr = o.out_nbr;
+  p.in_off = o.in_off;
+  p.in_nbr = o.in_nbr;
+  c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
+  c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
+  c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
+  c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
+  c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);
+  c.set_tiles(TM_ISORT, RANGE_EDGES, c.sort_tile);
+  c.set_tiles(TM_ICSR, RANGE_EDGES, SCAN_TILE);
+  c.A = (uint64_t *)(ws + L.off_A);
+  c.B = (uint64_t *)(ws + L.off_B);
+  c.counts = (uint32_t *)(ws + L.off_counts);
+  c.bsum = (uint32_t *)(ws + L.off_bsum);
+  c.base = (int64_t *)(ws + L.off_base);
+  c.results = (int64_t *)(ws + L.off_results);
+  c.meta = (uint8_t *)(ws + L.off_meta);
+  c.dir = (DirEntry *)(ws + L.off_dir);
+  // plan and tile maps, laid out as Call::upload lays them out
+  const size_t tmap_at = align_up(sizeof(SegPlan));
+  const size_t meta_bytes = tmap_at + sizeof(int64_t) * c.tmap.size();
+  static_assert(sizeof(SegPlan) <= 256, "plan fits its slot of the metadata");
+  if (meta_bytes > sizeof(MetaWords)) return RINGO_ERR_INVALID_ARG;
+  MetaWords m;
+  std::memset(&m, 0, sizeof(m));
+  std::memcpy(m.w, &p, sizeof(SegPlan));
+  std::memcpy((char *)m.w + tmap_at, c.tmap.data(), sizeof(int64_t) * c.tmap.size());
+  c.meta_bytes = meta_bytes;
+  const int cus = device_cu_count();
+  SegPlan *plan_dev = (SegPlan *)c.meta;
+
+  // traced entries only when asked (TRACED records events when tracing is on)
+#define FX(kind, units, bytes, expr)                             \
+  do {                                                           \
+    if (traced) TRACED(kind, units, bytes, expr);                \
+    else HIP_TRY(expr);                                          \
+  } while (0)
+#define FX_PASS(kcount, kscatter, keys, mode, a)                                                \
+  do {                                                                                          \
+    FX(kcount, keys, 8.0 * (keys), launch_sort_part(a, mode, c.items, c.rb, SORT_PART_COUNT, st)); \
+    FX(kscatter, keys, 16.0 * (keys),                                                           \
+       launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                        \
+  } while (0)
+
+  HIP_TRY(launch_meta_init(m, (int32_t)((meta_bytes + 7) / 8), (uint64_t *)c.meta, c.results, 2, st));
+  // node keys: ceil(64 / d) passes, the last one into B
+  const int P_n = lsd_passes(64, c.rb);
+  uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
+  for (int q = 0; q < P_n; ++q) {
+    SortLaunch a = c.sort_args(q == 0 ? nullptr : nbuf[(q - 1) & 1], nbuf[q & 1], TM_NSORT,
+                               RANGE_NODE_KEYS, P_n, q, c.rb * q);
+    FX_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * n, q == 0 ? SORT_NODE_FIRST : SORT_NODE, a);
+  }
+  FX(TK_UNIQUE, 2 * n, 16.0 * n,
+     launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.counts,
+                   grid_for(c.total(TM_UNIQ), cus * 4), st));
+  FX(TK_PLAN, 1, 0.0, launch_plan_nodes(plan_dev, c.results, L.dirk_cap, st));
+  FX(TK_DIR, 2 * n, 0.0,
+     launch_dir(c.tiles(TM_DIR, RANGE_NODES), c.A, c.dir, grid_for(c.total(TM_DIR), cus * 8), st));
+  FX(TK_REMAP, n, 24.0 * n,
+     launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B, 0,
+                  grid_for(c.total(TM_REMAP), cus * 8), st));
+  // edge keys: ceil(2b / d) passes from B
+  uint64_t *ebuf[2] = {c.B, c.A};
+  const int P_e = lsd_passes(2 * L.b, c.rb);
+  const int P_in = lsd_passes(L.b, c.rb);
+  for (int q = 0; q < P_e; ++q) {
+    SortLaunch a = c.sort_args(ebuf[q & 1], ebuf[(q + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, q,
+                               c.rb * q);
+    FX_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, n, SORT_EDGE, a);
+  }
+  uint64_t *sorted_edges = ebuf[P_e & 1];
+  uint64_t *ukeys = ebuf[(P_e + 1) & 1];
+  // first in-pass with the dedupe folded in: its count gives E
+  SortLaunch in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
+  in0.seg_total = c.results + 1;
+  FX(TK_IN_COUNT, n, 8.0 * n,
+     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
+  FX(TK_PLAN, 1, 0.0, launch_plan_edges(plan_dev, c.results, ve, st));
+  FX(TK_IN_SCATTER, n, 20.0 * n,
+     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
+  uint64_t *ib[2] = {ukeys, sorted_edges};
+  for (int q = 1; q < P_in; ++q) {
+    SortLaunch a = c.sort_args(ib[(q - 1) & 1], ib[q & 1], TM_ISORT, RANGE_EDGES, P_in, q,
+                               32 + c.rb * q);
+    FX_PASS(TK_IN_COUNT, TK_IN_SCATTER, n, SORT_IN, a);
+  }
+  FX(TK_IN_CSR, n, 12.0 * n,
+     launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ib[(P_in - 1) & 1], nullptr,
+                   grid_for(c.total(TM_ICSR), cus * 8), st));
+#undef FX_PASS
+#undef FX
+  return RINGO_OK;
+}
+
+// The single-table call through the sync-free path: library workspace,
+// outputs sized for the worst case in one block, one synchronisation at the
+// end to read V and E.
+ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, ringo_graph_t *out,
+                             hipStream_t st) {
+  const AllocHooks h = hooks();
+  const FixedLayout L = fixed_layout(n, digit_bits_for(n), items_for(n));
+  size_t offs[5], arena = 0;
+  const size_t sz[5] = {sizeof(int64_t) * 2 * n, sizeof(int64_t) * (2 * n + 1),
+                        sizeof(int32_t) * n, sizeof(int64_t) * (2 * n + 1), sizeof(int32_t) * n};
+  for (int f = 0; f < 5; ++f) {
+    offs[f] = arena;
+    arena = align_up(arena + sz[f]);
+  }
+  char *ws = (char *)dev_alloc(h, L.bytes, st);
+  char *blk = (char *)dev_alloc(h, arena, st);
+  Pinned *pin = pinned_acquire(sizeof(int64_t) * 2);
+  ringo_status_t rc = RINGO_OK;
+  int64_t V = 0, E = 0;
+  if (!ws || !blk || !pin) {
+    rc = RINGO_ERR_OUT_OF_MEMORY;
+  } else {
+    FixedOut o{(int64_t *)(blk + offs[0]), (int64_t *)(blk + offs[1]), (int32_t *)(blk + offs[2]),
+               (int64_t *)(blk + offs[3]), (int32_t *)(blk + offs[4])};
+    int64_t *ve = (int64_t *)(ws + L.off_results);
+    rc = enqueue_fixed(src, dst, n, o, ve, ws, L, true, st);
+    if (rc == RINGO_OK &&
+        (hipMemcpyAsync(pin->p, ve, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, st) != hipSuccess ||
+         hipStreamSynchronize(st) != hipSuccess))
+      rc = RINGO_ERR_HIP;
+    if (rc == RINGO_OK) {
+      V = ((const int64_t *)pin->p)[0];
+      E = ((const int64_t *)pin->p)[1];
+      if (V > max_nodes()) rc = RINGO_ERR_TOO_MANY_NODES;
+    }
+    if (rc == RINGO_OK) {
+      std::memset(out, 0, sizeof(*out));
+      Owner *owner = new Owner();
+      owner->stream = st;
+      owner->hooks = h;
+      owner->blocks[0] = blk;
+      owner->refs.store(1);
+      out->num_rows = n;
+      out->num_nodes = V;
+      out->num_edges = E;
+      out->node_ids = o.node_ids;
+      out->out_offsets = o.out_off;
+      out->out_nbrs = o.out_nbr;
+      out->in_offsets = o.in_off;
+      out->in_nbrs = o.in_nbr;
+      out->kind = RINGO_GRAPH_DIRECTED;
+      out->_alloc = owner;
+      blk = nullptr;  // now owned by the graph
+    }
+  }
+  if (rc != RINGO_OK) {
+    (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
+  }
+  dev_free(h, ws, st);
+  dev_free(h, blk, st);
+  if (pin) pinned_release(pin, st);
+  return rc;
+}
+
+// The sync-free path serves directed single tables above the LDS path's
+// size and up to FIXED_MAX_ROWS rows whose schedule numbers nodes by
+// sorting.  RINGO_FIXED_PATH=0 (test support) sends them through the pass
+// pipeline instead.
+bool fixed_path_for(int32_t S, int32_t kind, int64_t n) {
+  if (S != 1 || kind != RINGO_GRAPH_DIRECTED || n <= SMALL_ROWS || n > FIXED_MAX_ROWS) return false;
+  const char *e = std::getenv("RINGO_FIXED_PATH");
+  if (e && e[0] == '0') return false;
+  return method_for(n) == RINGO_NODES_SORT;
+}
+
 // Stable LSD sort of n keys by their low `bits` bits with the conversion's
 // radix passes (one table, plain mode, the schedule's digit width for n
 // rows); the last pass writes `out`.
@@ -1028,6 +1299,11 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
   if (S == 0) return RINGO_OK;
   (void)hipGetLastError();
   prepare_pool();
+  if (fixed_path_for(S, kind, num_rows[0])) {
+    const ringo_status_t rc = convert_fixed(src[0], dst[0], num_rows[0], &outs[0], stream);
+    if (rc != RINGO_OK) std::memset(&outs[0], 0, sizeof(ringo_graph_t));
+    return rc;
+  }
   Call c;
   c.S = S;
   c.kind = kind;

@@ -238,6 +238,20 @@ hipError_t launch_out_nbr(const TileLaunch &t, const uint64_t *in, int grid, hip
 // Multigraph: v[row_off + r] = r for every row of every table.
 hipError_t launch_iota(const TileLaunch &rows, uint32_t *v, int grid, hipStream_t s);
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
+// Sync-free single table (kernels.hip): the plan and tile maps passed by
+// value (at most META_WORDS words) and copied to dst, results[0, nres)
+// zeroed; V and E moved from results into the plan on the device (and to
+// ve = {V, E}); the outputs of an empty table.
+constexpr int META_WORDS = 64;
+struct MetaWords {
+  uint64_t w[META_WORDS];
+};
+hipError_t launch_meta_init(const MetaWords &m, int32_t nwords, uint64_t *dst, int64_t *results,
+                            int32_t nres, hipStream_t s);
+hipError_t launch_plan_nodes(SegPlan *plan, const int64_t *results, int32_t dirk_cap,
+                             hipStream_t s);
+hipError_t launch_plan_edges(SegPlan *plan, const int64_t *results, int64_t *ve, hipStream_t s);
+hipError_t launch_fixed_empty(int64_t *out_off, int64_t *in_off, int64_t *ve, hipStream_t s);
 int device_cu_count();
 
 // ------------------------------------------------ small tables (small.hip)

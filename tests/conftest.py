@@ -43,9 +43,12 @@ def method(request):
 
 @pytest.fixture(params=["lds", "pipeline"])
 def small_path(request):
-    """Runs the test with small tables converted in LDS (the default) and
-    with every table sent through the pass pipeline."""
+    """Runs the test with the default routing (tables of at most 2048 rows
+    converted in LDS, single tables up to 2^20 rows numbered by sorting on the
+    sync-free path) and with every table sent through the pass pipeline."""
     if request.param == "pipeline":
         os.environ["RINGO_SMALL_TABLES"] = "0"
+        os.environ["RINGO_FIXED_PATH"] = "0"
     yield request.param
     os.environ.pop("RINGO_SMALL_TABLES", None)
+    os.environ.pop("RINGO_FIXED_PATH", None)

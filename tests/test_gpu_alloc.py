@@ -71,11 +71,18 @@ KINDS = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
 
 
 @pytest.mark.parametrize("kname", list(KINDS))
-@pytest.mark.parametrize("method", ["sort", "hash"])
-def test_allocator_hook_and_out_of_memory(cuda, method, kname):
+@pytest.mark.parametrize("method", ["sort", "hash", "sync_free"])
+def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
+    """method: the node numbering of the pass pipeline, or (directed tables
+    numbered by sorting) the sync-free single-table path, whose workspace
+    and outputs are two requests."""
     import torch
+    if method == "sync_free" and kname != "directed":
+        pytest.skip("the sync-free path converts directed tables only")
+    if method != "sync_free":
+        monkeypatch.setenv("RINGO_FIXED_PATH", "0")
     rng = np.random.default_rng(5)
-    n = 300_000  # above the small-table size: the pass pipeline
+    n = 300_000  # above the small-table size
     src_h = rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
     dst_h = src_h[rng.permutation(n)]
     src, dst = (torch.from_numpy(a).to(cuda) for a in (src_h, dst_h))
@@ -91,7 +98,7 @@ def test_allocator_hook_and_out_of_memory(cuda, method, kname):
         rc, g = convert_raw(src, dst, kind)
         assert rc == 0
         total = al.requests
-        assert total > 3 and al.live
+        assert (total == 2 if method == "sync_free" else total > 3) and al.live
         ringo.graph_free(g)
         assert not al.live, "blocks left after graph_free"
         # refuse every request in turn (a sample of them for speed)
