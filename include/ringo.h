@@ -121,6 +121,43 @@ ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int6
                                     ringo_graph_t *out, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * conversion as ringo_table_to_graph (the graph is identical) for one table
+ * of at most RINGO_NOALLOC_MAX_ROWS rows, into arrays the caller allocates
+ * for the worst case, with the library's workspace in one fixed device array
+ * of RINGO_NOALLOC_SCRATCH_BYTES per device (held from the library's first
+ * use on that device until the process ends).  Nothing is allocated, and
+ * nothing is synchronised: the call only enqueues kernels on `stream`.
+ *   src, dst    : device arrays of num_rows int64 identifiers (as for
+ *                 ringo_table_to_graph).
+ *   num_rows    : 0 <= num_rows <= RINGO_NOALLOC_MAX_ROWS.
+ *   node_ids    : device int64 [2 * num_rows]      } the first V, V + 1, E
+ *   out_offsets : device int64 [2 * num_rows + 1]  } entries hold the graph
+ *   out_nbrs    : device int32 [num_rows]          } once the stream reaches
+ *   in_offsets  : device int64 [2 * num_rows + 1]  } the end of this work;
+ *   in_nbrs     : device int32 [num_rows]          } the rest is untouched
+ *   counts      : device int64 [2], receives {V, E}.
+ * With num_rows == 0 only out_offsets[0], in_offsets[0] (both 0) and counts
+ * ({0, 0}) are written; src, dst, node_ids and the neighbour arrays may then
+ * be NULL.
+ * Every call on a device uses that device's one workspace: calls that
+ * overlap on one device race and give wrong results, so order them (one
+ * stream, or events).  Each call writes every part of the workspace it
+ * reads, so no clearing is needed between calls.
+ * Errors: RINGO_ERR_INVALID_ARG (a NULL array, num_rows out of range),
+ * RINGO_ERR_HIP (the workspace's address could not be obtained, or a launch
+ * failed).
+ */
+#define RINGO_NOALLOC_MAX_ROWS ((int64_t)1 << 20)
+#define RINGO_NOALLOC_SCRATCH_BYTES ((size_t)50 << 20)
+ringo_status_t ringo_table_to_graph_noalloc(const int64_t *src, const int64_t *dst,
+                                            int64_t num_rows, int64_t *node_ids,
+                                            int64_t *out_offsets, int32_t *out_nbrs,
+                                            int64_t *in_offsets, int32_t *in_nbrs, int64_t *counts,
+                                            hipStream_t stream);
+
+/*
  * Batched conversion of num_tables independent edge tables (the same
  * operation as ringo_table_to_graph, Section 2.4, applied to each table).
  *   src, dst : HOST arrays of num_tables DEVICE pointers.

@@ -1226,6 +1226,37 @@ ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   return rc;
 }
 
+// ------------------------------------------- the entry point that allocates nothing
+//
+// Its workspace is one file-scope device array, the same on every call: the
+// sync-free path's layout for RINGO_NOALLOC_MAX_ROWS rows with 8-bit digits
+// and 8 items per thread fits in it (checked per call).  Host code never
+// passes the array's name to a kernel: its device address is looked up once
+// per device and kept.
+static __device__ __align__(256) uint8_t scratch[RINGO_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {nullptr};
+
+// The device address of `scratch` on the current device, or null.
+void *scratch_address() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // The sync-free path serves directed single tables above the LDS path's
 // size and up to FIXED_MAX_ROWS rows whose schedule numbers nodes by
 // sorting.  RINGO_FIXED_PATH=0 (test support) sends them through the pass
@@ -1333,6 +1364,24 @@ ringo_status_t ringo_table_to_graph(const int64_t *src, const int64_t *dst, int6
                                     ringo_graph_t *out, hipStream_t stream) {
   if (!out) return RINGO_ERR_INVALID_ARG;
   return convert(1, &src, &dst, &num_rows, RINGO_GRAPH_DIRECTED, out, stream);
+}
+
+ringo_status_t ringo_table_to_graph_noalloc(const int64_t *src, const int64_t *dst,
+                                            int64_t num_rows, int64_t *node_ids,
+                                            int64_t *out_offsets, int32_t *out_nbrs,
+                                            int64_t *in_offsets, int32_t *in_nbrs, int64_t *counts,
+                                            hipStream_t stream) {
+  if (num_rows < 0 || num_rows > RINGO_NOALLOC_MAX_ROWS) return RINGO_ERR_INVALID_ARG;
+  if (!out_offsets || !in_offsets || !counts) return RINGO_ERR_INVALID_ARG;
+  if (num_rows > 0 && (!src || !dst || !node_ids || !out_nbrs || !in_nbrs))
+    return RINGO_ERR_INVALID_ARG;
+  (void)hipGetLastError();
+  const FixedLayout L = fixed_layout(num_rows, DEFAULT_DIGIT_BITS, 8);
+  if (L.bytes > (size_t)RINGO_NOALLOC_SCRATCH_BYTES) return RINGO_ERR_INVALID_ARG;
+  char *ws = (char *)scratch_address();
+  if (!ws) return RINGO_ERR_HIP;
+  const FixedOut o{node_ids, out_offsets, out_nbrs, in_offsets, in_nbrs};
+  return enqueue_fixed(src, dst, num_rows, o, counts, ws, L, false, stream);
 }
 
 ringo_status_t ringo_table_to_graph_batched(int32_t num_tables, const int64_t *const *src,

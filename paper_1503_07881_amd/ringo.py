@@ -38,7 +38,10 @@ EXPORTED_SYMBOLS = (
     "ringo_server_stats", "ringo_server_destroy",
     "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
     "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex", "ringo_sort_keys",
+    "ringo_table_to_graph_noalloc",
 )
+
+NOALLOC_MAX_ROWS = 1 << 20
 
 
 class RingoError(RuntimeError):
@@ -128,6 +131,8 @@ def lib() -> ctypes.CDLL:
         L.ringo_pagerank.restype = ctypes.c_int
         L.ringo_sort_keys.argtypes = [p, p, i64, ctypes.c_int32, p]
         L.ringo_sort_keys.restype = ctypes.c_int
+        L.ringo_table_to_graph_noalloc.argtypes = [p, p, i64, p, p, p, p, p, p, p]
+        L.ringo_table_to_graph_noalloc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -178,6 +183,16 @@ def table_to_graph_batched_raw(src_ptrs, dst_ptrs, num_rows, stream: int,
         rc = lib().ringo_table_to_graph_batched_ex(k, S, D, N, kind, outs, stream)
     _check(rc, "ringo_table_to_graph_batched")
     return [outs[i] for i in range(k)]
+
+
+def table_to_graph_noalloc_raw(src_ptr: int, dst_ptr: int, num_rows: int, node_ids_ptr: int,
+                               out_offsets_ptr: int, out_nbrs_ptr: int, in_offsets_ptr: int,
+                               in_nbrs_ptr: int, counts_ptr: int, stream: int) -> None:
+    """ringo_table_to_graph_noalloc into caller-allocated worst-case device
+    arrays (node_ids [2n], offsets [2n + 1], neighbours [n], counts [2])."""
+    _check(lib().ringo_table_to_graph_noalloc(src_ptr, dst_ptr, num_rows, node_ids_ptr, out_offsets_ptr,
+                                              out_nbrs_ptr, in_offsets_ptr, in_nbrs_ptr, counts_ptr, stream),
+           "ringo_table_to_graph_noalloc")
 
 
 def graph_to_edge_table_raw(g: RawGraph, src_ptr: int, dst_ptr: int, stream: int) -> None:
