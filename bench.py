@@ -487,13 +487,17 @@ def measure_conversion(spec, args, kind, copy_gbps, steps, warmup):
     log(f"bench: untraced {ms_untraced:.3f} ms/step (median of {len(per)} single steps "
         f"{sorted(per)[len(per) // 2]:.3f})")
     # timed region, with per-kernel HIP events on the conversion's stream
+    # (a single table on the sync-free path enqueues its kernels here rather
+    # than replaying its captured graph, so that every kernel is timed)
     ringo.trace_enable(True)
+    os.environ["RINGO_FIXED_GRAPH"] = "0"
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         V, E = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    os.environ.pop("RINGO_FIXED_GRAPH", None)
     trace = ringo.trace_read()
     ringo.trace_enable(False)
     log(f"bench: timed {steps} steps: {ms:.3f} ms/step")

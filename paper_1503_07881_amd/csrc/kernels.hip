@@ -111,6 +111,8 @@ hipError_t launch_meta_init(const MetaWords &m, int32_t nwords, uint64_t *dst, i
   return hipGetLastError();
 }
 
+const void *meta_init_kernel() { return reinterpret_cast<const void *>(&k_meta_init); }
+
 hipError_t launch_plan_nodes(SegPlan *plan, const int64_t *results, int32_t dirk_cap,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_plan_nodes, dim3(1), dim3(64), 0, s, plan, results, dirk_cap);

@@ -361,7 +361,8 @@ struct Call {
 enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
-  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_KINDS
+  TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_GRAPH,
+  TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -371,7 +372,7 @@ const char *const kTraceNames[TK_KINDS] = {
     "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
-    "hash_bucket_sort", "plan_device"};
+    "hash_bucket_sort", "plan_device", "fixed_graph_replay"};
 
 struct TraceRec {
   int kind;
@@ -1025,30 +1026,13 @@ FixedLayout fixed_layout(int64_t n, int rb, int items) {
   return L;
 }
 
-// Enqueues the whole conversion of one table on st, in the workspace ws
-// (L.bytes bytes, laid out by L); ve receives {V, E} on the device.  No
-// allocation, no synchronisation; traced only when `traced` is set.
-ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, const FixedOut &o,
-                             int64_t *ve, char *ws, const FixedLayout &L, bool traced,
-                             hipStream_t st) {
-  if (n == 0) {
-    HIP_TRY(launch_fixed_empty(o.out_off, o.in_off, ve, st));
-    return RINGO_OK;
-  }
-  Call c;
-  // the workspace is the caller's: the call's own release must not free it
-  struct Detach {
-    Call &c;
-    ~Detach() {
-      c.A = c.B = nullptr;
-      c.base = c.results = nullptr;
-      c.meta = nullptr;
-      c.dir = nullptr;
-      c.counts = c.bsum = nullptr;
-    }
-  } detach{c};
+// The call state of the sync-free path over workspace ws: plan (sizes of
+// the worst case), tile maps, buffers, and the metadata words its first
+// kernel writes (plan and tile maps, laid out as Call::upload lays them out).
+ringo_status_t fixed_setup(Call &c, const int64_t *src, const int64_t *dst, int64_t n,
+                           const FixedOut &o, char *ws, const FixedLayout &L, MetaWords &m,
+                           int32_t &nwords) {
   c.S = 1;
-  c.stream = st;
   c.items = L.items;
   c.rb = L.rb;
   c.sort_tile = L.sort_tile;
@@ -1084,16 +1068,48 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   c.results = (int64_t *)(ws + L.off_results);
   c.meta = (uint8_t *)(ws + L.off_meta);
   c.dir = (DirEntry *)(ws + L.off_dir);
-  // plan and tile maps, laid out as Call::upload lays them out
   const size_t tmap_at = align_up(sizeof(SegPlan));
   const size_t meta_bytes = tmap_at + sizeof(int64_t) * c.tmap.size();
   static_assert(sizeof(SegPlan) <= 256, "plan fits its slot of the metadata");
   if (meta_bytes > sizeof(MetaWords)) return RINGO_ERR_INVALID_ARG;
-  MetaWords m;
   std::memset(&m, 0, sizeof(m));
   std::memcpy(m.w, &p, sizeof(SegPlan));
   std::memcpy((char *)m.w + tmap_at, c.tmap.data(), sizeof(int64_t) * c.tmap.size());
   c.meta_bytes = meta_bytes;
+  nwords = (int32_t)((meta_bytes + 7) / 8);
+  return RINGO_OK;
+}
+
+// The workspace belongs to the caller of the sync-free path: a Call over it
+// must not free it.
+struct Detach {
+  Call &c;
+  ~Detach() {
+    c.A = c.B = nullptr;
+    c.base = c.results = nullptr;
+    c.meta = nullptr;
+    c.dir = nullptr;
+    c.counts = c.bsum = nullptr;
+  }
+};
+
+// Enqueues the whole conversion of one table on st, in the workspace ws
+// (L.bytes bytes, laid out by L); ve receives {V, E} on the device.  No
+// allocation, no synchronisation; traced only when `traced` is set.
+ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, const FixedOut &o,
+                             int64_t *ve, char *ws, const FixedLayout &L, bool traced,
+                             hipStream_t st) {
+  if (n == 0) {
+    HIP_TRY(launch_fixed_empty(o.out_off, o.in_off, ve, st));
+    return RINGO_OK;
+  }
+  Call c;
+  Detach detach{c};
+  c.stream = st;
+  MetaWords m;
+  int32_t nwords = 0;
+  const ringo_status_t rs = fixed_setup(c, src, dst, n, o, ws, L, m, nwords);
+  if (rs != RINGO_OK) return rs;
   const int cus = device_cu_count();
   SegPlan *plan_dev = (SegPlan *)c.meta;
 
@@ -1110,7 +1126,7 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
        launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                        \
   } while (0)
 
-  HIP_TRY(launch_meta_init(m, (int32_t)((meta_bytes + 7) / 8), (uint64_t *)c.meta, c.results, 2, st));
+  HIP_TRY(launch_meta_init(m, nwords, (uint64_t *)c.meta, c.results, 2, st));
   // node keys: ceil(64 / d) passes, the last one into B
   const int P_n = lsd_passes(64, c.rb);
   uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
@@ -1161,9 +1177,174 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   return RINGO_OK;
 }
 
-// The single-table call through the sync-free path: library workspace,
-// outputs sized for the worst case in one block, one synchronisation at the
-// end to read V and E.
+// ------------------------------------------------ replay of the sync-free path
+//
+// The sync-free path's launch sequence depends only on n and the schedule,
+// and every pointer of a call (columns, outputs) is in the metadata its first
+// kernel writes from its arguments.  So each size's sequence is captured once
+// into a HIP graph over a workspace the library keeps per device, and a later
+// call of that size sets the first kernel's arguments and replays the graph:
+// one launch instead of about 75.  One call at a time per device uses the
+// kept workspace; a call that finds it busy, and calls through a caller's
+// allocator (which owns all device memory then), enqueue the kernels
+// themselves.  RINGO_FIXED_GRAPH=0 (test support) turns the replay off.
+constexpr int MAX_FIXED_GRAPHS = 8;
+
+struct FixedGraph {
+  int64_t n = 0;
+  int rb = 0, items = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t meta_node = nullptr;
+  hipKernelNodeParams meta{};
+  uint64_t used = 0;
+};
+
+// Per device: the kept workspace, the capture stream and the graphs.  Held
+// by one call at a time (its mutex); never released (the process owns it).
+struct GraphSlot {
+  std::mutex mu;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t cap = nullptr;
+  bool broken = false;  // capture failed once: calls enqueue their kernels
+  uint64_t clock = 0;
+  std::vector<FixedGraph> graphs;
+  std::vector<int64_t> seen;  // sizes met once (a size is captured when it comes back)
+};
+GraphSlot g_graph_slots[64];
+
+bool fixed_graph_enabled() {
+  const char *e = std::getenv("RINGO_FIXED_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+void fixed_graph_destroy(FixedGraph &g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+// The largest workspace of the sync-free path over every schedule.
+size_t fixed_ws_max() {
+  size_t m = 0;
+  for (int rb = MIN_DIGIT_BITS; rb <= MAX_DIGIT_BITS; ++rb)
+    for (int it : {8, 12, 16}) m = std::max(m, fixed_layout(FIXED_MAX_ROWS, rb, it).bytes);
+  return m;
+}
+
+// The slot's graph for n rows under layout L, captured when the size comes
+// the second time (the call's own pointers go into the capture; every
+// replay sets them anew); null when there is no graph (yet), and the call
+// enqueues its kernels.
+FixedGraph *fixed_graph_for(GraphSlot &S, const int64_t *src, const int64_t *dst, int64_t n,
+                            const FixedOut &o, const FixedLayout &L) {
+  for (FixedGraph &g : S.graphs)
+    if (g.n == n && g.rb == L.rb && g.items == L.items) {
+      g.used = ++S.clock;
+      return &g;
+    }
+  if (S.broken || n == 0) return nullptr;
+  // a size is captured the second time it comes: one-off sizes cost no
+  // capture, and the first call has set up what the launches query
+  const int64_t key = n * 64 + L.rb * 4 + L.items / 4;
+  if (std::find(S.seen.begin(), S.seen.end(), key) == S.seen.end()) {
+    if (S.seen.size() >= 64) S.seen.erase(S.seen.begin());
+    S.seen.push_back(key);
+    return nullptr;
+  }
+  if (!S.ws) {
+    const size_t bytes = fixed_ws_max();
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      S.broken = true;
+      return nullptr;
+    }
+    S.ws = (char *)p;
+    S.ws_bytes = bytes;
+  }
+  if (L.bytes > S.ws_bytes) return nullptr;
+  if (!S.cap && hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    S.cap = nullptr;
+    S.broken = true;
+    return nullptr;
+  }
+  FixedGraph g;
+  g.n = n;
+  g.rb = L.rb;
+  g.items = L.items;
+  bool ok = hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const ringo_status_t rc =
+        enqueue_fixed(src, dst, n, o, (int64_t *)(S.ws + L.off_results), S.ws, L, false, S.cap);
+    const hipError_t ec = hipStreamEndCapture(S.cap, &g.graph);
+    ok = rc == RINGO_OK && ec == hipSuccess && g.graph;
+  }
+  if (ok) ok = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) {
+    size_t nn = 0;
+    ok = hipGraphGetNodes(g.graph, nullptr, &nn) == hipSuccess && nn > 0;
+    std::vector<hipGraphNode_t> nodes(ok ? nn : 0);
+    if (ok) ok = hipGraphGetNodes(g.graph, nodes.data(), &nn) == hipSuccess;
+    for (size_t i = 0; ok && i < nn && !g.meta_node; ++i) {
+      hipGraphNodeType t;
+      if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+      hipKernelNodeParams kp{};
+      if (hipGraphKernelNodeGetParams(nodes[i], &kp) == hipSuccess && kp.func == meta_init_kernel()) {
+        g.meta_node = nodes[i];
+        g.meta = kp;
+      }
+    }
+    ok = ok && g.meta_node;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    fixed_graph_destroy(g);
+    S.broken = true;
+    return nullptr;
+  }
+  if ((int)S.graphs.size() >= MAX_FIXED_GRAPHS) {
+    size_t lru = 0;
+    for (size_t i = 1; i < S.graphs.size(); ++i)
+      if (S.graphs[i].used < S.graphs[lru].used) lru = i;
+    fixed_graph_destroy(S.graphs[lru]);
+    S.graphs.erase(S.graphs.begin() + (long)lru);
+  }
+  g.used = ++S.clock;
+  S.graphs.push_back(g);
+  return &S.graphs.back();
+}
+
+// One replay: the metadata kernel's arguments set to this call's, then the
+// graph launched on st (traced as one entry).
+ringo_status_t replay_fixed(GraphSlot &S, FixedGraph &g, const int64_t *src, const int64_t *dst,
+                            int64_t n, const FixedOut &o, const FixedLayout &L, hipStream_t st) {
+  Call c;
+  Detach detach{c};
+  c.stream = st;
+  MetaWords m;
+  int32_t nwords = 0;
+  const ringo_status_t rs = fixed_setup(c, src, dst, n, o, S.ws, L, m, nwords);
+  if (rs != RINGO_OK) return rs;
+  uint64_t *meta_dst = (uint64_t *)(S.ws + L.off_meta);
+  int64_t *results = (int64_t *)(S.ws + L.off_results);
+  int32_t nres = 2;
+  void *args[] = {&m, &nwords, &meta_dst, &results, &nres};
+  hipKernelNodeParams p = g.meta;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  HIP_TRY(hipGraphExecKernelNodeSetParams(g.exec, g.meta_node, &p));
+  TRACED(TK_GRAPH, n, 0.0, hipGraphLaunch(g.exec, st));
+  return RINGO_OK;
+}
+
+// The single-table call through the sync-free path: outputs sized for the
+// worst case in one block, the kept workspace and a graph replay when free
+// (else a workspace from the allocator and the kernels enqueued), one
+// synchronisation at the end to read V and E.
 ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, ringo_graph_t *out,
                              hipStream_t st) {
   const AllocHooks h = hooks();
@@ -1175,20 +1356,40 @@ ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
     offs[f] = arena;
     arena = align_up(arena + sz[f]);
   }
-  char *ws = (char *)dev_alloc(h, L.bytes, st);
+  // the kept workspace, when no caller's allocator is set and it is free
+  GraphSlot *slot = nullptr;
+  std::unique_lock<std::mutex> slot_lock;
+  int dev = -1;
+  if (!h.alloc && fixed_graph_enabled() && hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+    std::unique_lock<std::mutex> l(g_graph_slots[dev].mu, std::try_to_lock);
+    if (l.owns_lock()) {
+      slot = &g_graph_slots[dev];
+      slot_lock = std::move(l);
+    }
+  }
+  (void)hipGetLastError();
   char *blk = (char *)dev_alloc(h, arena, st);
   Pinned *pin = pinned_acquire(sizeof(int64_t) * 2);
   ringo_status_t rc = RINGO_OK;
   int64_t V = 0, E = 0;
-  if (!ws || !blk || !pin) {
+  char *ws = nullptr, *own_ws = nullptr;
+  if (!blk || !pin) {
     rc = RINGO_ERR_OUT_OF_MEMORY;
   } else {
     FixedOut o{(int64_t *)(blk + offs[0]), (int64_t *)(blk + offs[1]), (int32_t *)(blk + offs[2]),
                (int64_t *)(blk + offs[3]), (int32_t *)(blk + offs[4])};
-    int64_t *ve = (int64_t *)(ws + L.off_results);
-    rc = enqueue_fixed(src, dst, n, o, ve, ws, L, true, st);
+    FixedGraph *g = slot ? fixed_graph_for(*slot, src, dst, n, o, L) : nullptr;
+    if (g) {
+      ws = slot->ws;
+      rc = replay_fixed(*slot, *g, src, dst, n, o, L, st);
+    } else {
+      ws = own_ws = (char *)dev_alloc(h, L.bytes, st);
+      rc = ws ? enqueue_fixed(src, dst, n, o, (int64_t *)(ws + L.off_results), ws, L, true, st)
+              : RINGO_ERR_OUT_OF_MEMORY;
+    }
     if (rc == RINGO_OK &&
-        (hipMemcpyAsync(pin->p, ve, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        (hipMemcpyAsync(pin->p, ws + L.off_results, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, st) !=
+             hipSuccess ||
          hipStreamSynchronize(st) != hipSuccess))
       rc = RINGO_ERR_HIP;
     if (rc == RINGO_OK) {
@@ -1220,7 +1421,7 @@ ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
     (void)hipStreamSynchronize(st);
     (void)hipGetLastError();
   }
-  dev_free(h, ws, st);
+  dev_free(h, own_ws, st);
   dev_free(h, blk, st);
   if (pin) pinned_release(pin, st);
   return rc;

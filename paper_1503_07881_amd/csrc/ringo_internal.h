@@ -248,6 +248,8 @@ struct MetaWords {
 };
 hipError_t launch_meta_init(const MetaWords &m, int32_t nwords, uint64_t *dst, int64_t *results,
                             int32_t nres, hipStream_t s);
+// The metadata kernel itself (its node is found in a captured graph by it).
+const void *meta_init_kernel();
 hipError_t launch_plan_nodes(SegPlan *plan, const int64_t *results, int32_t dirk_cap,
                              hipStream_t s);
 hipError_t launch_plan_edges(SegPlan *plan, const int64_t *results, int64_t *ve, hipStream_t s);

@@ -17,6 +17,9 @@ pytestmark = pytest.mark.gpu
 
 I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
 FIXED_MAX_ROWS = 1 << 20
+# trace entries of the sync-free path: its kernels enqueued, or its graph
+# replayed (a size met before)
+SYNC_FREE = {"plan_device", "fixed_graph_replay"}
 
 
 def say(*a):
@@ -73,11 +76,11 @@ def test_sizes_vs_oracle_and_pipeline(cuda, sort_numbering, n):
         say("sync-free path n", n, "pool", pool)
         src, dst = random_table(n * 17 + pool, n, pool)
         got, names = convert(src, dst, cuda)
-        assert "plan_device" in names, sorted(names)
+        assert names & SYNC_FREE, sorted(names)
         assert_same(got, oracle.table_to_graph(src, dst), f"n={n} pool={pool}: ")
         if pool in (7, 4 * n):
             pipe, pnames = convert(src, dst, cuda, fixed=False)
-            assert "plan_device" not in pnames
+            assert not pnames & SYNC_FREE
             assert_same(got, pipe, f"n={n} pool={pool} against the pipeline: ")
 
 
@@ -105,7 +108,7 @@ def test_structures(cuda, sort_numbering):
     for name, (src, dst) in cases.items():
         say("sync-free structure", name, "rows", src.size)
         got, names = convert(src, dst, cuda)
-        assert "plan_device" in names, (name, sorted(names))
+        assert names & SYNC_FREE, (name, sorted(names))
         assert_same(got, oracle.table_to_graph(src, dst), name + ": ")
 
 
@@ -120,7 +123,7 @@ def test_schedules(cuda, sort_numbering, bits, items):
             say("sync-free schedule", bits, items, "pool", pool)
             src, dst = random_table(bits * 100 + items + pool, n, pool)
             got, names = convert(src, dst, cuda)
-            assert "plan_device" in names
+            assert names & SYNC_FREE
             assert_same(got, oracle.table_to_graph(src, dst), f"d={bits} items={items} pool={pool}: ")
     finally:
         ringo.tune_set(n, *saved)
@@ -138,7 +141,7 @@ def test_config1_and_repeat(cuda, sort_numbering):
                           ("small", small), ("config1 last", (src, dst))):
         say("sync-free sequence", label)
         got, names = convert(s, d, cuda)
-        assert "plan_device" in names
+        assert names & SYNC_FREE
         if s is src:
             assert_same(got, want, label + ": ")
         else:
@@ -149,5 +152,73 @@ def test_outside_the_range_uses_the_pipeline(cuda, sort_numbering):
     for n in (2048, FIXED_MAX_ROWS + 1):
         src, dst = random_table(n, n, n)
         got, names = convert(src, dst, cuda)
-        assert "plan_device" not in names, (n, sorted(names))
+        assert not names & SYNC_FREE, (n, sorted(names))
         assert_same(got, oracle.table_to_graph(src, dst), f"n={n}: ")
+
+
+def _convert_on(src_t, dst_t, stream=None):
+    import torch
+    ringo.trace_enable(True)
+    try:
+        g = ringo.to_graph(src_t, dst_t, stream=stream)
+        torch.cuda.synchronize()
+        names = set(ringo.trace_read())
+    finally:
+        ringo.trace_enable(False)
+    return {f: getattr(g, f).cpu().numpy() for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets",
+                                                     "in_nbrs")}, names
+
+
+def test_graph_replay_matches_eager(cuda, sort_numbering):
+    """A size met a second time is captured into a HIP graph and replayed.
+    Every replay, with other conversions, torch work and synchronisations in
+    between, on the default and on a side stream, equals the eager path
+    (replay off) and the oracle."""
+    import torch
+    hs1, hd1 = random_table(71, 300_001, 90_000)
+    hs2, hd2 = random_table(72, 50_000, 120_000)
+    s1, d1 = torch.from_numpy(hs1).to(cuda), torch.from_numpy(hd1).to(cuda)
+    s2, d2 = torch.from_numpy(hs2).to(cuda), torch.from_numpy(hd2).to(cuda)
+    os.environ["RINGO_FIXED_GRAPH"] = "0"
+    try:
+        ref1, n1 = _convert_on(s1, d1)
+        ref2, _ = _convert_on(s2, d2)
+    finally:
+        os.environ.pop("RINGO_FIXED_GRAPH", None)
+    assert "plan_device" in n1 and "fixed_graph_replay" not in n1
+    assert_same(ref1, oracle.table_to_graph(hs1, hd1), "eager: ")
+    side = torch.cuda.Stream(device=cuda)
+    replays = 0
+    for i in range(6):
+        say("graph replay round", i)
+        got, names = _convert_on(s1, d1, stream=side if i % 2 else None)
+        replays += "fixed_graph_replay" in names
+        if i >= 1:
+            assert "fixed_graph_replay" in names and "plan_device" not in names, (i, sorted(names))
+        assert_same(got, ref1, f"round {i}: ")
+        # other work in between: another size, torch kernels, the pipeline
+        got2, _ = _convert_on(s2, d2)
+        assert_same(got2, ref2, f"round {i}, second table: ")
+        x = torch.arange(1 << 20, device=cuda, dtype=torch.int64)
+        assert int((x * 3).sum()) == 3 * ((1 << 20) - 1) * (1 << 20) // 2
+        os.environ["RINGO_FIXED_PATH"] = "0"
+        try:
+            got3, _ = _convert_on(s2, d2)
+        finally:
+            os.environ.pop("RINGO_FIXED_PATH", None)
+        assert_same(got3, ref2, f"round {i}, pipeline: ")
+    assert replays >= 5
+
+
+def test_graph_cache_eviction(cuda, sort_numbering):
+    """More sizes than graphs kept: sizes come back after their graphs were
+    evicted; every result equals the oracle's."""
+    import torch
+    tables = [random_table(300 + k, 3000 + 997 * k, 2000 + 50 * k) for k in range(11)]
+    want = [oracle.table_to_graph(s, d) for s, d in tables]
+    dev_tabs = [(torch.from_numpy(s).to(cuda), torch.from_numpy(d).to(cuda)) for s, d in tables]
+    for r in range(3):
+        for k, (s, d) in enumerate(dev_tabs):
+            got, names = _convert_on(s, d)
+            assert names & SYNC_FREE
+            assert_same(got, want[k], f"round {r} table {k}: ")
