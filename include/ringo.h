@@ -327,11 +327,13 @@ int ringo_trace_read(ringo_trace_entry_t *out, int max_entries);
  * Served form: an interactive request loop that keeps built graphs resident
  * on the device (the paper's interactive-use goal, Sections 1 and 2.4).
  * Requests are host edge tables; worker threads, each with its own stream,
- * take every queued request that fits into one batch and convert it with
- * ringo_table_to_graph_batched, so batches started by different workers
- * overlap on the device.  A request is admitted only while the HBM budget
- * holds its estimated footprint on top of the resident graphs; the least
- * recently used resident graph is evicted when it does not.  Each result is
+ * take every queued request that fits into one batch and convert it as
+ * ringo_table_to_graph_batched does, so batches started by different workers
+ * overlap on the device.  Every graph of a batch holds device blocks of its
+ * own, in exact sizes, and counts against the budget by their bytes.  A
+ * request is admitted only while the HBM budget holds its estimated
+ * footprint on top of the resident graphs; the least recently used resident
+ * graph that is not pinned is evicted when it does not.  Each result is
  * bit-identical to ringo_table_to_graph on the same table.
  */
 typedef struct ringo_server ringo_server_t;
@@ -365,8 +367,30 @@ ringo_status_t ringo_server_submit(ringo_server_t *s, const int64_t *src, const 
 ringo_status_t ringo_server_poll(ringo_server_t *s, int64_t req_id, ringo_graph_t *out,
                                  double *latency_s);
 /* Frees a finished request and its resident graph; RINGO_ERR_PENDING while
- * it is still queued or running. */
+ * it is still queued or running, or pinned. */
 ringo_status_t ringo_server_release(ringo_server_t *s, int64_t req_id);
+/* A view as ringo_server_poll gives it (same results), pinned: the graph is
+ * not evicted until ringo_server_unpin.  A client that reads a view on its
+ * own stream pins it first and unpins it once that stream has finished the
+ * reads (an evicted graph's memory is freed in the order of the server's
+ * streams, not the client's).  Pins nest; RINGO_ERR_INVALID_ARG when unpin
+ * finds no pin. */
+ringo_status_t ringo_server_pin(ringo_server_t *s, int64_t req_id, ringo_graph_t *out);
+ringo_status_t ringo_server_unpin(ringo_server_t *s, int64_t req_id);
+/* Device times of finished batches (the latest max_entries of them, at most
+ * 65536 kept): events recorded on the batch's worker stream before its input
+ * copies and after its last kernel, in milliseconds since the server
+ * started.  Returns the number of entries written, or -1 (HIP error, bad
+ * argument).  Batches on different streams whose intervals intersect ran
+ * on the device at the same time. */
+typedef struct {
+  int64_t first_request; /* id of the batch's first request */
+  int64_t rows;          /* rows of its tables                */
+  int32_t stream;        /* worker (stream) index             */
+  int32_t tables;        /* requests in the batch             */
+  double start_ms, end_ms;
+} ringo_server_batch_t;
+int ringo_server_batches(ringo_server_t *s, ringo_server_batch_t *out, int max_entries);
 ringo_status_t ringo_server_stats(ringo_server_t *s, ringo_server_stats_t *out);
 /* Finishes the queued requests, frees every resident graph, joins the
  * workers.  NULL is a no-op. */

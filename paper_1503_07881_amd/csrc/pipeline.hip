@@ -84,10 +84,12 @@ void dev_free(const AllocHooks &h, void *p, hipStream_t s) {
   else (void)hipFreeAsync(p, s);
 }
 
-// Owner of the output arrays of one call (shared by the graphs of a batch).
+// Owner of output arrays: of one call (shared by the graphs of a batch), or
+// of one table when a batch gives every table blocks of its own.
 struct Owner {
   std::atomic<int> refs{0};
   void *blocks[3] = {nullptr, nullptr, nullptr};  // node-sized, edge-sized, small tables
+  size_t bytes = 0;  // device bytes of the blocks (as requested from the allocator)
   hipStream_t stream = nullptr;
   AllocHooks hooks;
 };
@@ -238,7 +240,6 @@ struct Call {
   // small tables converted in LDS (one workgroup each)
   std::vector<int> small;        // their indices in the call
   void *small_ws = nullptr;      // SmallTable array + V/E results
-  void *small_arena = nullptr;   // their outputs, until an Owner takes them
   Pinned *spin = nullptr;        // staging of the SmallTable array and the results
   std::vector<SmallTable> small_tabs;
   void *hmeta = nullptr;  // estimate registers, slot counts and flags of the hash tables
@@ -247,16 +248,56 @@ struct Call {
   size_t meta_bytes = 0;
   Pinned *pin = nullptr;
   int upload_slot = 0;
-  Owner *owner = nullptr;
+  // Output blocks, until the graphs take them: one Owner for the call, or
+  // (separate) one per table.
+  bool separate = false;
+  std::vector<Owner *> owners;
 
   ~Call() { release_workspace(); }
 
+  Owner *owner_for(int table) {
+    const size_t k = separate ? (size_t)table : 0;
+    if (owners.size() <= k) owners.resize(k + 1, nullptr);
+    if (!owners[k]) {
+      owners[k] = new Owner();
+      owners[k]->stream = stream;
+      owners[k]->hooks = hooks;
+    }
+    return owners[k];
+  }
+  // An output block of a table (slot 0 node-sized, 1 edge-sized, 2 small
+  // table), held by the table's Owner; null when the allocator refuses.
+  char *out_alloc(int table, int slot, size_t bytes) {
+    Owner *o = owner_for(table);
+    bytes = std::max<size_t>(bytes, 256);
+    void *p = dev_alloc(hooks, bytes, stream);
+    if (p) {
+      o->blocks[slot] = p;
+      o->bytes += bytes;
+    }
+    return (char *)p;
+  }
+  // The graphs of the call take their Owners (refs: graphs per Owner).
+  void hand_over(int S) {
+    for (Owner *o : owners)
+      if (o) o->refs.store(separate ? 1 : S);
+    owners.clear();
+  }
+  // Output blocks of a failed call.
+  void free_outputs() {
+    for (Owner *o : owners) {
+      if (!o) continue;
+      for (void *b : o->blocks) dev_free(hooks, b, stream);
+      delete o;
+    }
+    owners.clear();
+  }
+
   void release_workspace() {
     void *bufs[] = {A, B, base, results, meta, dir, tab, hslots, hmeta, counts,
-                    bsum, vals, small_ws, small_arena};
+                    bsum, vals, small_ws};
     for (void *b : bufs) dev_free(hooks, b, stream);
     small_ws = nullptr;
-    small_arena = nullptr;
     if (spin) pinned_release(spin, stream);
     spin = nullptr;
     tab = nullptr;
@@ -470,33 +511,48 @@ bool small_too_many_nodes(const Call &c) {
 }
 
 // Launches the small tables of a call (c.small): worst-case-sized outputs in
-// one arena, the SmallTable array uploaded through pinned memory, one
-// workgroup per table, and the V/E results copied back to pinned memory on
-// the same stream (read after the call's next synchronisation).
+// one block (or one per table when the call separates its outputs), the
+// SmallTable array uploaded through pinned memory, one workgroup per table,
+// and the V/E results copied back to pinned memory on the same stream (read
+// after the call's next synchronisation).
 ringo_status_t launch_small_part(Call &c, const int64_t *const *src, const int64_t *const *dst,
                                  const int64_t *num_rows) {
   const int K = (int)c.small.size();
   hipStream_t st = c.stream;
   size_t arena = 0;
-  std::vector<size_t> off((size_t)5 * K);
+  std::vector<size_t> off((size_t)5 * K), first(K), size(K);
   for (int k = 0; k < K; ++k) {
     const int64_t n = num_rows[c.small[k]];
     const size_t sz[5] = {sizeof(int64_t) * 2 * n, sizeof(int64_t) * (2 * n + 1),
                           sizeof(int64_t) * (2 * n + 1), sizeof(int32_t) * n, sizeof(int32_t) * n};
+    first[k] = arena;
     for (int f = 0; f < 5; ++f) {
       off[(size_t)5 * k + f] = arena;
       arena = align_up(arena + sz[f]);
     }
+    size[k] = arena - first[k];
   }
   const size_t tab_bytes = align_up(sizeof(SmallTable) * K);
-  c.small_arena = dev_alloc(c.hooks, arena, st);
+  // base[k]: the address that table k's offsets are relative to
+  std::vector<char *> base(K, nullptr);
+  if (c.separate) {
+    for (int k = 0; k < K; ++k) {
+      char *blk = c.out_alloc(c.small[k], 2, size[k]);
+      if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+      base[k] = blk - first[k];
+    }
+  } else {
+    char *blk = c.out_alloc(0, 2, arena);
+    if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+    for (int k = 0; k < K; ++k) base[k] = blk;
+  }
   c.small_ws = dev_alloc(c.hooks, tab_bytes + sizeof(int64_t) * 2 * K, st);
   c.spin = pinned_acquire(tab_bytes + sizeof(int64_t) * 2 * K);
-  if (!c.small_arena || !c.small_ws || !c.spin) return RINGO_ERR_OUT_OF_MEMORY;
-  char *a = (char *)c.small_arena;
+  if (!c.small_ws || !c.spin) return RINGO_ERR_OUT_OF_MEMORY;
   c.small_tabs.resize(K);
   for (int k = 0; k < K; ++k) {
     const int i = c.small[k];
+    char *a = base[k];
     SmallTable &T = c.small_tabs[k];
     T.src = src[i];
     T.dst = dst[i];
@@ -517,7 +573,7 @@ ringo_status_t launch_small_part(Call &c, const int64_t *const *src, const int64
 }
 
 // Fills the graphs of the small tables (after a synchronisation).
-void handoff_small(Call &c, const int64_t *num_rows, ringo_graph_t *outs, Owner *owner) {
+void handoff_small(Call &c, const int64_t *num_rows, ringo_graph_t *outs) {
   const int K = (int)c.small.size();
   const int64_t *vres = (const int64_t *)((char *)c.spin->p + align_up(sizeof(SmallTable) * K));
   for (int k = 0; k < K; ++k) {
@@ -533,10 +589,8 @@ void handoff_small(Call &c, const int64_t *num_rows, ringo_graph_t *outs, Owner 
     g.in_offsets = T.in_off;
     g.in_nbrs = T.in_nbr;
     g.kind = RINGO_GRAPH_DIRECTED;
-    g._alloc = owner;
+    g._alloc = c.owner_for(c.small[k]);
   }
-  owner->blocks[2] = c.small_arena;
-  c.small_arena = nullptr;  // now owned by the graphs
 }
 
 ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst,
@@ -564,11 +618,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     if ((int)c.small.size() == S) {  // nothing for the pipeline: one synchronisation
       HIP_TRY(hipStreamSynchronize(st));
       if (small_too_many_nodes(c)) return RINGO_ERR_TOO_MANY_NODES;
-      Owner *owner = new Owner();
-      owner->stream = st;
-      owner->hooks = c.hooks;
-      owner->refs.store(S);
-      handoff_small(c, num_rows, outs, owner);
+      handoff_small(c, num_rows, outs);
+      c.hand_over(S);
       return RINGO_OK;
     }
   }
@@ -745,21 +796,30 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   // key (bucketed: with its slot)
   trace_set_bytes(hcompact_rec, (bucket_place ? 16.0 : 8.0) * slots +
                                     (bucket_place ? 12.0 : 8.0) * sumV);
-  c.owner = new Owner();
-  c.owner->stream = st;
-  c.owner->hooks = c.hooks;
-  c.owner->blocks[0] = dev_alloc(c.hooks, arena1, st);
-  if (!c.owner->blocks[0]) return RINGO_ERR_OUT_OF_MEMORY;
+  // node-sized outputs: one block, or one per table (base1[i]: the address
+  // that table i's offsets are relative to)
+  std::vector<char *> base1(S, nullptr);
+  if (c.separate) {
+    for (int i = 0; i < S; ++i) {
+      const size_t end = i + 1 < S ? off1[3 * (i + 1)] : arena1;
+      char *blk = c.out_alloc(i, 0, end - off1[3 * i]);
+      if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+      base1[i] = blk - off1[3 * i];
+    }
+  } else {
+    char *blk = c.out_alloc(0, 0, arena1);
+    if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+    for (int i = 0; i < S; ++i) base1[i] = blk;
+  }
   if (!hashed) {
     c.dir = (DirEntry *)dev_alloc(c.hooks, sizeof(DirEntry) * std::max<int64_t>(dir_words, 1), st);
     if (!c.dir) return RINGO_ERR_OUT_OF_MEMORY;
   }
-  char *a1 = (char *)c.owner->blocks[0];
   for (int i = 0; i < S; ++i) {
     SegPlan &p = c.plan[i];
-    p.node_ids = (int64_t *)(a1 + off1[3 * i]);
-    p.out_off = (int64_t *)(a1 + off1[3 * i + 1]);
-    p.in_off = (int64_t *)(a1 + off1[3 * i + 2]);
+    p.node_ids = (int64_t *)(base1[i] + off1[3 * i]);
+    p.out_off = (int64_t *)(base1[i] + off1[3 * i + 1]);
+    p.in_off = (int64_t *)(base1[i] + off1[3 * i + 2]);
   }
   const int P_e = lsd_passes(2 * b_max, c.rb);
   const int P_in = lsd_passes(b_max, c.rb);
@@ -889,11 +949,22 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
   for (int i = 0; i < S; ++i) sumE += E[i];
   trace_set_bytes(dedupe_rec, 8.0 * NE + (multi ? 0.0 : 8.0 * sumE) + 8.0 * (sumV + S));
-  c.owner->blocks[1] = dev_alloc(c.hooks, arena2, st);
-  if (!c.owner->blocks[1]) return RINGO_ERR_OUT_OF_MEMORY;
-  char *a2 = (char *)c.owner->blocks[1];
+  std::vector<char *> base2(S, nullptr);
+  if (c.separate) {
+    for (int i = 0; i < S; ++i) {
+      const size_t end = i + 1 < S ? off2[(size_t)narr * (i + 1)] : arena2;
+      char *blk = c.out_alloc(i, 1, end - off2[(size_t)narr * i]);
+      if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+      base2[i] = blk - off2[(size_t)narr * i];
+    }
+  } else {
+    char *blk = c.out_alloc(0, 1, arena2);
+    if (!blk) return RINGO_ERR_OUT_OF_MEMORY;
+    for (int i = 0; i < S; ++i) base2[i] = blk;
+  }
   for (int i = 0; i < S; ++i) {
     SegPlan &p = c.plan[i];
+    char *a2 = base2[i];
     p.out_nbr = (int32_t *)(a2 + off2[(size_t)narr * i]);
     p.in_nbr = undirected ? p.out_nbr : (int32_t *)(a2 + off2[(size_t)narr * i + 1]);
     p.out_eid = multi ? (int32_t *)(a2 + off2[(size_t)narr * i + 2]) : nullptr;
@@ -945,7 +1016,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   }
 
   // ------------------------------------------------------------- handoff
-  c.owner->refs.store(S);
   for (int i = 0; i < S; ++i) {
     const SegPlan &p = c.plan[i];
     ringo_graph_t &g = outs[i];
@@ -957,13 +1027,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     g.out_nbrs = p.E > 0 ? p.out_nbr : nullptr;
     g.in_offsets = p.in_off;
     g.in_nbrs = p.E > 0 ? p.in_nbr : nullptr;
-    g._alloc = c.owner;
+    g._alloc = c.owner_for(i);
     g.kind = c.kind;
     g.out_eids = p.E > 0 ? p.out_eid : nullptr;
     g.in_eids = p.E > 0 ? p.in_eid : nullptr;
   }
-  if (!c.small.empty()) handoff_small(c, num_rows, outs, c.owner);
-  c.owner = nullptr;  // now owned by the graphs
+  if (!c.small.empty()) handoff_small(c, num_rows, outs);
+  c.hand_over(S);  // now owned by the graphs
   return RINGO_OK;
 }
 
@@ -1344,9 +1414,11 @@ ringo_status_t replay_fixed(GraphSlot &S, FixedGraph &g, const int64_t *src, con
 // The single-table call through the sync-free path: outputs sized for the
 // worst case in one block, the kept workspace and a graph replay when free
 // (else a workspace from the allocator and the kernels enqueued), one
-// synchronisation at the end to read V and E.
+// synchronisation at the end to read V and E.  With `exact`, the arrays are
+// then copied into a block of their exact sizes (for graphs that stay
+// resident) and the worst-case block is freed.
 ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, ringo_graph_t *out,
-                             hipStream_t st) {
+                             hipStream_t st, bool exact) {
   const AllocHooks h = hooks();
   const FixedLayout L = fixed_layout(n, digit_bits_for(n), items_for(n));
   size_t offs[5], arena = 0;
@@ -1397,12 +1469,40 @@ ringo_status_t convert_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
       E = ((const int64_t *)pin->p)[1];
       if (V > max_nodes()) rc = RINGO_ERR_TOO_MANY_NODES;
     }
+    size_t kept = std::max<size_t>(arena, 256);
+    if (rc == RINGO_OK && exact) {
+      // the graph's arrays into a block of their exact sizes
+      const size_t esz[5] = {sizeof(int64_t) * V, sizeof(int64_t) * (V + 1), sizeof(int32_t) * E,
+                             sizeof(int64_t) * (V + 1), sizeof(int32_t) * E};
+      void *const from[5] = {o.node_ids, o.out_off, o.out_nbr, o.in_off, o.in_nbr};
+      size_t eoff[5], ebytes = 0;
+      for (int f = 0; f < 5; ++f) {
+        eoff[f] = ebytes;
+        ebytes = align_up(ebytes + esz[f]);
+      }
+      char *eb = (char *)dev_alloc(h, ebytes, st);
+      if (!eb) rc = RINGO_ERR_OUT_OF_MEMORY;
+      for (int f = 0; f < 5 && rc == RINGO_OK; ++f)
+        if (esz[f] > 0 &&
+            hipMemcpyAsync(eb + eoff[f], from[f], esz[f], hipMemcpyDeviceToDevice, st) != hipSuccess)
+          rc = RINGO_ERR_HIP;
+      if (rc == RINGO_OK) {
+        dev_free(h, blk, st);
+        blk = eb;
+        kept = std::max<size_t>(ebytes, 256);
+        o = FixedOut{(int64_t *)(eb + eoff[0]), (int64_t *)(eb + eoff[1]), (int32_t *)(eb + eoff[2]),
+                     (int64_t *)(eb + eoff[3]), (int32_t *)(eb + eoff[4])};
+      } else {
+        dev_free(h, eb, st);
+      }
+    }
     if (rc == RINGO_OK) {
       std::memset(out, 0, sizeof(*out));
       Owner *owner = new Owner();
       owner->stream = st;
       owner->hooks = h;
       owner->blocks[0] = blk;
+      owner->bytes = kept;
       owner->refs.store(1);
       out->num_rows = n;
       out->num_nodes = V;
@@ -1519,7 +1619,7 @@ ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits,
 
 ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *const *dst,
                        const int64_t *num_rows, int32_t kind, ringo_graph_t *outs,
-                       hipStream_t stream) {
+                       hipStream_t stream, bool separate = false) {
   if (S < 0 || (S > 0 && (!src || !dst || !num_rows || !outs))) return RINGO_ERR_INVALID_ARG;
   if (kind != RINGO_GRAPH_DIRECTED && kind != RINGO_GRAPH_UNDIRECTED && kind != RINGO_GRAPH_MULTI)
     return RINGO_ERR_INVALID_ARG;
@@ -1532,7 +1632,7 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
   (void)hipGetLastError();
   prepare_pool();
   if (fixed_path_for(S, kind, num_rows[0])) {
-    const ringo_status_t rc = convert_fixed(src[0], dst[0], num_rows[0], &outs[0], stream);
+    const ringo_status_t rc = convert_fixed(src[0], dst[0], num_rows[0], &outs[0], stream, separate);
     if (rc != RINGO_OK) std::memset(&outs[0], 0, sizeof(ringo_graph_t));
     return rc;
   }
@@ -1541,16 +1641,13 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
   c.kind = kind;
   c.stream = stream;
   c.hooks = hooks();
+  c.separate = separate;
   ringo_status_t rc = run(c, src, dst, num_rows, outs);
   if (rc != RINGO_OK) {
     // drain what was enqueued before releasing anything it may touch
     (void)hipStreamSynchronize(stream);
     (void)hipGetLastError();
-    if (c.owner) {
-      for (void *b : c.owner->blocks) dev_free(c.hooks, b, stream);
-      delete c.owner;
-      c.owner = nullptr;
-    }
+    c.free_outputs();
     for (int i = 0; i < S; ++i) std::memset(&outs[i], 0, sizeof(ringo_graph_t));
   }
   c.release_workspace();
@@ -1558,6 +1655,20 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
 }
 
 }  // namespace
+
+namespace ringo {
+
+ringo_status_t convert_separate(int32_t S, const int64_t *const *src, const int64_t *const *dst,
+                                const int64_t *num_rows, ringo_graph_t *outs, hipStream_t stream) {
+  return convert(S, src, dst, num_rows, RINGO_GRAPH_DIRECTED, outs, stream, true);
+}
+
+size_t graph_bytes(const ringo_graph_t *g) {
+  const Owner *o = g ? (const Owner *)g->_alloc : nullptr;
+  return o ? o->bytes : 0;
+}
+
+}  // namespace ringo
 
 extern "C" {
 

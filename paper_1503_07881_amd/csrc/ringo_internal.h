@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ringo.h"
+
 namespace ringo {
 
 // Radix digits of the LSD passes: 8 to 11 bits, chosen per table size by
@@ -276,6 +278,15 @@ struct SmallTable {
 // Converts count small tables (directed kind), one workgroup each; V and E
 // of table i go to vres[2i] and vres[2i + 1].
 hipError_t launch_small(const SmallTable *tabs, int count, int64_t *vres, hipStream_t s);
+
+// The batched conversion (directed) with every table's outputs in device
+// blocks of its own, so that its graphs are freed one by one (the served
+// form), and the device bytes that a graph's outputs hold: the blocks of
+// its owner (all tables' blocks when a batch shares them), as requested from
+// the allocator; 0 for a graph that owns nothing.
+ringo_status_t convert_separate(int32_t S, const int64_t *const *src, const int64_t *const *dst,
+                                const int64_t *num_rows, ringo_graph_t *outs, hipStream_t stream);
+size_t graph_bytes(const ringo_graph_t *g);
 
 // Stream-ordered device memory from the library's allocator (the caller's
 // hooks when set, else the device pool); used by the entry points other than

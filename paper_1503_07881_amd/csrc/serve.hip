@@ -13,9 +13,14 @@
 //     their work overlaps on the device (continuous batching);
 //   * admits a request only while the HBM budget holds its estimated
 //     footprint (input, workspace, outputs) on top of the resident graphs,
-//     evicting the least recently used resident graph when it does not;
+//     evicting the least recently used resident graph that no client holds
+//     pinned when it does not;
+//   * gives every graph of a batch output blocks of its own and counts a
+//     resident graph by the bytes those blocks hold, so that evicting a
+//     graph frees what it is counted for;
 //   * records each request's latency from submission to its graph being
-//     resident (the host-to-device copy of its input included).
+//     resident (the host-to-device copy of its input included), and each
+//     batch's device start and end (events on its stream).
 // A request's result is bit-identical to a lone ringo_table_to_graph call:
 // every table of a batch is converted independently.
 
@@ -31,6 +36,7 @@
 #include <vector>
 
 #include "ringo.h"
+#include "ringo_internal.h"
 
 namespace {
 
@@ -49,26 +55,36 @@ struct Request {
   ringo_graph_t graph{};
   int64_t reserve = 0;    // bytes held against the budget
   uint64_t last_use = 0;  // LRU clock
+  int pins = 0;           // client reads in flight: not evictable while > 0
+};
+
+// One batch's device work: events on its worker stream before its input
+// copy and after its last kernel.
+struct BatchRec {
+  hipEvent_t start = nullptr, end = nullptr;
+  int32_t stream = 0, tables = 0;
+  int64_t rows = 0, first_request = 0;
 };
 
 // Bytes a request may need while it is converted: its input columns, the
-// workspace (two key buffers of 2n keys, slot indices or directory, per-tile
-// digit counts of the schedule's tiles and digit width) and an upper bound
-// of its outputs (V <= 2n nodes, E <= n edges).
+// workspace (two key buffers of 2n keys, slot indices or the directory of up
+// to 2^ceil(log2 2n) entries, per-tile digit counts of the schedule's tiles
+// and digit width) and its outputs at their upper bound (V <= 2n nodes,
+// E <= n edges) twice: a table converted into worst-case arrays is copied
+// into arrays of its exact sizes before those are freed.
 int64_t footprint(int64_t n) {
   const int64_t input = 16 * n;
   ringo_schedule_t sc;
   if (ringo_tune_get(n, &sc) != RINGO_OK) sc.digit_bits = 11, sc.items_per_thread = 8;
   const int64_t tiles = 2 * n / (256 * sc.items_per_thread) + 2;
   const int64_t counts = 4 * tiles * ((int64_t)1 << sc.digit_bits);
-  const int64_t workspace = 32 * n + 8 * n + counts + (int64_t)(1 << 20);
+  const int64_t workspace = 32 * n + 64 * n + counts + (int64_t)(1 << 20);
   const int64_t outputs = 8 * (2 * n) + 16 * (2 * n + 1) + 8 * n;
-  return input + workspace + outputs;
+  return input + workspace + 2 * outputs;
 }
 
-int64_t resident_bytes(const ringo_graph_t &g) {
-  return 8 * g.num_nodes + 16 * (g.num_nodes + 1) + 8 * g.num_edges;
-}
+// Batches whose device times are kept (the latest ones).
+constexpr size_t MAX_BATCH_RECS = 1 << 16;
 
 }  // namespace
 
@@ -87,15 +103,20 @@ struct ringo_server {
   std::vector<hipStream_t> streams;  // one per worker; resident graphs free on them
   ringo_server_stats_t stats{};
   int running_batches = 0;
+  hipEvent_t t0 = nullptr;  // device time origin of the batch records
+  std::vector<BatchRec> batch_recs;
+  std::vector<BatchRec> done_recs;  // events of dropped records, freed at the end
 
-  // Evicts least recently used resident graphs until `need` more bytes fit
-  // in the budget.  Returns whether they fit.  Caller holds mu.
+  // Evicts least recently used resident graphs that no client has pinned
+  // until `need` more bytes fit in the budget.  Returns whether they fit.
+  // Caller holds mu.
   bool make_room(int64_t need) {
     while (reserved + need > cfg.budget_bytes) {
       Request *victim = nullptr;
       for (auto &kv : reqs) {
         Request &r = kv.second;
-        if (r.state == RS_READY && (!victim || r.last_use < victim->last_use)) victim = &r;
+        if (r.state == RS_READY && r.pins == 0 && (!victim || r.last_use < victim->last_use))
+          victim = &r;
       }
       if (!victim) return false;
       ringo_graph_free(&victim->graph);
@@ -149,7 +170,7 @@ struct ringo_server {
             std::max<int64_t>(stats.max_concurrent_batches, running_batches);
         stats.peak_reserved_bytes = std::max<int64_t>(stats.peak_reserved_bytes, reserved);
       }
-      run_batch(batch, stream);
+      run_batch(batch, stream, index);
       {
         std::lock_guard<std::mutex> lk(mu);
         running_batches -= 1;
@@ -158,7 +179,7 @@ struct ringo_server {
     }
   }
 
-  void run_batch(const std::vector<int64_t> &ids, hipStream_t stream) {
+  void run_batch(const std::vector<int64_t> &ids, hipStream_t stream, int index) {
     const size_t k = ids.size();
     std::vector<const int64_t *> hsrc(k), hdst(k);
     std::vector<int64_t> n(k), off(k + 1, 0);
@@ -175,6 +196,18 @@ struct ringo_server {
     ringo_status_t rc = RINGO_OK;
     int64_t *dev = nullptr;
     const int64_t total = off[k];
+    BatchRec rec;
+    rec.stream = index;
+    rec.tables = (int32_t)k;
+    rec.rows = total;
+    rec.first_request = ids.empty() ? 0 : ids[0];
+    if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.end) != hipSuccess ||
+        hipEventRecord(rec.start, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      if (rec.start) (void)hipEventDestroy(rec.start);
+      if (rec.end) (void)hipEventDestroy(rec.end);
+      rec.start = rec.end = nullptr;
+    }
     if (hipMallocAsync((void **)&dev, (size_t)std::max<int64_t>(16 * total, 256), stream) !=
         hipSuccess) {
       (void)hipGetLastError();
@@ -194,9 +227,14 @@ struct ringo_server {
           rc = RINGO_ERR_HIP;
       }
     }
+    // every graph in blocks of its own: evicting one frees what it is counted for
     if (rc == RINGO_OK)
-      rc = ringo_table_to_graph_batched((int32_t)k, dsrc.data(), ddst.data(), n.data(), outs.data(),
-                                        stream);
+      rc = ringo::convert_separate((int32_t)k, dsrc.data(), ddst.data(), n.data(), outs.data(),
+                                   stream);
+    if (rc == RINGO_OK && rec.end && hipEventRecord(rec.end, stream) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = RINGO_ERR_HIP;
+    }
     if (rc == RINGO_OK && hipStreamSynchronize(stream) != hipSuccess) rc = RINGO_ERR_HIP;
     if (dev) (void)hipFreeAsync(dev, stream);
     if (rc != RINGO_OK) {
@@ -211,7 +249,7 @@ struct ringo_server {
       reserved -= r.reserve;
       if (rc == RINGO_OK) {
         r.graph = outs[i];
-        r.reserve = resident_bytes(outs[i]);
+        r.reserve = (int64_t)ringo::graph_bytes(&outs[i]);
         reserved += r.reserve;
         r.state = RS_READY;
         r.last_use = ++clock;
@@ -225,6 +263,17 @@ struct ringo_server {
       }
     }
     stats.resident_bytes = reserved;
+    if (rec.start && rec.end) {
+      if (rc == RINGO_OK) {
+        if (batch_recs.size() >= MAX_BATCH_RECS) {
+          done_recs.push_back(batch_recs.front());
+          batch_recs.erase(batch_recs.begin());
+        }
+        batch_recs.push_back(rec);
+      } else {
+        done_recs.push_back(rec);
+      }
+    }
   }
 };
 
@@ -250,6 +299,12 @@ ringo_status_t ringo_server_create(const ringo_server_config_t *cfg, ringo_serve
       return RINGO_ERR_HIP;
     }
     s->streams.push_back(st);
+  }
+  if (hipEventCreate(&s->t0) != hipSuccess || hipEventRecord(s->t0, s->streams[0]) != hipSuccess ||
+      hipEventSynchronize(s->t0) != hipSuccess) {
+    (void)hipGetLastError();
+    if (s->t0) (void)hipEventDestroy(s->t0);
+    s->t0 = nullptr;
   }
   for (int i = 0; i < cfg->num_streams; ++i)
     s->workers.emplace_back([s, i] { s->worker_main(i); });
@@ -311,7 +366,7 @@ ringo_status_t ringo_server_release(ringo_server_t *s, int64_t req_id) {
   auto it = s->reqs.find(req_id);
   if (it == s->reqs.end()) return RINGO_ERR_INVALID_ARG;
   Request &r = it->second;
-  if (r.state == RS_QUEUED || r.state == RS_RUNNING) return RINGO_ERR_PENDING;
+  if (r.state == RS_QUEUED || r.state == RS_RUNNING || r.pins > 0) return RINGO_ERR_PENDING;
   if (r.state == RS_READY) {
     ringo_graph_free(&r.graph);
     s->reserved -= r.reserve;
@@ -319,6 +374,70 @@ ringo_status_t ringo_server_release(ringo_server_t *s, int64_t req_id) {
   }
   s->reqs.erase(it);
   return RINGO_OK;
+}
+
+ringo_status_t ringo_server_pin(ringo_server_t *s, int64_t req_id, ringo_graph_t *out) {
+  if (!s) return RINGO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req_id);
+  if (it == s->reqs.end()) return RINGO_ERR_INVALID_ARG;
+  Request &r = it->second;
+  switch (r.state) {
+    case RS_QUEUED:
+    case RS_RUNNING: return RINGO_ERR_PENDING;
+    case RS_EVICTED: return RINGO_ERR_EVICTED;
+    case RS_RELEASED: return RINGO_ERR_INVALID_ARG;
+    case RS_FAILED: return r.status;
+    case RS_READY:
+      r.pins += 1;
+      r.last_use = ++s->clock;
+      if (out) {
+        *out = r.graph;
+        out->_alloc = nullptr;
+      }
+      return RINGO_OK;
+  }
+  return RINGO_ERR_INVALID_ARG;
+}
+
+ringo_status_t ringo_server_unpin(ringo_server_t *s, int64_t req_id) {
+  if (!s) return RINGO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req_id);
+  if (it == s->reqs.end() || it->second.pins <= 0) return RINGO_ERR_INVALID_ARG;
+  it->second.pins -= 1;
+  return RINGO_OK;
+}
+
+int ringo_server_batches(ringo_server_t *s, ringo_server_batch_t *out, int max_entries) {
+  if (!s || max_entries < 0 || (max_entries > 0 && !out)) return -1;
+  std::vector<BatchRec> recs;
+  hipEvent_t t0 = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    recs = s->batch_recs;
+    t0 = s->t0;
+  }
+  if (!t0) return -1;
+  const size_t first = recs.size() > (size_t)max_entries ? recs.size() - (size_t)max_entries : 0;
+  int n = 0;
+  for (size_t i = first; i < recs.size(); ++i) {
+    const BatchRec &r = recs[i];
+    float a = 0, b = 0;
+    if (hipEventSynchronize(r.end) != hipSuccess || hipEventElapsedTime(&a, t0, r.start) != hipSuccess ||
+        hipEventElapsedTime(&b, t0, r.end) != hipSuccess) {
+      (void)hipGetLastError();
+      return -1;
+    }
+    ringo_server_batch_t &o = out[n++];
+    o.first_request = r.first_request;
+    o.rows = r.rows;
+    o.stream = r.stream;
+    o.tables = r.tables;
+    o.start_ms = a;
+    o.end_ms = b;
+  }
+  return n;
 }
 
 ringo_status_t ringo_server_stats(ringo_server_t *s, ringo_server_stats_t *out) {
@@ -345,6 +464,12 @@ void ringo_server_destroy(ringo_server_t *s) {
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
   }
+  for (auto *v : {&s->batch_recs, &s->done_recs})
+    for (BatchRec &r : *v) {
+      (void)hipEventDestroy(r.start);
+      (void)hipEventDestroy(r.end);
+    }
+  if (s->t0) (void)hipEventDestroy(s->t0);
   delete s;
 }
 

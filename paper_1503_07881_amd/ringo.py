@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "ringo_server_stats", "ringo_server_destroy",
     "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
     "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex", "ringo_sort_keys",
-    "ringo_table_to_graph_noalloc",
+    "ringo_table_to_graph_noalloc", "ringo_server_pin", "ringo_server_unpin", "ringo_server_batches",
 )
 
 NOALLOC_MAX_ROWS = 1 << 20

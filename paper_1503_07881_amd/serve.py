@@ -22,6 +22,12 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_tables", ctypes.c_int32), ("max_batch_rows", ctypes.c_int64)]
 
 
+class BatchTimes(ctypes.Structure):
+    """ringo_server_batch_t"""
+    _fields_ = [("first_request", ctypes.c_int64), ("rows", ctypes.c_int64), ("stream", ctypes.c_int32),
+                ("tables", ctypes.c_int32), ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
+
+
 class ServerStats(ctypes.Structure):
     """ringo_server_stats_t"""
     _fields_ = [(n, ctypes.c_int64) for n in
@@ -45,6 +51,12 @@ def _lib():
         L.ringo_server_poll.restype = ctypes.c_int
         L.ringo_server_release.argtypes = [p, i64]
         L.ringo_server_release.restype = ctypes.c_int
+        L.ringo_server_pin.argtypes = [p, i64, ctypes.POINTER(ringo.RawGraph)]
+        L.ringo_server_pin.restype = ctypes.c_int
+        L.ringo_server_unpin.argtypes = [p, i64]
+        L.ringo_server_unpin.restype = ctypes.c_int
+        L.ringo_server_batches.argtypes = [p, ctypes.POINTER(BatchTimes), ctypes.c_int]
+        L.ringo_server_batches.restype = ctypes.c_int
         L.ringo_server_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
         L.ringo_server_stats.restype = ctypes.c_int
         L.ringo_server_destroy.argtypes = [p]
@@ -97,16 +109,40 @@ class Server:
                 raise TimeoutError(f"request {req_id} still pending after {timeout_s} s")
             time.sleep(0.0002)
 
+    def pin(self, req_id: int):
+        """(status, RawGraph view or None): the graph is not evicted until unpin."""
+        g = ringo.RawGraph()
+        rc = _lib().ringo_server_pin(self._h, req_id, ctypes.byref(g))
+        return rc, (g if rc == 0 else None)
+
+    def unpin(self, req_id: int) -> int:
+        return _lib().ringo_server_unpin(self._h, req_id)
+
     def graph(self, req_id: int, device) -> ringo.Graph:
-        """Tensor copies of a resident graph (the view stays owned by the server)."""
+        """Tensor copies of a resident graph: the view is pinned while the
+        copies are made on the current stream, and unpinned once that stream
+        has finished them (the view stays owned by the server)."""
         import torch
-        rc, g, _ = self.poll(req_id)
+        rc, g = self.pin(req_id)
         if rc != 0:
-            raise ringo.RingoError(rc, "ringo_server_poll")
-        out = ringo.view_graph(g, device)
-        return ringo.Graph(out.num_rows, out.num_nodes, out.num_edges,
-                           *(torch.clone(getattr(out, f)) for f in
-                             ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs")))
+            raise ringo.RingoError(rc, "ringo_server_pin")
+        try:
+            out = ringo.view_graph(g, device)
+            copy = ringo.Graph(out.num_rows, out.num_nodes, out.num_edges,
+                               *(torch.clone(getattr(out, f)) for f in
+                                 ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs")))
+            torch.cuda.current_stream(device).synchronize()
+        finally:
+            self.unpin(req_id)
+        return copy
+
+    def batches(self, max_entries: int = 1 << 16) -> list[dict]:
+        """Device start/end (ms since the server started) of finished batches."""
+        buf = (BatchTimes * max_entries)()
+        k = _lib().ringo_server_batches(self._h, buf, max_entries)
+        if k < 0:
+            raise ringo.RingoError(4, "ringo_server_batches")
+        return [{f: getattr(buf[i], f) for f, _ in BatchTimes._fields_} for i in range(k)]
 
     def release(self, req_id: int) -> int:
         self._inputs.pop(req_id, None)
@@ -150,10 +186,37 @@ class TraceResult:
                 "max_concurrent_batches": self.stats.get("max_concurrent_batches")}
 
 
+def device_overlap(batches: list[dict]) -> dict:
+    """From batch device intervals: the time with at least one batch on the
+    device, the part of it with two or more (on different streams), and the
+    most batches at once."""
+    ev = []
+    for b in batches:
+        ev.append((b["start_ms"], 1))
+        ev.append((b["end_ms"], -1))
+    ev.sort()
+    busy = multi = 0.0
+    cur = peak = 0
+    last = None
+    for t, d in ev:
+        if last is not None:
+            if cur >= 1:
+                busy += t - last
+            if cur >= 2:
+                multi += t - last
+        cur += d
+        peak = max(peak, cur)
+        last = t
+    return {"device_busy_ms": busy, "device_overlap_ms": multi,
+            "overlap_frac": multi / busy if busy > 0 else 0.0, "max_batches_at_once": peak}
+
+
 def replay(server: Server, tables, arrivals_s, warmup: int = 0, release: bool = True) -> TraceResult:
     """Submits tables[i] at arrivals_s[i] (seconds from start), waits for all
     of them, and returns the latencies of the requests after the first
-    `warmup` ones.  With release, each graph is released once measured."""
+    `warmup` ones.  With release, each graph is released once measured;
+    without, graphs stay resident and the budget evicts the least recently
+    used ones."""
     ids = []
     t0 = time.perf_counter()
     for (src, dst), at in zip(tables, arrivals_s):
@@ -169,12 +232,12 @@ def replay(server: Server, tables, arrivals_s, warmup: int = 0, release: bool = 
     for i, rid in enumerate(ids):
         rc, g, l = server.wait(rid)
         if i >= warmup:
-            if rc == 0:
+            # a graph evicted before this poll was converted all the same
+            if rc in (0, ringo.STATUS_EVICTED) and l is not None:
                 lat.append(l)
-                rows += int(g.num_rows)
+                rows += int(tables[i][0].size)
                 t_last = max(t_last, t0 + arrivals_s[i] + l)
-            elif rc == ringo.STATUS_EVICTED:
-                evicted += 1
+                evicted += rc == ringo.STATUS_EVICTED
             else:
                 failed += 1
         if release:

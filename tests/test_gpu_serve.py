@@ -69,10 +69,15 @@ def test_poisson_replay_overlaps(cuda):
     say("serve: 60 requests at 2000/s, 2 workers")
     with serve.Server(budget_bytes=64 << 30, num_streams=2, max_batch_tables=8) as srv:
         res = serve.replay(srv, tables, arrivals, warmup=5)
+        ov = serve.device_overlap(srv.batches())
     s = res.summary()
     say("serve:", s)
+    say("serve: device overlap", ov)
     assert s["requests"] == 55 and s["failed"] == 0
-    assert res.stats["max_concurrent_batches"] == 2  # batches overlapped on the device
+    assert res.stats["max_concurrent_batches"] == 2  # two batches admitted at once
+    # and their device work overlapped: intervals between events recorded on
+    # the two worker streams intersect
+    assert ov["max_batches_at_once"] == 2 and ov["device_overlap_ms"] > 0
     assert s["p99_ms"] >= s["p50_ms"] > 0
 
 
@@ -96,3 +101,60 @@ def test_budget_evicts_lru_and_rejects_oversized(cuda):
         rid = srv.submit(*big)
         rc, _, _ = srv.wait(rid)
         assert rc == 3  # RINGO_ERR_OUT_OF_MEMORY: its footprint exceeds the whole budget
+
+
+@pytest.mark.gpu
+def test_batched_budget_frees_what_it_counts(cuda):
+    """Batches of up to 6 requests under a budget that binds: every graph
+    holds blocks of its own, so once the server is idle the bytes it counts
+    as resident are exactly the live blocks a caller's allocator handed out;
+    evictions happened; a graph pinned all along was never evicted, and its
+    view, read on the client's stream while other graphs were evicted,
+    equals the oracle's graph."""
+    import torch
+    from test_gpu_alloc import CountingAllocator
+    specs = [workloads.mixed_table(60, i, 3_000, 150_000) for i in range(40)]
+    tables = pinned_tables(specs)
+    al = CountingAllocator(cuda)
+    al.install()
+    try:
+        with serve.Server(budget_bytes=80 << 20, num_streams=2, max_batch_tables=6,
+                          max_batch_rows=400_000) as srv:
+            first = srv.submit(*tables[0])
+            assert srv.wait(first)[0] == 0
+            rc, view = srv.pin(first)
+            assert rc == 0
+            say("serve: 39 more requests under an 80 MB budget, first graph pinned")
+            ids = [first] + [srv.submit(s, d) for s, d in tables[1:]]
+            for rid in ids:
+                rc, _, _ = srv.wait(rid)
+                assert rc in (0, ringo.STATUS_EVICTED), rc
+            # the pinned view, read on the client's stream
+            g = ringo.view_graph(view, cuda)
+            got = {f: getattr(g, f).cpu().numpy() for f in ("node_ids", "out_offsets", "out_nbrs",
+                                                            "in_offsets", "in_nbrs")}
+            torch.cuda.synchronize()
+            assert_same(got, oracle.table_to_graph(*tables[0]), "pinned graph: ")
+            assert srv.poll(first)[0] == 0, "a pinned graph was evicted"
+            st = srv.stats()
+            states = [srv.poll(r)[0] for r in ids]
+            say("serve: stats", st, "evicted", states.count(ringo.STATUS_EVICTED))
+            assert st["completed"] == 40 and st["failed"] == 0
+            assert st["evicted"] >= 1 and states.count(ringo.STATUS_EVICTED) == st["evicted"]
+            assert st["resident_bytes"] <= 80 << 20
+            torch.cuda.synchronize()
+            live = sum(al.live.values())
+            assert st["resident_bytes"] == live, (st["resident_bytes"], live)
+            assert srv.release(first) == ringo.STATUS_PENDING  # still pinned
+            assert srv.unpin(first) == 0
+            assert srv.unpin(first) == 1  # no pin left
+            # resident graphs read back correctly after the evictions
+            for i, rid in enumerate(ids):
+                if states[i] == 0 and i % 5 == 0:
+                    assert_same(srv.graph(rid, cuda), oracle.table_to_graph(*tables[i]), f"request {i}: ")
+            for rid in ids:
+                srv.release(rid)
+            assert srv.stats()["resident_bytes"] == 0
+    finally:
+        assert ringo.lib().ringo_set_allocator(None, None, None) == 0
+    assert not al.live, "blocks left after the server released every graph"
