@@ -1668,6 +1668,14 @@ size_t graph_bytes(const ringo_graph_t *g) {
   return o ? o->bytes : 0;
 }
 
+void graph_free_on(ringo_graph_t *g, hipStream_t stream) {
+  if (!g) return;
+  Owner *o = (Owner *)g->_alloc;
+  if (o) o->stream = stream;
+  owner_release(o);
+  std::memset(g, 0, sizeof(*g));
+}
+
 }  // namespace ringo
 
 extern "C" {

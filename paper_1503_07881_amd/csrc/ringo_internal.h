@@ -287,6 +287,11 @@ hipError_t launch_small(const SmallTable *tabs, int count, int64_t *vres, hipStr
 ringo_status_t convert_separate(int32_t S, const int64_t *const *src, const int64_t *const *dst,
                                 const int64_t *num_rows, ringo_graph_t *outs, hipStream_t stream);
 size_t graph_bytes(const ringo_graph_t *g);
+// ringo_graph_free with the release ordered on `stream` instead of the
+// stream that built the graph (whose later work the arrays no longer need),
+// so that allocations on `stream` can reuse the memory at once.  Only for a
+// graph that no enqueued work reads any more.
+void graph_free_on(ringo_graph_t *g, hipStream_t stream);
 
 // Stream-ordered device memory from the library's allocator (the caller's
 // hooks when set, else the device pool); used by the entry points other than

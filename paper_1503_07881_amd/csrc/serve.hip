@@ -67,20 +67,21 @@ struct BatchRec {
 };
 
 // Bytes a request may need while it is converted: its input columns, the
-// workspace (two key buffers of 2n keys, slot indices or the directory of up
-// to 2^ceil(log2 2n) entries, per-tile digit counts of the schedule's tiles
-// and digit width) and its outputs at their upper bound (V <= 2n nodes,
-// E <= n edges) twice: a table converted into worst-case arrays is copied
-// into arrays of its exact sizes before those are freed.
+// workspace (two key buffers of 2n keys, slot indices, per-tile digit counts
+// of the schedule's tiles and digit width) and its outputs at their upper
+// bound (V <= 2n nodes, E <= n edges).  A table of at most 2^20 rows also
+// holds its node directory (up to 2^ceil(log2 n) entries) and, once
+// converted into worst-case arrays, the copy in exact sizes.
 int64_t footprint(int64_t n) {
   const int64_t input = 16 * n;
   ringo_schedule_t sc;
   if (ringo_tune_get(n, &sc) != RINGO_OK) sc.digit_bits = 11, sc.items_per_thread = 8;
   const int64_t tiles = 2 * n / (256 * sc.items_per_thread) + 2;
   const int64_t counts = 4 * tiles * ((int64_t)1 << sc.digit_bits);
-  const int64_t workspace = 32 * n + 64 * n + counts + (int64_t)(1 << 20);
+  const int64_t workspace = 32 * n + 8 * n + counts + (int64_t)(1 << 20);
   const int64_t outputs = 8 * (2 * n) + 16 * (2 * n + 1) + 8 * n;
-  return input + workspace + 2 * outputs;
+  const int64_t small_extra = n <= ((int64_t)1 << 20) ? 32 * n + outputs : 0;
+  return input + workspace + outputs + small_extra;
 }
 
 // Batches whose device times are kept (the latest ones).
@@ -109,8 +110,11 @@ struct ringo_server {
 
   // Evicts least recently used resident graphs that no client has pinned
   // until `need` more bytes fit in the budget.  Returns whether they fit.
+  // An evicted graph's memory is released in the order of `stream`, the
+  // admitting worker's, so that its next allocations reuse the memory at
+  // once (the stream that built the graph may be busy with another batch).
   // Caller holds mu.
-  bool make_room(int64_t need) {
+  bool make_room(int64_t need, hipStream_t stream) {
     while (reserved + need > cfg.budget_bytes) {
       Request *victim = nullptr;
       for (auto &kv : reqs) {
@@ -119,7 +123,7 @@ struct ringo_server {
           victim = &r;
       }
       if (!victim) return false;
-      ringo_graph_free(&victim->graph);
+      ringo::graph_free_on(&victim->graph, stream);
       reserved -= victim->reserve;
       victim->reserve = 0;
       victim->state = RS_EVICTED;
@@ -151,7 +155,7 @@ struct ringo_server {
             stats.failed += 1;
             continue;
           }
-          if (!make_room(need)) break;  // wait for running batches to finish
+          if (!make_room(need, stream)) break;  // wait for running batches to finish
           queue.pop_front();
           reserved += need;
           r.reserve = need;
