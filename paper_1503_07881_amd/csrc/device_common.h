@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ringo_internal.h"
+
 namespace ringo {
 
 // --------------------------------------------------------------- helpers
@@ -60,6 +62,36 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
   total = tot;
   __syncthreads();
   return off + inc - v;
+}
+
+// Writes `len` units of value (w0) or (w0, w1) from dst on: by this lane
+// when the run is short, else queued in chunks for launch_gap_fill (chunks
+// beyond the queue's capacity, which its bound never reaches, are written
+// here as well).
+__device__ __forceinline__ void fill_run(const GapQueue &q, uint64_t *dst, int64_t len,
+                                         uint64_t w0, uint64_t w1, int words) {
+  if (len <= 0) return;
+  int64_t from = 0;  // first unit this lane writes itself
+  if (len > GAP_INLINE && q.e) {
+    const int64_t chunks = (len + GAP_CHUNK - 1) / GAP_CHUNK;
+    const uint64_t at = atomicAdd(q.count, (uint32_t)chunks);
+    const int64_t queued = at >= q.cap ? 0 : std::min<int64_t>(chunks, (int64_t)q.cap - (int64_t)at);
+    for (int64_t c = 0; c < queued; ++c) {
+      GapEntry g;
+      g.dst = dst + c * GAP_CHUNK * words;
+      g.len = std::min<int64_t>(GAP_CHUNK, len - c * GAP_CHUNK);
+      g.w0 = w0;
+      g.w1 = w1;
+      g.words = words;
+      q.e[at + c] = g;
+    }
+    from = std::min<int64_t>(len, queued * GAP_CHUNK);
+  }
+  __attribute__((address_space(1))) uint64_t *p = G(dst);
+  for (int64_t u = from; u < len; ++u) {
+    p[u * words] = w0;
+    if (words == 2) p[u * words + 1] = w1;
+  }
 }
 
 }  // namespace ringo

@@ -61,6 +61,34 @@ __global__ void k_empty_offsets(const SegPlan *plan, int32_t S) {
   }
 }
 
+// The runs queued by fill_run: one block per chunk of up to GAP_CHUNK units,
+// grid-stride over the chunks (their count is read on the device).
+__global__ __launch_bounds__(256) void k_gap_fill(const GapEntry *e, const uint32_t *count,
+                                                  uint32_t cap) {
+  const uint32_t n = std::min(*count, cap);
+  for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const GapEntry g = e[i];
+    if (g.words == 2) {
+      __attribute__((address_space(1))) u64x2 *p = (__attribute__((address_space(1))) u64x2 *)G(g.dst);
+      u64x2 v;
+      v.x = g.w0;
+      v.y = g.w1;
+      for (int64_t u = threadIdx.x; u < g.len; u += 256) p[u] = v;
+    } else {
+      __attribute__((address_space(1))) uint64_t *p = G(g.dst);
+      for (int64_t u = threadIdx.x; u < g.len; u += 256) p[u] = g.w0;
+    }
+  }
+}
+
+hipError_t launch_gap_fill(const GapQueue &q, hipStream_t s) {
+  if (!q.e || q.cap == 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<uint32_t>(q.cap, (uint32_t)device_cu_count() * 4);
+  hipLaunchKernelGGL(k_gap_fill, dim3(g), dim3(256), 0, s, (const GapEntry *)q.e, (const uint32_t *)q.count,
+                     q.cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s) {
   hipLaunchKernelGGL(k_empty_offsets, dim3((S + 255) / 256), dim3(256), 0, s, plan, S);
   return hipGetLastError();
@@ -197,11 +225,9 @@ __global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes
       const int64_t qp = j == 0 ? -1 : (int64_t)((nd[j - 1] - lo) >> shift);
       const int64_t qn = j == P.V - 1 ? ((int64_t)1 << P.dirk) + 1 : (int64_t)((nd[j + 1] - lo) >> shift);
       if (q != qp) {  // first key of bucket q; the buckets skipped before it are empty
-        for (int64_t x = qp + 1; x < q; ++x) {
-          D[x].key = 0;
-          D[x].start = (uint32_t)j;
-          D[x].next = (uint32_t)j;
-        }
+        // {key 0, start j, next j} for each of them
+        fill_run(t.gaps, (uint64_t *)(dir + P.dir_off + qp + 1), q - qp - 1, 0,
+                 (uint64_t)(uint32_t)j | ((uint64_t)(uint32_t)j << 32), 2);
         D[q].key = u;
         D[q].start = (uint32_t)j;
       }
@@ -209,11 +235,8 @@ __global__ __launch_bounds__(256) void k_dir(TileLaunch t, const uint64_t *nodes
         D[q].next = (uint32_t)(j + 1);
         if (j == P.V - 1) {
           const int64_t nb = (int64_t)1 << P.dirk;
-          for (int64_t x = q + 1; x <= nb; ++x) {
-            D[x].key = 0;
-            D[x].start = (uint32_t)P.V;
-            D[x].next = (uint32_t)P.V;
-          }
+          fill_run(t.gaps, (uint64_t *)(dir + P.dir_off + q + 1), nb - q, 0,
+                   (uint64_t)(uint32_t)P.V | ((uint64_t)(uint32_t)P.V << 32), 2);
         }
       }
     }
@@ -446,13 +469,13 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_dedupe_write(TileLaunch t, const
         if (OFFSETS) {
           const int64_t hsrc = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1);
           const int64_t hp = (base + idx == 0) ? -1 : (int64_t)(kp[i] >> b);
-          for (int64_t v = hp + 1; v <= hsrc; ++v) G(P.out_off)[v] = j;
+          fill_run(t.gaps, (uint64_t *)(P.out_off + hp + 1), hsrc - hp, (uint64_t)j, 0, 1);
         }
       }
       if (OFFSETS && last_tile && idx == cnt - 1) {
         // the last row of the table closes the offsets
-        for (int64_t v = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1) + 1; v <= P.V; ++v)
-          G(P.out_off)[v] = E;
+        const int64_t h = std::min<int64_t>((int64_t)(k[i] >> b), P.V - 1);
+        fill_run(t.gaps, (uint64_t *)(P.out_off + h + 1), P.V - h, (uint64_t)E, 0, 1);
       }
     }
     if (tid == 0 && last_tile) seg_count[seg] = E;
@@ -518,9 +541,9 @@ __global__ __launch_bounds__(256) void k_multi_offsets(TileLaunch t, const uint6
         if (j < end) {
           const int64_t h = std::min<int64_t>((int64_t)(k[u] >> b), last);
           const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(kp[u] >> b), last);
-          for (int64_t v = hp + 1; v <= h; ++v) G(P.out_off)[v] = j;
+          fill_run(t.gaps, (uint64_t *)(P.out_off + hp + 1), h - hp, (uint64_t)j, 0, 1);
           if (j == count - 1) {
-            for (int64_t v = h + 1; v <= P.V; ++v) G(P.out_off)[v] = count;
+            fill_run(t.gaps, (uint64_t *)(P.out_off + h + 1), P.V - h, (uint64_t)count, 0, 1);
             seg_count[seg] = count;
           }
         }
@@ -575,9 +598,9 @@ __global__ __launch_bounds__(256) void k_in_csr(TileLaunch t, const uint64_t *in
           if (vals) G(P.in_eid)[j] = (int32_t)G(vals)[P.row_off + j];
           const int64_t h = std::min<int64_t>((int64_t)(k[u] >> 32), last);
           const int64_t hp = j == 0 ? -1 : std::min<int64_t>((int64_t)(kp[u] >> 32), last);
-          for (int64_t v = hp + 1; v <= h; ++v) G(P.in_off)[v] = j;
+          fill_run(t.gaps, (uint64_t *)(P.in_off + hp + 1), h - hp, (uint64_t)j, 0, 1);
           if (j == P.E - 1)
-            for (int64_t v = h + 1; v <= P.V; ++v) G(P.in_off)[v] = P.E;
+            fill_run(t.gaps, (uint64_t *)(P.in_off + h + 1), P.V - h, (uint64_t)P.E, 0, 1);
         }
       }
     }

@@ -544,10 +544,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
           G(H.P.out_nbr)[j] = (int32_t)(uint32_t)(keys[i] >> 32);
           // out_off[v] = first position whose source is >= v
           const int64_t hp = e == 0 ? -1 : (int64_t)psrc[DEDUP ? i : 0];
-          for (int64_t v = hp + 1; v <= s_own; ++v) G(H.P.out_off)[v] = j;
+          fill_run(a.gaps, (uint64_t *)(H.P.out_off + hp + 1), s_own - hp, (uint64_t)j, 0, 1);
         }
         if (idx < cnt && e == H.count - 1)  // the table's last key closes the offsets
-          for (int64_t v = s_own + 1; v <= V; ++v) G(H.P.out_off)[v] = H.P.E;
+          fill_run(a.gaps, (uint64_t *)(H.P.out_off + s_own + 1), V - s_own, (uint64_t)H.P.E, 0, 1);
         dpos += (uint32_t)__popcll(lb);
       }
     }

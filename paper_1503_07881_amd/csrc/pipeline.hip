@@ -248,6 +248,16 @@ struct Call {
   size_t meta_bytes = 0;
   Pinned *pin = nullptr;
   int upload_slot = 0;
+  // queued long runs of offsets (fill_run): chunks, then one counter per use
+  char *gaps = nullptr;
+  uint32_t gap_cap = 0;
+  GapQueue gapq(int use) const {
+    GapQueue q;
+    q.e = (GapEntry *)gaps;
+    q.count = gaps ? (uint32_t *)(gaps + align_up(sizeof(GapEntry) * gap_cap)) + use : nullptr;
+    q.cap = gap_cap;
+    return q;
+  }
   // Output blocks, until the graphs take them: one Owner for the call, or
   // (separate) one per table.
   bool separate = false;
@@ -295,9 +305,10 @@ struct Call {
 
   void release_workspace() {
     void *bufs[] = {A, B, base, results, meta, dir, tab, hslots, hmeta, counts,
-                    bsum, vals, small_ws};
+                    bsum, vals, small_ws, gaps};
     for (void *b : bufs) dev_free(hooks, b, stream);
     small_ws = nullptr;
+    gaps = nullptr;
     if (spin) pinned_release(spin, stream);
     spin = nullptr;
     tab = nullptr;
@@ -710,6 +721,14 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     // sync #0: size every table's node hash table from its estimate
     std::vector<int64_t> est;
     HIP_TRY(c.readback(0, est));
+    // Mostly distinct identifiers (V above half the rows, such as the leaves
+    // of a star): sorting all 2n keys is then as cheap as the table, whose
+    // probes and compaction grow with V; measured faster at 2^25 rows from
+    // V/n = 0.5 on (9.9 against 17.2 ms at V/n = 1.6), slower below (4.1
+    // against 7.2 ms at V/n = 0.016).
+    int64_t est_sum = 0;
+    for (int i = 0; i < S; ++i) est_sum += est[i];
+    if (2 * est_sum > N) goto numbering;
     for (int i = 0; i < S; ++i) {
       SegPlan &p = c.plan[i];
       p.tab_off = slots;
@@ -749,6 +768,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
     }
   }
+numbering:
   uint64_t *buf[2] = {c.A, c.B};
   if (!hashed) {
     const int P_n = lsd_passes(64, c.rb);
@@ -821,6 +841,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     p.out_off = (int64_t *)(base1[i] + off1[3 * i + 1]);
     p.in_off = (int64_t *)(base1[i] + off1[3 * i + 2]);
   }
+  // Long runs of equal offsets or directory entries go to a queue that a
+  // fill kernel writes (uses: 0 directory, 1 out-offsets, 2 in-offsets).
+  // Every run lies in one array of at most 2V + 1 entries per table.
+  c.gap_cap = (uint32_t)std::min<int64_t>(gap_chunks_bound(2 * sumV + 2 * S) + 2 * S, INT32_MAX);
+  c.gaps = (char *)dev_alloc(c.hooks, align_up(sizeof(GapEntry) * c.gap_cap) + 64, st);
+  if (!c.gaps) return RINGO_ERR_OUT_OF_MEMORY;
+  HIP_TRY(launch_fill_u64((uint64_t *)(c.gaps + align_up(sizeof(GapEntry) * c.gap_cap)), 0, 8, st));
   const int P_e = lsd_passes(2 * b_max, c.rb);
   const int P_in = lsd_passes(b_max, c.rb);
   c.set_tiles(TM_DIR, RANGE_NODES, DIR_TILE);
@@ -867,9 +894,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
                              counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else {
+    TileLaunch dt = c.tiles(TM_DIR, RANGE_NODES);
+    dt.gaps = c.gapq(0);
     TRACED(TK_DIR, sumV, 16.0 * sumV + 16.0 * dir_words,
-           launch_dir(c.tiles(TM_DIR, RANGE_NODES), c.A, c.dir,
-                      grid_for(c.total(TM_DIR), cus * 8), st));
+           launch_dir(dt, c.A, c.dir, grid_for(c.total(TM_DIR), cus * 8), st));
+    HIP_TRY(launch_gap_fill(dt.gaps, st));
     TRACED(TK_REMAP, N, 24.0 * N,
            launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B, undirected,
                         grid_for(c.total(TM_REMAP), cus * 8), st));
@@ -919,16 +948,22 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   } else if (multi) {
     // every row is an edge: offsets only, and the in-sort reads the sorted
     // keys in place
+    TileLaunch mt = c.tiles(TM_DEDUP, erange);
+    mt.gaps = c.gapq(1);
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_multi_offsets(c.tiles(TM_DEDUP, erange), sorted_edges, c.results + S,
-                                 grid_for(c.total(TM_DEDUP), cus * 8), st));
+    HIP_TRY(launch_multi_offsets(mt, sorted_edges, c.results + S, grid_for(c.total(TM_DEDUP), cus * 8),
+                                 st));
+    HIP_TRY(launch_gap_fill(mt.gaps, st));
     dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   } else {
     // undirected: compaction by per-tile counts and a scan (the digit counts
     // of the edge sort are free now)
+    TileLaunch ut = c.tiles(TM_DEDUP, erange);
+    ut.gaps = c.gapq(1);
     TraceMark m = trace_begin(st);
-    HIP_TRY(launch_dedupe_scan(c.tiles(TM_DEDUP, erange), sorted_edges, ukeys, c.results + S,
-                               c.counts, grid_for(c.total(TM_DEDUP), cus * 4), st));
+    HIP_TRY(launch_dedupe_scan(ut, sorted_edges, ukeys, c.results + S, c.counts,
+                               grid_for(c.total(TM_DEDUP), cus * 4), st));
+    HIP_TRY(launch_gap_fill(ut.gaps, st));
     dedupe_rec = trace_end(m, TK_DEDUPE, NE, 8.0 * NE, st);
   }
 
@@ -983,17 +1018,21 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   } else if (folded) {
     // first in-pass: sorted edge keys with repeats -> distinct (d, s) keys,
     // out_nbr and out_off at the de-duplicated positions
+    in0.gaps = c.gapq(1);
     TRACED(TK_IN_SCATTER, N, 8.0 * N + 12.0 * sumE + 8.0 * (sumV + S),
            launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
+    HIP_TRY(launch_gap_fill(in0.gaps, st));
     uint64_t *ib[2] = {ukeys, sorted_edges};
     for (int p = 1; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ib[(p - 1) & 1], ib[p & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + c.rb * p);
       TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a);
     }
+    TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
+    it.gaps = c.gapq(2);
     TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
-           launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ib[(P_in - 1) & 1], nullptr,
-                         grid_for(c.total(TM_ICSR), cus * 8), st));
+           launch_in_csr(it, ib[(P_in - 1) & 1], nullptr, grid_for(c.total(TM_ICSR), cus * 8), st));
+    HIP_TRY(launch_gap_fill(it.gaps, st));
   } else {
     // the multigraph's first in-pass reads the sorted keys themselves
     uint64_t *ibuf[2] = {multi ? sorted_edges : ukeys, multi ? ukeys : sorted_edges};
@@ -1010,9 +1049,12 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, (p == 0 ? 4.0 : 0.0) + (multi ? 8.0 : 0.0),
                   mode, a);
     }
+    TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
+    it.gaps = c.gapq(2);
     TRACED(TK_IN_CSR, sumE, 12.0 * sumE + 8.0 * (sumV + S),
-           launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ibuf[P_in & 1], multi ? ivb[P_in & 1] : nullptr,
+           launch_in_csr(it, ibuf[P_in & 1], multi ? ivb[P_in & 1] : nullptr,
                          grid_for(c.total(TM_ICSR), cus * 8), st));
+    HIP_TRY(launch_gap_fill(it.gaps, st));
   }
 
   // ------------------------------------------------------------- handoff
@@ -1061,10 +1103,14 @@ struct FixedOut {
 };
 
 // Workspace of the sync-free path: offsets of its buffers in one block.
+// results holds V, E and the counters of the three queues of long runs
+// (directory, out-offsets, in-offsets).
+constexpr int FIXED_RESULTS = 5;
 struct FixedLayout {
   int rb = DEFAULT_DIGIT_BITS, items = 8, sort_tile = 2048, b = 1, dirk_cap = 0;
+  uint32_t gap_cap = 0;
   size_t off_A = 0, off_B = 0, off_counts = 0, off_bsum = 0, off_base = 0, off_results = 0,
-         off_meta = 0, off_dir = 0, bytes = 0;
+         off_meta = 0, off_dir = 0, off_gaps = 0, bytes = 0;
 };
 
 FixedLayout fixed_layout(int64_t n, int rb, int items) {
@@ -1089,9 +1135,13 @@ FixedLayout fixed_layout(int64_t n, int rb, int items) {
   L.off_counts = take(sizeof(uint32_t) * R * (node_tiles + 1));
   L.off_bsum = take(sizeof(uint32_t) * R * std::max(sort_runs(node_tiles), sort_runs(row_tiles)));
   L.off_base = take(sizeof(int64_t) * R);
-  L.off_results = take(sizeof(int64_t) * 2);
+  L.off_results = take(sizeof(int64_t) * FIXED_RESULTS);
   L.off_meta = take(sizeof(uint64_t) * META_WORDS);
   L.off_dir = take(sizeof(DirEntry) * (((size_t)1 << L.dirk_cap) + 1));
+  // runs lie in the directory (2^dirk_cap + 1 entries) or in an offset array
+  // (at most 2n + 1 entries)
+  L.gap_cap = (uint32_t)gap_chunks_bound(std::max<int64_t>(((int64_t)1 << L.dirk_cap) + 1, 2 * n + 1));
+  L.off_gaps = take(sizeof(GapEntry) * L.gap_cap);
   L.bytes = off;
   return L;
 }
@@ -1196,7 +1246,15 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
        launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                        \
   } while (0)
 
-  HIP_TRY(launch_meta_init(m, nwords, (uint64_t *)c.meta, c.results, 2, st));
+  HIP_TRY(launch_meta_init(m, nwords, (uint64_t *)c.meta, c.results, FIXED_RESULTS, st));
+  // queues of long runs: one counter per use (results[2..4])
+  auto gq = [&](int use) {
+    GapQueue q;
+    q.e = (GapEntry *)(ws + L.off_gaps);
+    q.count = (uint32_t *)(c.results + 2 + use);
+    q.cap = L.gap_cap;
+    return q;
+  };
   // node keys: ceil(64 / d) passes, the last one into B
   const int P_n = lsd_passes(64, c.rb);
   uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
@@ -1209,8 +1267,10 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
      launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.counts,
                    grid_for(c.total(TM_UNIQ), cus * 4), st));
   FX(TK_PLAN, 1, 0.0, launch_plan_nodes(plan_dev, c.results, L.dirk_cap, st));
-  FX(TK_DIR, 2 * n, 0.0,
-     launch_dir(c.tiles(TM_DIR, RANGE_NODES), c.A, c.dir, grid_for(c.total(TM_DIR), cus * 8), st));
+  TileLaunch dt = c.tiles(TM_DIR, RANGE_NODES);
+  dt.gaps = gq(0);
+  FX(TK_DIR, 2 * n, 0.0, launch_dir(dt, c.A, c.dir, grid_for(c.total(TM_DIR), cus * 8), st));
+  HIP_TRY(launch_gap_fill(dt.gaps, st));
   FX(TK_REMAP, n, 24.0 * n,
      launch_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.A, c.dir, c.B, 0,
                   grid_for(c.total(TM_REMAP), cus * 8), st));
@@ -1231,17 +1291,21 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   FX(TK_IN_COUNT, n, 8.0 * n,
      launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
   FX(TK_PLAN, 1, 0.0, launch_plan_edges(plan_dev, c.results, ve, st));
+  in0.gaps = gq(1);
   FX(TK_IN_SCATTER, n, 20.0 * n,
      launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
+  HIP_TRY(launch_gap_fill(in0.gaps, st));
   uint64_t *ib[2] = {ukeys, sorted_edges};
   for (int q = 1; q < P_in; ++q) {
     SortLaunch a = c.sort_args(ib[(q - 1) & 1], ib[q & 1], TM_ISORT, RANGE_EDGES, P_in, q,
                                32 + c.rb * q);
     FX_PASS(TK_IN_COUNT, TK_IN_SCATTER, n, SORT_IN, a);
   }
+  TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
+  it.gaps = gq(2);
   FX(TK_IN_CSR, n, 12.0 * n,
-     launch_in_csr(c.tiles(TM_ICSR, RANGE_EDGES), ib[(P_in - 1) & 1], nullptr,
-                   grid_for(c.total(TM_ICSR), cus * 8), st));
+     launch_in_csr(it, ib[(P_in - 1) & 1], nullptr, grid_for(c.total(TM_ICSR), cus * 8), st));
+  HIP_TRY(launch_gap_fill(it.gaps, st));
 #undef FX_PASS
 #undef FX
   return RINGO_OK;
@@ -1401,7 +1465,7 @@ ringo_status_t replay_fixed(GraphSlot &S, FixedGraph &g, const int64_t *src, con
   if (rs != RINGO_OK) return rs;
   uint64_t *meta_dst = (uint64_t *)(S.ws + L.off_meta);
   int64_t *results = (int64_t *)(S.ws + L.off_results);
-  int32_t nres = 2;
+  int32_t nres = FIXED_RESULTS;
   void *args[] = {&m, &nwords, &meta_dst, &results, &nres};
   hipKernelNodeParams p = g.meta;
   p.kernelParams = args;

@@ -80,6 +80,29 @@ __host__ __device__ inline int ceil_log2(int64_t x) {
   return k;
 }
 
+// Runs of equal entries in the offset arrays (and the node directory): the
+// positions of a node range without edges, such as the leaves of a star,
+// all take the value that follows them.  The lane that finds a run writes
+// it when it is short; a long run is queued in chunks of GAP_CHUNK units,
+// and launch_gap_fill then writes every queued chunk with the whole grid.
+constexpr int64_t GAP_INLINE = 256;       // longest run a lane writes itself
+constexpr int64_t GAP_CHUNK = 1 << 16;    // units per queued chunk
+struct GapEntry {
+  uint64_t *dst;   // first word of the chunk
+  int64_t len;     // units
+  uint64_t w0, w1; // the unit's value: w0 (8-byte units) or w0, w1 (16-byte)
+  int64_t words;   // words per unit: 1 or 2
+};
+struct GapQueue {
+  GapEntry *e = nullptr;     // null: every run is written by its lane
+  uint32_t *count = nullptr; // chunks queued (may pass cap; those beyond are not queued)
+  uint32_t cap = 0;
+};
+// Chunks that runs totalling `units` entries of one array can queue.
+inline int64_t gap_chunks_bound(int64_t units) {
+  return units / (GAP_INLINE + 1) + units / GAP_CHUNK + 2;
+}
+
 // ------------------------------------------------------------ kernel launchers
 
 
@@ -99,6 +122,7 @@ struct SortLaunch {
   const uint32_t *vin;        // values carried with the keys (key-value modes), else null
   uint32_t *vout;
   int64_t *seg_total;         // if set, the count part writes each table's key total
+  GapQueue gaps;              // long runs of the out-offsets (first in-pass with dedupe)
 };
 
 // Key source of a pass: the two first passes read their keys from elsewhere
@@ -124,6 +148,7 @@ struct TileLaunch {
   int32_t num_segs;
   int32_t range_kind;
   int64_t total_tiles;
+  GapQueue gaps;  // long runs of offsets or directory entries the kernel writes
 };
 
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
@@ -240,6 +265,8 @@ hipError_t launch_out_nbr(const TileLaunch &t, const uint64_t *in, int grid, hip
 // Multigraph: v[row_off + r] = r for every row of every table.
 hipError_t launch_iota(const TileLaunch &rows, uint32_t *v, int grid, hipStream_t s);
 hipError_t launch_empty_offsets(const SegPlan *plan, int32_t S, hipStream_t s);
+// Writes the chunks queued in q (after the kernel that queued them).
+hipError_t launch_gap_fill(const GapQueue &q, hipStream_t s);
 // Sync-free single table (kernels.hip): the plan and tile maps passed by
 // value (at most META_WORDS words) and copied to dst, results[0, nres)
 // zeroed; V and E moved from results into the plan on the device (and to

@@ -83,7 +83,9 @@ def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
         monkeypatch.setenv("RINGO_FIXED_PATH", "0")
     rng = np.random.default_rng(5)
     n = 300_000  # above the small-table size
-    src_h = rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
+    # identifiers from a pool of n / 8, so that hash numbering builds its table
+    ids = rng.integers(-(1 << 62), 1 << 62, n // 8, dtype=np.int64)
+    src_h = ids[rng.integers(0, ids.size, n)]
     dst_h = src_h[rng.permutation(n)]
     src, dst = (torch.from_numpy(a).to(cuda) for a in (src_h, dst_h))
     kind = KINDS[kname]

@@ -193,3 +193,18 @@ def test_config2_full_size(cuda):
     own_u = torch.repeat_interleave(torch.arange(V, device=cuda), gu.out_offsets[1:] - gu.out_offsets[:-1])
     assert torch.equal(own_u * V + gu.out_nbrs.long(), want)
     assert torch.equal(gu.in_offsets, gu.out_offsets) and torch.equal(gu.in_nbrs, gu.out_nbrs)
+
+
+@pytest.mark.parametrize("kname", sorted(KINDS))
+@pytest.mark.parametrize("hub", ["min", "max"])
+def test_star_long_offset_runs(cuda, kname, method, hub):
+    """Stars of 2^21 leaves whose hub sits at either end of the signed range:
+    the offsets of every leaf form one long run, written by the queued fill
+    rather than by the lane that finds it."""
+    n = 1 << 21
+    h = I64_MIN if hub == "min" else I64_MAX
+    leaves = np.arange(-(n // 2), n // 2, dtype=np.int64)
+    for direction in ("out", "in"):
+        s, d = (np.full(n, h, np.int64), leaves) if direction == "out" else (leaves, np.full(n, h, np.int64))
+        say("kinds star", kname, direction, "hub", hub, method)
+        check(s, d, KINDS[kname], cuda, f"{kname} {direction}-star hub {hub}: ")

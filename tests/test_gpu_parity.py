@@ -85,8 +85,10 @@ def test_hash_bucket_paths(cuda):
     saved = [ringo.tune_get(1 << e) for e in range(63)]
     try:
         ringo.set_node_method(ringo.NODES_HASH)
-        spread = random_table(91, 200_000, 150_000)
-        crowded = (np.arange(0, 60_000, dtype=np.int64), np.arange(7, 60_007, dtype=np.int64))
+        # fewer distinct identifiers than half the rows, so the table is built
+        spread = random_table(91, 400_000, 100_000)
+        crowded = (np.tile(np.arange(0, 60_000, dtype=np.int64), 4),
+                   np.tile(np.arange(7, 60_007, dtype=np.int64), 4))
         for name, (src, dst), want, not_want in (
                 ("spread", spread, "hash_bucket_sort", "sort_vnode_count"),
                 ("crowded", crowded, "sort_vnode_count", "hash_bucket_sort")):
@@ -97,6 +99,30 @@ def test_hash_bucket_paths(cuda):
             ringo.trace_enable(False)
             assert want in names and not_want not in names, (name, sorted(names))
             assert_same(g, oracle.table_to_graph(src, dst), name + ": ")
+    finally:
+        ringo.trace_enable(False)
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
+
+
+def test_hash_numbering_steps_aside_for_distinct_ids(cuda):
+    """Under hash numbering, a table whose estimated distinct identifiers
+    exceed half its rows is numbered by sorting (no table is built); one with
+    fewer builds the table.  Both give the oracle's graph."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    try:
+        ringo.set_node_method(ringo.NODES_HASH)
+        n = 300_000
+        for pool, built in ((n // 8, True), (n // 3, True), (2 * n, False), (8 * n, False)):
+            src, dst = random_table(pool, n, pool)
+            ringo.trace_enable(True)
+            g = gpu_graph(src, dst, cuda)
+            names = set(ringo.trace_read())
+            ringo.trace_enable(False)
+            say("hash or sort by distinct count: pool", pool, "V", g.num_nodes, sorted(names))
+            assert ("hash_insert" in names) == built, (pool, g.num_nodes, sorted(names))
+            assert "hash_estimate" in names
+            assert_same(g, oracle.table_to_graph(src, dst), f"pool {pool}: ")
     finally:
         ringo.trace_enable(False)
         for e, (d, it, m) in enumerate(saved):
@@ -134,6 +160,23 @@ def test_special_structures(cuda, method, small_path):
     for name, (src, dst) in cases.items():
         say("special case", name, method, small_path)
         assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), name + ": ")
+
+
+@pytest.mark.parametrize("n", [1 << 20, 1 << 22])
+@pytest.mark.parametrize("hub", ["min", "max"])
+def test_star_long_offset_runs(cuda, method, n, hub):
+    """Out- and in-stars whose hub sits at either end of the signed range:
+    the out- or in-offsets of every leaf form one run of about n equal
+    entries, and (sort numbering) the directory has a run of about 2^b empty
+    buckets; such runs are queued and written by a grid-wide fill.  2^20
+    rows take the sync-free path under sort numbering, 2^22 the pipeline."""
+    h = I64_MIN if hub == "min" else I64_MAX
+    leaves = np.arange(n, dtype=np.int64)
+    for direction in ("out", "in"):
+        src, dst = (np.full(n, h, np.int64), leaves) if direction == "out" else (leaves, np.full(n, h, np.int64))
+        say("star", direction, "hub", hub, "rows", n, method)
+        assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst, all_cores=True),
+                    f"{direction}-star hub {hub} n={n}: ")
 
 
 def test_config1_full(cuda, method):
