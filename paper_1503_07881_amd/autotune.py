@@ -10,8 +10,13 @@ library through ringo_tune_set.  The schedule changes only the tiling and
 the number of passes: the output is the same bit for bit whichever schedule
 runs.
 
-    python -m paper_1503_07881_amd.autotune            # tune and save
+    python -m paper_1503_07881_amd.autotune                 # tune and save
+    python -m paper_1503_07881_amd.autotune --emit-header   # cache -> csrc/tuned_schedule.h
     from paper_1503_07881_amd import autotune; autotune.apply()   # load and apply
+
+The library's built-in schedule table is generated from the committed
+cache (csrc/tuned_schedule.h), so the tuned schedules apply from the
+library's first call on; apply() sets another cache at run time.
 """
 from __future__ import annotations
 
@@ -36,45 +41,67 @@ def _device_name() -> str:
     return torch.cuda.get_device_properties(0).name if torch.cuda.is_available() else "none"
 
 
-def tune(log2_sizes=range(10, 27, 2), reps: int = 3, verbose: bool = False) -> dict:
+def tune(log2_sizes=range(10, 27), rounds: int = 0, margin: float = 0.03, verbose: bool = False) -> dict:
     """Times every schedule for R-MAT tables of 2^k rows; returns
     {"device": ..., "buckets": {str(rows): {"items": i, "digit_bits": d, "node_method": m,
-    "ms": {...}}}}."""
+    "ms": {...}}}}.  Every schedule runs twice first (allocations, graph
+    captures), then the schedules take turns, one call each per round, so
+    that drifts of the device affect them alike; the median per schedule
+    counts (each timed call follows an untimed one of the same schedule, and
+    each round starts at another schedule).  The library's built-in schedule
+    for the size is kept unless
+    another is faster by more than `margin` (calls of a few milliseconds or
+    less vary by a few percent from call to call)."""
     import torch
     dev = torch.device("cuda:0")
     sh = torch.cuda.current_stream().cuda_stream
-    out = {"device": _device_name(), "buckets": {}}
+    out = {"device": _device_name(), "margin": margin, "buckets": {}}
+    builtin = {k: ringo.tune_get(1 << k) for k in log2_sizes}
+    scheds = [(m, b, i) for m in METHODS for b in DIGIT_BITS for i in ITEMS]
+
+    def call(src, dst, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
     for k in log2_sizes:
         n = 1 << k
         spec = workloads.TableSpec("rmat", n, seed=99, table=k, scale=workloads.rmat_scale_for(n))
         src = torch.empty(n, dtype=torch.int64, device=dev)
         dst = torch.empty_like(src)
         workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), sh)
-        times = {}
-        for method in METHODS:
-            for bits in DIGIT_BITS:
-                for items in ITEMS:
-                    ringo.tune_set(n, bits, items, method)
-                    t0 = time.perf_counter()
-                    ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
-                    torch.cuda.synchronize()
-                    # small tables take milliseconds or less and vary from call
-                    # to call: enough repetitions for about 50 ms each
-                    first = time.perf_counter() - t0
-                    ts = []
-                    for _ in range(max(reps, min(50, int(0.05 / max(first, 1e-6))))):
-                        t0 = time.perf_counter()
-                        ringo.graph_free(ringo.table_to_graph_raw(src.data_ptr(), dst.data_ptr(), n, sh))
-                        torch.cuda.synchronize()
-                        ts.append(time.perf_counter() - t0)
-                    times[(method, bits, items)] = sorted(ts)[len(ts) // 2] * 1e3
-        method, bits, items = min(times, key=times.get)
+        first = 0.0
+        for method, bits, items in scheds:
+            ringo.tune_set(n, bits, items, method)
+            call(src, dst, n)
+            first = max(first, call(src, dst, n))
+        # about a second of timed calls per size, 5 to 20 rounds
+        r = rounds or max(5, min(20, int(1.0 / max(2 * first * len(scheds), 1e-6))))
+        ts = {sc: [] for sc in scheds}
+        for rd in range(r):
+            # each round starts at another schedule, and each schedule's timed
+            # call follows an untimed one of its own (the first call after a
+            # change of schedule pays for buffers of other sizes)
+            for j in range(len(scheds)):
+                sc = scheds[(j + rd * 7) % len(scheds)]
+                ringo.tune_set(n, sc[1], sc[2], sc[0])
+                call(src, dst, n)
+                ts[sc].append(call(src, dst, n))
+        times = {sc: sorted(v)[len(v) // 2] * 1e3 for sc, v in ts.items()}
+        d0, i0, m0 = builtin[k]
+        best = min(times, key=times.get)
+        if (m0, d0, i0) in times and times[(m0, d0, i0)] <= times[best] * (1 + margin):
+            best = (m0, d0, i0)
+        method, bits, items = best
         out["buckets"][str(n)] = {"items": items, "digit_bits": bits, "node_method": method,
                                   "ms": {f"{'hash' if m else 'sort'}/d{d}/{i}": round(v, 4)
                                          for (m, d, i), v in times.items()}}
         if verbose:
-            print(f"rows 2^{k}: best {'hash' if method else 'sort'}/d{bits}/{items}  "
-                  f"{out['buckets'][str(n)]['ms']}", flush=True)
+            print(f"rows 2^{k}: best {'hash' if method else 'sort'}/d{bits}/{items} "
+                  f"({times[best]:.4f} ms; built-in {'hash' if m0 else 'sort'}/d{d0}/{i0} "
+                  f"{times.get((m0, d0, i0), float('nan')):.4f} ms)", flush=True)
         del src, dst
     apply(out)
     return out
@@ -127,6 +154,44 @@ def apply(cache: dict | None = None) -> int:
     return applied
 
 
+HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "tuned_schedule.h")
+
+
+def header_text(cache: dict) -> str:
+    """The library's built-in schedule table (csrc/tuned_schedule.h) for a
+    cache: one row per tuned size, in ascending order, that the library
+    applies to the size buckets the cache covers as apply() does."""
+    rows = sorted((int(k), v.get("digit_bits", 8), v["items"], v.get("node_method", 0))
+                  for k, v in cache.get("buckets", {}).items()
+                  if v.get("items") in ITEMS and v.get("node_method", 0) in METHODS
+                  and v.get("digit_bits", 8) in DIGIT_BITS)
+    lines = ["// Generated from tuned_schedules.json by `python -m paper_1503_07881_amd.autotune --emit-header`;",
+             "// do not edit.  Schedules measured on " + str(cache.get("device", "?")) + " for R-MAT tables:",
+             "// {log2 rows, digit bits, items per thread, node method (0 sort, 1 hash)}.",
+             "#pragma once", "", "namespace ringo {", "",
+             "struct TunedBucket {", "  int log2_rows, digit_bits, items, node_method;", "};", "",
+             f"constexpr int NUM_TUNED = {len(rows)};",
+             "constexpr TunedBucket TUNED[NUM_TUNED > 0 ? NUM_TUNED : 1] = {"]
+    for n, d, it, m in rows:
+        lines.append(f"    {{{n.bit_length() - 1}, {d}, {it}, {m}}},")
+    if not rows:
+        lines.append("    {0, 8, 8, 0},")
+    lines += ["};", "", "}  // namespace ringo", ""]
+    return "\n".join(lines)
+
+
+def emit_header(cache: dict | None = None, path: str | None = None) -> str:
+    cache = cache if cache is not None else load()
+    path = path or HEADER
+    with open(path, "w") as f:
+        f.write(header_text(cache or {}))
+    return path
+
+
 if __name__ == "__main__":
-    c = tune(verbose=True)
-    print("saved", save(c))
+    import sys
+    if "--emit-header" in sys.argv:
+        print("wrote", emit_header())
+    else:
+        c = tune(verbose=True)
+        print("saved", save(c))

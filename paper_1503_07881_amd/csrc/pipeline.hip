@@ -32,6 +32,7 @@
 
 #include "ringo.h"
 #include "ringo_internal.h"
+#include "tuned_schedule.h"
 
 using namespace ringo;
 
@@ -150,11 +151,12 @@ void pinned_release(Pinned *b, hipStream_t s) {
 // Items per thread of the scatter tile, digit bits of the radix passes and
 // node-numbering method by table size (log2 buckets of rows).  Built-in
 // defaults, from measurements on an MI355X (R-MAT tables, 2^10 to 1.5e9
-// rows): the sort numbering up to 2^23 rows and the hash numbering above;
-// 8 items per thread and 8-bit digits up to 2^26 rows (16 items within
-// noise there); above, 16 items (full 128-byte digit runs), and from 2^29
-// rows 9-bit digits, which save an edge pass and an in-pass once node
-// indices need 25 bits or more (3-4% faster at 2^29 and 1.5e9 rows).
+// rows): up to 2^26 rows the autotuner's table (tuned_schedule.h, generated
+// from its cache); where it has no entry, the sort numbering up to 2^23 rows
+// and the hash numbering above, 8 items per thread and 8-bit digits up to
+// 2^26 rows; above, 16 items (full 128-byte digit runs), and from 2^29 rows
+// 9-bit digits, which save an edge pass and an in-pass once node indices
+// need 25 bits or more (3-4% faster at 2^29 and 1.5e9 rows).
 int g_items[64];
 int g_bits[64];
 int g_method[64];
@@ -169,6 +171,19 @@ void schedule_init_locked() {
     g_items[i] = i >= WIDE_TILE_LOG2 ? 16 : 8;
     g_bits[i] = i >= WIDE_DIGIT_LOG2 ? 9 : DEFAULT_DIGIT_BITS;
     g_method[i] = i >= HASH_DEFAULT_LOG2 ? RINGO_NODES_HASH : RINGO_NODES_SORT;
+  }
+  // the autotuner's measured schedules (tuned_schedule.h) for the buckets
+  // up to its largest size: each bucket takes the tuned size at or below it
+  // (the smallest tuned size for the buckets below that)
+  if (NUM_TUNED > 0) {
+    for (int i = 0; i <= TUNED[NUM_TUNED - 1].log2_rows && i < 64; ++i) {
+      int t = 0;
+      for (int j = 0; j < NUM_TUNED; ++j)
+        if (TUNED[j].log2_rows <= i) t = j;
+      g_items[i] = TUNED[t].items;
+      g_bits[i] = TUNED[t].digit_bits;
+      g_method[i] = TUNED[t].node_method;
+    }
   }
   g_items_init = true;
 }
@@ -1322,7 +1337,7 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
 // kept workspace; a call that finds it busy, and calls through a caller's
 // allocator (which owns all device memory then), enqueue the kernels
 // themselves.  RINGO_FIXED_GRAPH=0 (test support) turns the replay off.
-constexpr int MAX_FIXED_GRAPHS = 8;
+constexpr int MAX_FIXED_GRAPHS = 32;
 
 struct FixedGraph {
   int64_t n = 0;
@@ -1344,7 +1359,10 @@ struct GraphSlot {
   bool broken = false;  // capture failed once: calls enqueue their kernels
   uint64_t clock = 0;
   std::vector<FixedGraph> graphs;
-  std::vector<int64_t> seen;  // sizes met once (a size is captured when it comes back)
+  // sizes met since their last capture: a size is captured the second time
+  // it comes, so one-off sizes cost no capture and a size whose graph was
+  // evicted comes back twice before it is captured again
+  std::vector<int64_t> seen;
 };
 GraphSlot g_graph_slots[64];
 
@@ -1380,14 +1398,16 @@ FixedGraph *fixed_graph_for(GraphSlot &S, const int64_t *src, const int64_t *dst
       return &g;
     }
   if (S.broken || n == 0) return nullptr;
-  // a size is captured the second time it comes: one-off sizes cost no
-  // capture, and the first call has set up what the launches query
+  // a size is captured the second time it comes (the first call has also
+  // set up what the launches query)
   const int64_t key = n * 64 + L.rb * 4 + L.items / 4;
-  if (std::find(S.seen.begin(), S.seen.end(), key) == S.seen.end()) {
-    if (S.seen.size() >= 64) S.seen.erase(S.seen.begin());
+  const auto it = std::find(S.seen.begin(), S.seen.end(), key);
+  if (it == S.seen.end()) {
+    if (S.seen.size() >= 256) S.seen.erase(S.seen.begin());
     S.seen.push_back(key);
     return nullptr;
   }
+  S.seen.erase(it);
   if (!S.ws) {
     const size_t bytes = fixed_ws_max();
     void *p = nullptr;

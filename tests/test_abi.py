@@ -8,7 +8,8 @@ import pytest
 
 from paper_1503_07881_amd import ringo, workloads
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ringo.h")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ringo.h")
 
 
 def declared_functions():
@@ -166,3 +167,29 @@ def test_autotune_cache_roundtrip(tmp_path):
     # restore the library's schedule
     for e, (d, it, m) in enumerate(saved):
         ringo.tune_set(1 << e, d, it, m)
+
+
+def test_builtin_schedule_is_the_tuned_cache():
+    """The library's built-in schedule table is the committed autotuner cache:
+    the generated header matches the cache, and in a fresh process (no
+    schedule set at run time) every size bucket the cache covers has the
+    schedule that autotune.apply() would give it from the cache."""
+    import json
+    import subprocess
+    import sys
+    from paper_1503_07881_amd import autotune
+    pkg = os.path.dirname(autotune.__file__)
+    cache = autotune.load(os.path.join(pkg, "tuned_schedules.json"))
+    assert cache and cache["buckets"], "no committed cache"
+    with open(autotune.HEADER) as f:
+        assert f.read() == autotune.header_text(cache), "csrc/tuned_schedule.h is stale: re-emit it"
+    rows = sorted((int(k), v["digit_bits"], v["items"], v["node_method"]) for k, v in cache["buckets"].items())
+    largest = rows[-1][0].bit_length() - 1
+    code = ("import json, sys; sys.path.insert(0, %r); from paper_1503_07881_amd import ringo; "
+            "print(json.dumps([ringo.tune_get(1 << e) for e in range(%d)]))" % (ROOT, largest + 1))
+    got = json.loads(subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                                    check=True).stdout)
+    for e in range(largest + 1):
+        below = [r for r in rows if r[0] <= (1 << e)]
+        n, d, it, m = below[-1] if below else rows[0]
+        assert tuple(got[e]) == (d, it, m), (e, got[e], (d, it, m))
