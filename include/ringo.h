@@ -262,9 +262,13 @@ const char *ringo_status_string(ringo_status_t s);
  * Optional device allocator for workspaces and outputs (for example a
  * framework's caching allocator).  alloc(bytes, stream, ctx) returns device
  * memory usable in stream order on `stream`, or NULL; free_(ptr, stream, ctx)
- * returns it.  Passing NULL for both restores the built-in allocator
- * (stream-ordered hipMallocAsync).  Must not be changed while graphs
- * allocated by the previous allocator are alive.
+ * returns it.  Passing NULL for both restores the built-in allocator: a
+ * cache of device blocks per device (hipMalloc), where a freed block stays
+ * allocated and is reused by later requests on the stream that freed it at
+ * once, on other streams once the work before its release has completed;
+ * cached blocks are returned to the device only when hipMalloc fails.  Must
+ * not be changed while graphs allocated by the previous allocator are
+ * alive.
  */
 ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stream, void *ctx),
                                    void (*free_)(void *ptr, hipStream_t stream, void *ctx),

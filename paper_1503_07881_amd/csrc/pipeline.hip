@@ -27,7 +27,9 @@
 #include <atomic>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "ringo.h"
@@ -48,41 +50,137 @@ struct AllocHooks {
 
 std::mutex g_mu;
 AllocHooks g_hooks;
-bool g_pool_ready[64] = {false};
 
 AllocHooks hooks() {
   std::lock_guard<std::mutex> lk(g_mu);
   return g_hooks;
 }
 
-void prepare_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (g_pool_ready[dev]) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;  // keep freed blocks cached in the pool
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+// Device blocks of the built-in allocator.  The runtime's stream-ordered
+// pool gives its memory back to the device at synchronisations whatever its
+// release threshold, so that repeated large calls map and unmap tens of
+// gigabytes each time (freeing the outputs of a 10^9-row batch then took
+// over a second).  The library keeps its own cache instead: a freed block
+// stays allocated, and a request takes the smallest cached block that holds
+// it (up to a quarter, or 64 MB, larger) once the block's last use has
+// completed, or at once on the stream that used it last (stream order).
+// Cached blocks go back to the device only when hipMalloc fails.
+struct CachedBlock {
+  void *p;
+  size_t size;
+  hipStream_t stream;
+  hipEvent_t ev;  // recorded on `stream` when the block was freed
+};
+struct DeviceCache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> idle;   // by size
+  std::unordered_map<void *, size_t> live;   // handed-out blocks and their sizes
+  std::vector<hipEvent_t> spare;             // events of reused blocks
+};
+DeviceCache g_cache[64];
+
+size_t size_class(size_t bytes) {
+  const size_t g = bytes <= ((size_t)1 << 20) ? 512 : ((size_t)2 << 20);
+  return (bytes + g - 1) / g * g;
+}
+
+// Every idle block back to the device (after its last use).  Caller holds C.mu.
+void release_idle(DeviceCache &C) {
+  for (auto &kv : C.idle) {
+    (void)hipEventSynchronize(kv.second.ev);
+    (void)hipEventDestroy(kv.second.ev);
+    (void)hipFree(kv.second.p);
   }
-  g_pool_ready[dev] = true;
+  C.idle.clear();
+  (void)hipGetLastError();
+}
+
+void *cache_alloc(size_t bytes, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  DeviceCache &C = g_cache[dev];
+  const size_t want = size_class(bytes);
+  const size_t most = std::max(want + want / 4, want + ((size_t)64 << 20));
+  std::lock_guard<std::mutex> lk(C.mu);
+  for (auto it = C.idle.lower_bound(want); it != C.idle.end() && it->first <= most; ++it) {
+    const CachedBlock b = it->second;
+    bool ready = b.stream == s;
+    if (!ready) {
+      const hipError_t q = hipEventQuery(b.ev);
+      ready = q == hipSuccess;
+      if (q != hipSuccess) (void)hipGetLastError();
+    }
+    if (ready) {
+      C.idle.erase(it);
+      C.spare.push_back(b.ev);
+      C.live[b.p] = b.size;
+      return b.p;
+    }
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    release_idle(C);
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  C.live[p] = want;
+  return p;
+}
+
+void cache_free(void *p, hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  // the block's device: the current one, else the one whose cache holds it
+  for (int k = 0; k < 64; ++k) {
+    std::lock_guard<std::mutex> lk(g_cache[(dev + k) % 64].mu);
+    if (g_cache[(dev + k) % 64].live.count(p)) {
+      dev = (dev + k) % 64;
+      break;
+    }
+  }
+  DeviceCache &C = g_cache[dev];
+  std::lock_guard<std::mutex> lk(C.mu);
+  auto it = C.live.find(p);
+  if (it == C.live.end()) return;  // not a block of the cache
+  const size_t size = it->second;
+  C.live.erase(it);
+  hipEvent_t ev = nullptr;
+  if (!C.spare.empty()) {
+    ev = C.spare.back();
+    C.spare.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);  // no event: the block is idle once the stream is
+    (void)hipFree(p);
+    return;
+  }
+  if (hipEventRecord(ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    (void)hipEventRecord(ev, nullptr);
+  }
+  C.idle.insert({size, CachedBlock{p, size, s, ev}});
 }
 
 void *dev_alloc(const AllocHooks &h, size_t bytes, hipStream_t s) {
   bytes = std::max<size_t>(bytes, 256);
   if (h.alloc) return h.alloc(bytes, s, h.ctx);
-  void *p = nullptr;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  return p;
+  return cache_alloc(bytes, s);
 }
 
 void dev_free(const AllocHooks &h, void *p, hipStream_t s) {
   if (!p) return;
   if (h.free_) h.free_(p, s, h.ctx);
-  else (void)hipFreeAsync(p, s);
+  else cache_free(p, s);
 }
 
 // Owner of output arrays: of one call (shared by the graphs of a batch), or
@@ -1657,7 +1755,6 @@ bool fixed_path_for(int32_t S, int32_t kind, int64_t n) {
 // radix passes (one table, plain mode, the schedule's digit width for n
 // rows); the last pass writes `out`.
 ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits, hipStream_t st) {
-  prepare_pool();
   Call c;
   c.S = 1;
   c.stream = st;
@@ -1714,7 +1811,6 @@ ringo_status_t convert(int32_t S, const int64_t *const *src, const int64_t *cons
   }
   if (S == 0) return RINGO_OK;
   (void)hipGetLastError();
-  prepare_pool();
   if (fixed_path_for(S, kind, num_rows[0])) {
     const ringo_status_t rc = convert_fixed(src[0], dst[0], num_rows[0], &outs[0], stream, separate);
     if (rc != RINGO_OK) std::memset(&outs[0], 0, sizeof(ringo_graph_t));
@@ -1929,7 +2025,6 @@ const char *ringo_version(void) { return "ringo-mi355x 0.1 (gfx950)"; }
 namespace ringo {
 
 void *workspace_alloc(size_t bytes, hipStream_t s) {
-  prepare_pool();
   return dev_alloc(hooks(), bytes, s);
 }
 

@@ -321,8 +321,8 @@ size_t graph_bytes(const ringo_graph_t *g);
 void graph_free_on(ringo_graph_t *g, hipStream_t stream);
 
 // Stream-ordered device memory from the library's allocator (the caller's
-// hooks when set, else the device pool); used by the entry points other than
-// the conversion itself.
+// hooks when set, else the library's cache of device blocks); used by the
+// entry points other than the conversion itself.
 void *workspace_alloc(size_t bytes, hipStream_t s);
 void workspace_free(void *p, hipStream_t s);
 

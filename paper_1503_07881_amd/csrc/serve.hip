@@ -212,11 +212,8 @@ struct ringo_server {
       if (rec.end) (void)hipEventDestroy(rec.end);
       rec.start = rec.end = nullptr;
     }
-    if (hipMallocAsync((void **)&dev, (size_t)std::max<int64_t>(16 * total, 256), stream) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      rc = RINGO_ERR_OUT_OF_MEMORY;
-    }
+    dev = (int64_t *)ringo::workspace_alloc((size_t)std::max<int64_t>(16 * total, 256), stream);
+    if (!dev) rc = RINGO_ERR_OUT_OF_MEMORY;
     std::vector<const int64_t *> dsrc(k), ddst(k);
     std::vector<ringo_graph_t> outs(k);
     if (rc == RINGO_OK) {
@@ -240,7 +237,7 @@ struct ringo_server {
       rc = RINGO_ERR_HIP;
     }
     if (rc == RINGO_OK && hipStreamSynchronize(stream) != hipSuccess) rc = RINGO_ERR_HIP;
-    if (dev) (void)hipFreeAsync(dev, stream);
+    if (dev) ringo::workspace_free(dev, stream);
     if (rc != RINGO_OK) {
       (void)hipStreamSynchronize(stream);
       (void)hipGetLastError();

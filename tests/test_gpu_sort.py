@@ -20,9 +20,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def expected(keys: np.ndarray, bits: int, digit: int = 8) -> np.ndarray:
-    """Stable sort by the low digit * ceil(bits / digit) bits (at most 64);
+def expected(keys: np.ndarray, bits: int, digit: int | None = None) -> np.ndarray:
+    """Stable sort by the low digit * ceil(bits / digit) bits (at most 64),
+    digit being the schedule's digit width for that many keys unless given;
     higher bits ride along."""
+    if digit is None:
+        digit = ringo.tune_get(max(1, keys.size))[0]
     width = min(64, digit * ((bits + digit - 1) // digit))
     u = keys.view(np.uint64)
     k = u if width == 64 else u & np.uint64((1 << width) - 1)
