@@ -30,9 +30,10 @@
 // an independent numpy/scipy route, closed forms and invariants (tests/).
 //
 // oracle_table_to_graph_par is the same computation with libstdc++'s
-// parallel-mode sort (OpenMP, all host threads) in place of std::sort, for
-// timing the oracle on every core; sorting values of a total order gives
-// the same sequence either way, so the result is identical.
+// parallel-mode sort (OpenMP, all host threads) in place of std::sort and the
+// rows' independent lookups spread over the threads, for running the oracle
+// on every core (timing, and the largest tables); sorting values of a total
+// order gives the same sequence either way, so the result is identical.
 //
 // Two further graph kinds (oracle_table_to_graph_kind), the same definition
 // with another edge rule (the paper limits its discussion to directed graphs,
@@ -45,6 +46,8 @@
 
 #include <omp.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <new>
@@ -96,10 +99,22 @@ void build_direction(const std::vector<std::pair<int32_t, int32_t>> &pairs, int6
   for (size_t i = 0; i < pairs.size(); ++i) nbr[i] = pairs[i].second;
 }
 
+// ORACLE_PROGRESS=1: the parallel mode names each finished step on stderr
+// (runs on the largest tables take minutes).
+void progress(bool parallel, const char *what) {
+  static const bool on = getenv("ORACLE_PROGRESS") && getenv("ORACLE_PROGRESS")[0] == '1';
+  if (parallel && on) {
+    fprintf(stderr, "oracle: %s\n", what);
+    fflush(stderr);
+  }
+}
+
 struct SerialSort {
+  static constexpr bool parallel = false;
   template <class It> void operator()(It b, It e) const { std::sort(b, e); }
 };
 struct ParallelSort {
+  static constexpr bool parallel = true;
   template <class It> void operator()(It b, It e) const { __gnu_parallel::sort(b, e); }
 };
 
@@ -119,6 +134,7 @@ int table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **han
     all.insert(all.end(), src, src + n);
     all.insert(all.end(), dst, dst + n);
     sort(all.begin(), all.end());
+    progress(Sort::parallel, "node keys sorted");
     all.erase(std::unique(all.begin(), all.end()), all.end());
     g->nodes.swap(all);
     const int64_t V = (int64_t)g->nodes.size();
@@ -132,14 +148,23 @@ int table_to_graph(const int64_t *src, const int64_t *dst, int64_t n, void **han
     // Edge set: one (source index, destination index) pair per row, sorted,
     // repeated pairs removed.
     std::vector<std::pair<int32_t, int32_t>> e((size_t)n);
-    for (int64_t r = 0; r < n; ++r) e[(size_t)r] = {index_of(src[r]), index_of(dst[r])};
+    // (each row's lookup is independent: the parallel mode spreads the rows
+    // over the host threads, in eight slices, which gives the same pairs)
+    for (int part = 0; part < 8; ++part) {
+      const int64_t r0 = n * part / 8, r1 = n * (part + 1) / 8;
+#pragma omp parallel for schedule(static) if (Sort::parallel)
+      for (int64_t r = r0; r < r1; ++r) e[(size_t)r] = {index_of(src[r]), index_of(dst[r])};
+      progress(Sort::parallel, "an eighth of the rows looked up");
+    }
     sort(e.begin(), e.end());
     e.erase(std::unique(e.begin(), e.end()), e.end());
+    progress(Sort::parallel, "edges sorted");
     build_direction(e, V, g->out_off, g->out_nbr);
     // In-direction: the same edges keyed by destination.
     for (auto &p : e) std::swap(p.first, p.second);
     sort(e.begin(), e.end());
     build_direction(e, V, g->in_off, g->in_nbr);
+    progress(Sort::parallel, "in-direction built");
     *num_nodes = V;
     *num_edges = (int64_t)e.size();
     *handle = g;

@@ -9,10 +9,13 @@ conversion; bit-exact, since it is integer work).
   schedule of the 1.5e9-row workload (9-bit digits, 16 items per thread)
 - every one of the 4096 tables of the batched workload (in
   test_gpu_parity.test_config4_batched_full)
+- the whole 1.5e9-row workload, where the host has the memory (the oracle
+  takes about two minutes on 16 threads and 100 GB)
 
 The oracle runs on the host with its sorts in parallel mode where a table is
 large (the same steps, identical result, tested in the oracle's pins).
 """
+import os
 import sys
 
 import numpy as np
@@ -96,3 +99,41 @@ def test_rmat_2e24_vs_oracle(cuda, sched):
         ringo.tune_set(spec.n, *saved)
     want = oracle.table_to_graph(hs, hd, all_cores=True)
     assert_same(got, want, f"2^24 rows {sched}: ")
+
+
+def _host_gib():
+    try:
+        import psutil
+        return psutil.virtual_memory().total / 2**30
+    except ImportError:
+        return 0.0
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(_host_gib() < 160 or os.environ.get("RINGO_FULL_ORACLE") == "0",
+                    reason="the oracle on 1.5e9 rows needs about 100 GB of host memory (160 GiB asked) "
+                           "and about two minutes on 16 threads; RINGO_FULL_ORACLE=0 skips it")
+def test_config3_whole_table_vs_oracle(cuda):
+    """The whole 1.5e9-row table (the benchmark's headline workload, built-in
+    schedule: hash numbering, 9-bit digits, 16 items per thread) equals the
+    oracle's graph element by element; the oracle runs on every host thread."""
+    import time
+    import torch
+    spec = workloads.config3()
+    d, it, m = ringo.tune_get(spec.n)
+    say("config 3 whole table: 1.5e9 rows, schedule digit bits", d, "items", it, "method", m)
+    src, dst = _device_rmat(spec, cuda)
+    g = ringo.to_graph(src, dst)
+    torch.cuda.synchronize()
+    got = _host_graph(g)
+    del g
+    hs, hd = src.cpu().numpy(), dst.cpu().numpy()
+    del src, dst
+    torch.cuda.empty_cache()
+    say("config 3 whole table: V", got["node_ids"].size, "E", got["out_nbrs"].size, "- oracle on the host")
+    t0 = time.perf_counter()
+    want = oracle.table_to_graph(hs, hd, all_cores=True)
+    say("config 3 whole table: oracle", round(time.perf_counter() - t0, 1), "s on", oracle.last_threads, "threads")
+    del hs, hd
+    assert_same(got, want, "config 3 whole table: ")
+    say("config 3 whole table: equal to the oracle")
