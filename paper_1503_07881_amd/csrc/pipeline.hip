@@ -601,14 +601,15 @@ void trace_set_bytes(long idx, double bytes) {
     (void)trace_end(_m, (kind), (units), (double)(bytes), st); \
   } while (0)
 
-// One radix pass as two traced entries: counting (reads every key) and
-// scatter (reads and writes every key, plus extra bytes per key).
-#define TRACED_PASS(kcount, kscatter, keys, extra, mode, a)                                     \
+// One radix pass of w-bit digits as two traced entries: counting (reads
+// every key) and scatter (reads and writes every key, plus extra bytes per
+// key).
+#define TRACED_PASS(kcount, kscatter, keys, extra, mode, a, w)                                  \
   do {                                                                                        \
     TRACED(kcount, keys, 8.0 * (keys),                                                        \
-           launch_sort_part(a, mode, c.items, c.rb, SORT_PART_COUNT, st));                    \
+           launch_sort_part(a, mode, c.items, (w), SORT_PART_COUNT, st));                     \
     TRACED(kscatter, keys, (16.0 + (extra)) * (keys),                                         \
-           launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                  \
+           launch_sort_part(a, mode, c.items, (w), SORT_PART_SCATTER, st));                   \
   } while (0)
 
 int grid_for(int64_t tiles, int cap) {
@@ -889,9 +890,9 @@ numbering:
     uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
     for (int p = 0; p < P_n; ++p) {
       SortLaunch a = c.sort_args(p == 0 ? nullptr : nbuf[(p - 1) & 1], nbuf[p & 1], TM_NSORT,
-                                 RANGE_NODE_KEYS, P_n, p, c.rb * p);
+                                 RANGE_NODE_KEYS, P_n, p, lsd_shift(64, c.rb, p));
       TRACED_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * N, 0.0, p == 0 ? SORT_NODE_FIRST : SORT_NODE,
-                  a);
+                  a, lsd_width(64, c.rb, p));
     }
     // the sorted keys are in B; the distinct keys go to A
     TraceMark m = trace_begin(st);
@@ -977,7 +978,7 @@ numbering:
   // The hash remap also counts the first edge pass's digits of every sort
   // tile (directed and multigraph keys, sort tiles that divide its tiles);
   // that pass then starts from its prefixes.
-  uint32_t *counts0 = hashed && !undirected && c.rb == FUSED_RADIX_BITS &&
+  uint32_t *counts0 = hashed && !undirected && lsd_width(2 * b_max, c.rb, 0) == FUSED_RADIX_BITS &&
                               REMAP_TILE % c.sort_tile == 0
                           ? c.counts
                           : nullptr;
@@ -996,8 +997,8 @@ numbering:
     const int P_n = lsd_passes(64, c.rb);
     for (int p = 0; p < P_n; ++p) {  // A -> B -> ...; an odd count ends in B
       SortLaunch a = c.sort_args(buf[p & 1], buf[(p + 1) & 1], TM_VSORT, RANGE_NODES, P_n, p,
-                                 c.rb * p);
-      TRACED_PASS(TK_VNODE_COUNT, TK_VNODE_SCATTER, sumV, 0.0, SORT_VNODE, a);
+                                 lsd_shift(64, c.rb, p));
+      TRACED_PASS(TK_VNODE_COUNT, TK_VNODE_SCATTER, sumV, 0.0, SORT_VNODE, a, lsd_width(64, c.rb, p));
     }
     TRACED(TK_HRANK, sumV, 20.0 * sumV,
            launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), buf[P_n & 1], hkeys, hrank,
@@ -1029,8 +1030,9 @@ numbering:
   }
   {
     for (int p = 0; p < P_e; ++p) {
+      const int w = lsd_width(2 * b_max, c.rb, p);
       SortLaunch a = c.sort_args(ebuf[p & 1], ebuf[(p + 1) & 1], TM_ESORT, erange, P_e, p,
-                                 c.rb * p);
+                                 lsd_shift(2 * b_max, c.rb, p));
       if (multi) {
         a.vin = vbuf[p & 1];
         a.vout = vbuf[(p + 1) & 1];
@@ -1038,11 +1040,11 @@ numbering:
       const int mode = multi ? SORT_EDGE_KV : SORT_EDGE;
       if (p == 0 && counts0) {  // tile counts written by the remap
         TRACED(TK_EDGE_COUNT, NE, 0.0,
-               launch_sort_part(a, mode, c.items, c.rb, SORT_PART_PREFIX, st));
+               launch_sort_part(a, mode, c.items, w, SORT_PART_PREFIX, st));
         TRACED(TK_EDGE_SCATTER, NE, (16.0 + (multi ? 8.0 : 0.0)) * NE,
-               launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));
+               launch_sort_part(a, mode, c.items, w, SORT_PART_SCATTER, st));
       } else {
-        TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a);
+        TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a, w);
       }
     }
   }
@@ -1057,7 +1059,8 @@ numbering:
     in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
     in0.seg_total = c.results + S;
     TRACED(TK_IN_COUNT, N, 8.0 * N,
-           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, lsd_width(b_max, c.rb, 0),
+                            SORT_PART_COUNT, st));
   } else if (multi) {
     // every row is an edge: offsets only, and the in-sort reads the sorted
     // keys in place
@@ -1133,13 +1136,14 @@ numbering:
     // out_nbr and out_off at the de-duplicated positions
     in0.gaps = c.gapq(1);
     TRACED(TK_IN_SCATTER, N, 8.0 * N + 12.0 * sumE + 8.0 * (sumV + S),
-           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
+           launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, lsd_width(b_max, c.rb, 0),
+                            SORT_PART_SCATTER, st));
     HIP_TRY(launch_gap_fill(in0.gaps, st));
     uint64_t *ib[2] = {ukeys, sorted_edges};
     for (int p = 1; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ib[(p - 1) & 1], ib[p & 1], TM_ISORT, RANGE_EDGES, P_in, p,
-                                 32 + c.rb * p);
-      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a);
+                                 32 + lsd_shift(b_max, c.rb, p));
+      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a, lsd_width(b_max, c.rb, p));
     }
     TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
     it.gaps = c.gapq(2);
@@ -1152,7 +1156,7 @@ numbering:
     uint32_t *ivb[2] = {uvals, multi ? vbuf[(P_e + 1) & 1] : nullptr};
     for (int p = 0; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ibuf[p & 1], ibuf[(p + 1) & 1], TM_ISORT, RANGE_EDGES, P_in, p,
-                                 32 + c.rb * p);
+                                 32 + lsd_shift(b_max, c.rb, p));
       int mode = p == 0 ? SORT_IN_FIRST : SORT_IN;
       if (multi) {
         a.vin = ivb[p & 1];
@@ -1160,7 +1164,7 @@ numbering:
         mode = p == 0 ? SORT_IN_FIRST_KV : SORT_IN_KV;
       }
       TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, (p == 0 ? 4.0 : 0.0) + (multi ? 8.0 : 0.0),
-                  mode, a);
+                  mode, a, lsd_width(b_max, c.rb, p));
     }
     TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
     it.gaps = c.gapq(2);
@@ -1352,11 +1356,11 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
     if (traced) TRACED(kind, units, bytes, expr);                \
     else HIP_TRY(expr);                                          \
   } while (0)
-#define FX_PASS(kcount, kscatter, keys, mode, a)                                                \
+#define FX_PASS(kcount, kscatter, keys, mode, a, w)                                             \
   do {                                                                                          \
-    FX(kcount, keys, 8.0 * (keys), launch_sort_part(a, mode, c.items, c.rb, SORT_PART_COUNT, st)); \
+    FX(kcount, keys, 8.0 * (keys), launch_sort_part(a, mode, c.items, (w), SORT_PART_COUNT, st)); \
     FX(kscatter, keys, 16.0 * (keys),                                                           \
-       launch_sort_part(a, mode, c.items, c.rb, SORT_PART_SCATTER, st));                        \
+       launch_sort_part(a, mode, c.items, (w), SORT_PART_SCATTER, st));                         \
   } while (0)
 
   HIP_TRY(launch_meta_init(m, nwords, (uint64_t *)c.meta, c.results, FIXED_RESULTS, st));
@@ -1373,8 +1377,9 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   uint64_t *nbuf[2] = {(P_n & 1) ? c.B : c.A, (P_n & 1) ? c.A : c.B};
   for (int q = 0; q < P_n; ++q) {
     SortLaunch a = c.sort_args(q == 0 ? nullptr : nbuf[(q - 1) & 1], nbuf[q & 1], TM_NSORT,
-                               RANGE_NODE_KEYS, P_n, q, c.rb * q);
-    FX_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * n, q == 0 ? SORT_NODE_FIRST : SORT_NODE, a);
+                               RANGE_NODE_KEYS, P_n, q, lsd_shift(64, c.rb, q));
+    FX_PASS(TK_NODE_COUNT, TK_NODE_SCATTER, 2 * n, q == 0 ? SORT_NODE_FIRST : SORT_NODE, a,
+            lsd_width(64, c.rb, q));
   }
   FX(TK_UNIQUE, 2 * n, 16.0 * n,
      launch_unique(c.tiles(TM_UNIQ, RANGE_NODE_KEYS), c.B, c.A, c.results, c.counts,
@@ -1393,8 +1398,8 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   const int P_in = lsd_passes(L.b, c.rb);
   for (int q = 0; q < P_e; ++q) {
     SortLaunch a = c.sort_args(ebuf[q & 1], ebuf[(q + 1) & 1], TM_ESORT, RANGE_ROWS, P_e, q,
-                               c.rb * q);
-    FX_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, n, SORT_EDGE, a);
+                               lsd_shift(2 * L.b, c.rb, q));
+    FX_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, n, SORT_EDGE, a, lsd_width(2 * L.b, c.rb, q));
   }
   uint64_t *sorted_edges = ebuf[P_e & 1];
   uint64_t *ukeys = ebuf[(P_e + 1) & 1];
@@ -1402,17 +1407,19 @@ ringo_status_t enqueue_fixed(const int64_t *src, const int64_t *dst, int64_t n, 
   SortLaunch in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
   in0.seg_total = c.results + 1;
   FX(TK_IN_COUNT, n, 8.0 * n,
-     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_COUNT, st));
+     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, lsd_width(L.b, c.rb, 0), SORT_PART_COUNT,
+                      st));
   FX(TK_PLAN, 1, 0.0, launch_plan_edges(plan_dev, c.results, ve, st));
   in0.gaps = gq(1);
   FX(TK_IN_SCATTER, n, 20.0 * n,
-     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, c.rb, SORT_PART_SCATTER, st));
+     launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, lsd_width(L.b, c.rb, 0), SORT_PART_SCATTER,
+                      st));
   HIP_TRY(launch_gap_fill(in0.gaps, st));
   uint64_t *ib[2] = {ukeys, sorted_edges};
   for (int q = 1; q < P_in; ++q) {
     SortLaunch a = c.sort_args(ib[(q - 1) & 1], ib[q & 1], TM_ISORT, RANGE_EDGES, P_in, q,
-                               32 + c.rb * q);
-    FX_PASS(TK_IN_COUNT, TK_IN_SCATTER, n, SORT_IN, a);
+                               32 + lsd_shift(L.b, c.rb, q));
+    FX_PASS(TK_IN_COUNT, TK_IN_SCATTER, n, SORT_IN, a, lsd_width(L.b, c.rb, q));
   }
   TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
   it.gaps = gq(2);

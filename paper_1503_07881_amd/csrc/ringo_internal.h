@@ -13,6 +13,22 @@ namespace ringo {
 constexpr int MIN_DIGIT_BITS = 8, MAX_DIGIT_BITS = 11, DEFAULT_DIGIT_BITS = 8;
 // LSD passes over the low `bits` bits of the keys with digits of rb bits.
 inline int lsd_passes(int bits, int rb) { return (bits + rb - 1) / rb; }
+// Digit width of pass p of an LSD sort of `bits`-bit keys in
+// lsd_passes(bits, rb) passes: where the passes' total width leaves room,
+// passes take 8-bit digits (a quarter or less of the counters per tile of
+// the wider ones), and those come first; the rest take rb bits.
+inline int lsd_width(int bits, int rb, int p) {
+  const int P = lsd_passes(bits, rb);
+  const int spare = bits - 8 * P;
+  const int wide = rb == 8 || spare <= 0 ? 0 : (spare + rb - 9) / (rb - 8);
+  return p < P - wide ? 8 : rb;
+}
+// Lowest key bit of pass p's digit.
+inline int lsd_shift(int bits, int rb, int p) {
+  int s = 0;
+  for (int q = 0; q < p; ++q) s += lsd_width(bits, rb, q);
+  return s;
+}
 // The remap's fused counts of the first edge pass are for 8-bit digits.
 constexpr int FUSED_RADIX_BITS = 8;
 constexpr int FUSED_RADIX = 1 << FUSED_RADIX_BITS;
