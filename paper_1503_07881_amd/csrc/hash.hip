@@ -28,6 +28,25 @@
 // array, so the probe phase walks a table half the size, and the remap reads
 // only the rank array, a quarter of it.
 //
+// Large tables probed often (partitioned numbering): a probe in row order
+// misses every cache once the table outgrows them, so the keys are first
+// grouped by the part of the table their home slot lies in (2^PART_BITS
+// contiguous parts), with the radix pass kernels:
+//   group rows   the rows by their source key's part, destination keys
+//                carried beside them (grouped sources, then destinations)
+//   group dst    the carried destination keys by their own part
+//   insert       both groupings, tiles in contiguous ranges per XCD, so the
+//                probes of one XCD meet one part at a time in its L2
+//   (compact, sort, rank as above), then every slot's (key, position) pair
+//   group rank   the grouping of the destination keys again, now carrying
+//                the position of the source key beside each (one 16-byte
+//                pair load per lookup, inside one part)
+//   pack         (source position, destination position) edge keys in the
+//                destinations' grouped order; the edge sort does not need
+//                row order
+// Multigraph edges keep their rows through the sorts, so they stay in row
+// order and take the remap.
+//
 // Keys are uint64(id) ^ 2^63 as in the sort-based path.  The key ~0 marks a
 // free slot; a table holding that key sets a flag instead (its elements get
 // the slot index NO_SLOT), and since ~0 is the largest key its position is
@@ -40,18 +59,7 @@
 
 namespace ringo {
 
-constexpr uint32_t MAX_PROBES = 4096;
 constexpr uint32_t NO_SLOT = 0xffffffffu;
-
-// MurmurHash3's 64-bit finaliser (Appleby): a bijection with full avalanche.
-__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ull;
-  k ^= k >> 33;
-  return k;
-}
 
 // ------------------------------------------------------------- estimate
 
@@ -226,6 +234,195 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
     }
     if (flag) atomicOr(&flags[seg], flag);
   }
+}
+
+// ------------------------------------------------- partitioned numbering
+//
+// With the keys grouped by the part of the table their home slot lies in,
+// the blocks of one XCD walk a contiguous range of tiles (blocks go to the
+// XCDs round-robin, and the grid is a multiple of their count), so the
+// probes of that XCD meet one part of the table at a time, which stays in
+// its L2.
+
+__device__ __forceinline__ int64_t xcd_first_tile(int64_t total) {
+  return total * (blockIdx.x % NUM_XCD) / NUM_XCD + blockIdx.x / NUM_XCD;
+}
+__device__ __forceinline__ int64_t xcd_end_tile(int64_t total) {
+  return total * (blockIdx.x % NUM_XCD + 1) / NUM_XCD;
+}
+inline int xcd_grid(int grid) { return std::max(NUM_XCD, grid / NUM_XCD * NUM_XCD); }
+
+// The insert of k_hash_insert over grouped keys, with no slots written.
+__global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const uint64_t *keys,
+                                                          uint64_t *hkeys, uint32_t *flags) {
+  const int tid = threadIdx.x;
+  const int64_t t_end = xcd_end_tile(t.total_tiles);
+  for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    uint64_t *T = hkeys + P.tab_off;
+    const uint64_t *K = keys + P.row_off;
+    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t max_probes = (uint32_t)std::min<int64_t>(P.tab_cap, MAX_PROBES);
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    uint32_t flag = 0;
+    constexpr int U = 8;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t u[U], pos[U];
+      uint32_t left[U];
+      bool act[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) u[j] = G(K)[std::min<int64_t>(r0 + j * 256, end - 1)];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const bool valid = r0 + j * 256 < end;
+        if (valid && u[j] == EMPTY_KEY) flag |= HFLAG_MAX_KEY;
+        act[j] = valid && u[j] != EMPTY_KEY;
+        pos[j] = fmix64(u[j]) & mask;
+        left[j] = max_probes;
+      }
+      bool more = true;
+      bool first = true;
+      while (more) {
+        uint64_t k[U];
+        if (first) {
+#pragma unroll
+          for (int j = 0; j < U; ++j) k[j] = G(T)[pos[j]];
+          first = false;
+        } else {
+#pragma unroll
+          for (int j = 0; j < U; ++j) k[j] = act[j] ? G(T)[pos[j]] : 0ull;
+        }
+        more = false;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          if (!act[j]) continue;
+          uint64_t seen = k[j];
+          if (seen == EMPTY_KEY) seen = atomicCAS((unsigned long long *)&T[pos[j]],
+                                                  (unsigned long long)EMPTY_KEY,
+                                                  (unsigned long long)u[j]);
+          if (seen == EMPTY_KEY || seen == u[j]) {
+            act[j] = false;
+          } else if (--left[j] == 0) {
+            flag |= HFLAG_OVERFLOW;
+            act[j] = false;
+          } else {
+            pos[j] = (pos[j] + 1) & mask;
+            more = true;
+          }
+        }
+      }
+    }
+    if (flag) atomicOr(&flags[seg], flag);
+  }
+}
+
+hipError_t launch_hash_insert_keys(const TileLaunch &rows, const uint64_t *keys, uint64_t *hkeys,
+                                   uint32_t *flags, int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_insert_keys, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, keys, hkeys,
+                     flags);
+  return hipGetLastError();
+}
+
+// Edge keys from the grouped destination keys and the source positions
+// beside them; the counts of the first edge pass as in k_hash_remap.
+__global__ __launch_bounds__(256) void k_hash_pairs(TileLaunch t, const uint64_t *hkeys,
+                                                    const uint32_t *hrank, uint64_t *pairs) {
+  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const int64_t base = P.tab_off + (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
+    const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.tab_off + P.tab_cap);
+    __attribute__((address_space(1))) u64x2 *out = (__attribute__((address_space(1))) u64x2 *)G(pairs);
+    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
+      u64x2 e;
+      e.x = G(hkeys)[j];
+      e.y = G(hrank)[j];
+      out[j] = e;
+    }
+  }
+}
+
+hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys,
+                             const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s) {
+  if (slot_tiles.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_pairs, dim3(grid), dim3(256), 0, s, slot_tiles, hkeys, hrank, pairs);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uint64_t *dkeys,
+                                                         const uint32_t *spos,
+                                                         const uint64_t *hpairs, uint64_t *ekeys,
+                                                         int sym, uint32_t *counts0, int sort_tile,
+                                                         const int64_t *esort_tmap) {
+  constexpr int MAX_SUB = REMAP_TILE / 2048;  // sort tiles of at least 2048 keys
+  __shared__ uint32_t s_c[MAX_SUB * FUSED_RADIX];
+  const int tid = threadIdx.x;
+  const int nsub = counts0 ? REMAP_TILE / sort_tile : 0;
+  for (int i = tid; i < nsub * FUSED_RADIX; i += 256) s_c[i] = 0;
+  __syncthreads();
+  const int64_t t_end = xcd_end_tile(t.total_tiles);
+  for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint64_t *TP = hpairs + 2 * P.tab_off;
+    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t last = (uint32_t)(P.V - 1);
+    const int b = P.b;
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    constexpr int U = 8;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t u[U];
+      uint32_t rs[U], rd[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int64_t r = P.row_off + std::min<int64_t>(r0 + j * 256, end - 1);
+        u[j] = G(dkeys)[r];
+        rs[j] = G(spos)[r];
+      }
+      key_ranks<U>(TP, mask, u, last, rd);
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end) {
+          const uint64_t key = ((uint64_t)rs[j] << b) | rd[j];
+          if (sym) {  // both orientations, 2n keys at 2 * row_off
+            G(ekeys)[2 * P.row_off + r0 + j * 256] = key;
+            G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rd[j] << b) | rs[j];
+          } else {
+            G(ekeys)[P.row_off + r0 + j * 256] = key;
+            if (counts0)
+              atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * FUSED_RADIX +
+                             (uint32_t)(key & (FUSED_RADIX - 1))], 1u);
+          }
+        }
+    }
+    if (counts0) {
+      __syncthreads();
+      const int64_t first = (tile - t.tmap[seg]) * nsub;
+      for (int i = tid; i < nsub * FUSED_RADIX; i += 256) {
+        const int st = i / FUSED_RADIX;
+        if ((first + st) * sort_tile < P.n)
+          G(counts0)[(esort_tmap[seg] + first + st) * FUSED_RADIX + i % FUSED_RADIX] = s_c[i];
+        s_c[i] = 0;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint64_t *dkeys,
+                                  const uint32_t *spos, const uint64_t *hpairs, uint64_t *ekeys, int sym,
+                                  uint32_t *counts0, int sort_tile, const int64_t *esort_tmap,
+                                  int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  if (counts0 && (sym || sort_tile < 2048 || REMAP_TILE % sort_tile != 0))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hash_pack_parts, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, dkeys, spos,
+                     hpairs, ekeys, sym, counts0, sort_tile, esort_tmap);
+  return hipGetLastError();
 }
 
 // Exclusive scan of the bucket counts (bstart [NBUCKETS + 1], bcur a copy of

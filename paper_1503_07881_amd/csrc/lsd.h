@@ -34,15 +34,39 @@
 
 namespace ringo {
 
-constexpr int NUM_XCD = 8;    // accelerator complex dies of the MI355X
 // s_waitcnt immediate: lgkmcnt(0), vmcnt and expcnt left at their maxima
 constexpr int LGKMCNT_0 = 0xC07F;
+
+template <int MODE>
+constexpr bool part_mode() {
+  return MODE == SORT_PART_ROWS || MODE == SORT_PART_DST || MODE == SORT_PART_RANK;
+}
+
+// Digit of key k in the pass: bits [shift, shift + RB) of the key, or
+// (partition passes) the part of its table of 2^lcap slots that holds the
+// key's home slot.
+template <int MODE, int RB>
+__device__ __forceinline__ uint32_t key_digit(uint64_t k, int shift, int lcap) {
+  if constexpr (part_mode<MODE>()) {
+    static_assert(RB == PART_BITS, "partition passes have PART_BITS-bit digits");
+    return slot_part(k, lcap);
+  } else {
+    return (uint32_t)(k >> shift) & ((1u << RB) - 1);
+  }
+}
+
+// log2 of a table's node hash table slots (partition passes).
+__device__ __forceinline__ int table_lcap(const SegPlan &P) {
+  return __builtin_ctzll((uint64_t)P.tab_cap | (1ull << 62));
+}
 
 // The key of element e of a table's range, as the pass sorts it.
 template <int MODE>
 __device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan &P, int64_t start,
                                              int64_t e) {
-  if (MODE == SORT_NODE_FIRST) {
+  if (MODE == SORT_PART_ROWS) {
+    return (uint64_t)G(P.src)[e] ^ SIGN_FLIP;
+  } else if (MODE == SORT_NODE_FIRST) {
     // one load from a selected pointer: no branch, so loads stay in flight
     const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? G(P.src) + e : G(P.dst) + (e - P.n);
     return (uint64_t)*ptr ^ SIGN_FLIP;
@@ -108,7 +132,8 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
   typedef SubBin<SUB> Bin;
   // the passes that read their keys from elsewhere, or compare neighbours
   constexpr bool FIRST = MODE == SORT_NODE_FIRST || MODE == SORT_IN_FIRST ||
-                         MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_FIRST_DEDUP;
+                         MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_FIRST_DEDUP ||
+                         MODE == SORT_PART_ROWS;
   __shared__ typename Bin::T s_hb[W * R];
   uint32_t *s_h = (uint32_t *)s_hb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -127,6 +152,7 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
     __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
     __builtin_amdgcn_wave_barrier();
     H.at(a, t);
+    const int lcap = part_mode<MODE>() ? table_lcap(H.P) : 0;
     const int64_t k0 = (t - H.first) * tile_keys;
     // a tile past the table's key count (tile maps sized for the worst case,
     // the count set on the device) is empty
@@ -145,12 +171,12 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
 #pragma unroll
         for (int j = 0; j < U2; ++j)
           if (q0 + j * 64 < np) {
-            atomicAdd(&h[((uint32_t)(k[j].x >> shift) & (R - 1)) * SUB], 1u);
-            atomicAdd(&h[((uint32_t)(k[j].y >> shift) & (R - 1)) * SUB], 1u);
+            atomicAdd(&h[key_digit<MODE, RB>(k[j].x, shift, lcap) * SUB], 1u);
+            atomicAdd(&h[key_digit<MODE, RB>(k[j].y, shift, lcap) * SUB], 1u);
           }
       }
       if ((cnt & 1) && lane == 0)
-        atomicAdd(&h[((uint32_t)(G(a.in)[H.start + k1 - 1] >> shift) & (R - 1)) * SUB], 1u);
+        atomicAdd(&h[key_digit<MODE, RB>(G(a.in)[H.start + k1 - 1], shift, lcap) * SUB], 1u);
     } else {
       for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
         uint64_t k[U];
@@ -168,7 +194,7 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
             if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
             valid = valid && (e == 0 || k[j] != prev);
           }
-          if (valid) atomicAdd(&h[((uint32_t)(k[j] >> shift) & (R - 1)) * SUB], 1u);
+          if (valid) atomicAdd(&h[key_digit<MODE, RB>(k[j], shift, lcap) * SUB], 1u);
         }
       }
     }
@@ -327,6 +353,7 @@ __global__ __launch_bounds__(256) void k_seg_base(SortLaunch a) {
 constexpr int ds_waves(int items, int mode, int rb) {
   return mode == SORT_IN_FIRST_DEDUP
              ? (items <= 8 ? (rb <= 9 ? 3 : 2) : items <= 12 ? 2 : (rb <= 9 ? 2 : 1))
+         : (mode == SORT_PART_ROWS || mode == SORT_PART_RANK) ? (items <= 8 ? 3 : 2)
          : (mode == SORT_EDGE_KV || mode == SORT_IN_FIRST_KV || mode == SORT_IN_KV)
              ? (items <= 8 ? (rb <= 9 ? 4 : 3) : items <= 12 ? (rb <= 9 ? 3 : 2) : 2)
              : (items <= 8 ? (rb <= 10 ? 4 : 3) : items <= 12 || rb == 8 ? 3 : 2);
@@ -339,7 +366,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   static_assert(R % BLOCK == 0, "whole digits per thread");
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
-  constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV;
+  // RANKV: the staged values are the looked-up source positions, and only
+  // they are written; WIDE: 64-bit destination keys carried with the keys
+  constexpr bool RANKV = MODE == SORT_PART_RANK;
+  constexpr bool WIDE = MODE == SORT_PART_ROWS;
+  constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV || RANKV;
   constexpr bool DEDUP = MODE == SORT_IN_FIRST_DEDUP;
   constexpr bool IN_FIRST = MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV;
   // Per-wave digit counts, then slot bases; they never exceed TILE, so
@@ -348,6 +379,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   static_assert(TILE < 65536, "16-bit slot bases");
   __shared__ uint64_t s_stage[TILE];
   __shared__ uint32_t s_vstage[KV ? TILE : 1];
+  __shared__ uint64_t s_wstage[WIDE ? TILE : 1];
   __shared__ hist_t s_whist[WAVES * R];
   __shared__ int64_t s_goff[R];
   __shared__ uint32_t s_w[WAVES];
@@ -356,6 +388,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
   TileHeader H;
+  int lcap = 0;          // partition passes: log2 of the table's slots
   int64_t dbase[DPT];    // this thread's digits: first output position in the table
   uint32_t pfirst[DPT];  // prefix of the table's first tile
 #pragma unroll
@@ -377,6 +410,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
        tile += per) {
     if (tile >= H.end) {
       H.at(a, tile);
+      if (part_mode<MODE>()) lcap = table_lcap(H.P);
 #pragma unroll
       for (int j = 0; j < DPT; ++j) {
         const int d = tid * DPT + j;
@@ -396,11 +430,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     // wait.
     uint64_t keys[ITEMS];
     uint32_t vals[KV ? ITEMS : 1];
+    uint64_t wv[WIDE ? ITEMS : 1];
+    uint64_t xs[RANKV ? ITEMS : 1];  // RANKV: the source keys at the same places
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
-      keys[i] = pass_key<MODE>(a, H.P, H.start, base + (idx < cnt ? idx : 0));
-      if (KV) vals[KV ? i : 0] = G(a.vin)[H.start + base + (idx < cnt ? idx : 0)];
+      const int64_t e = base + (idx < cnt ? idx : 0);
+      keys[i] = pass_key<MODE>(a, H.P, H.start, e);
+      if (KV && !RANKV) vals[KV ? i : 0] = G(a.vin)[H.start + e];
+      if (WIDE) wv[WIDE ? i : 0] = (uint64_t)G(H.P.dst)[e] ^ SIGN_FLIP;
+      if (RANKV) xs[RANKV ? i : 0] = G(a.win)[H.start + e];
     }
     // This tile's digit counts are the differences of its prefixes and the
     // next tile's (the last tile's next row is the scan's sentinel row).
@@ -431,6 +470,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         ls += dcnt[j];
       }
     }
+    if constexpr (RANKV)
+      key_ranks<ITEMS>(a.hpairs + 2 * H.P.tab_off, (uint64_t)H.P.tab_cap - 1, xs,
+                       (uint32_t)(H.P.V - 1), vals);
     uint32_t dpos = 0;  // DEDUP: de-duplicated position of this wave's first live key
     if (DEDUP) {
       // the table's live keys in earlier tiles (the digit prefixes summed)
@@ -475,12 +517,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     if (DEDUP && lane == 0) s_wu[DEDUP ? wave : 0] = wave_live;
 
     // Stable rank inside the wave: lanes with an equal digit are found with
-    // RB ballots; the lowest such lane bumps the wave's digit count.
+    // RB ballots; the lowest such lane bumps the wave's digit count.  The
+    // partition passes keep each key's digit (a hash) beside its rank, in
+    // the upper 16 bits.
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const bool valid = (live_bits >> i) & 1u;
-      const uint32_t d = (uint32_t)(keys[i] >> shift) & (R - 1);
+      const uint32_t d = key_digit<MODE, RB>(keys[i], shift, lcap);
       uint64_t m = __ballot(valid);
 #pragma unroll
       for (int bit = 0; bit < RB; ++bit) {
@@ -495,7 +539,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         if (below == 0) s_whist[wave * R + d] = (hist_t)(old + (uint32_t)__popcll(m));
         rk = old + below;
       }
-      rank[i] = rk;
+      rank[i] = part_mode<MODE>() ? rk | d << 16 : rk;
     }
     __syncthreads();
 
@@ -522,10 +566,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       if ((live_bits >> i) & 1u) {
-        const uint32_t d = (uint32_t)(keys[i] >> shift) & (R - 1);
-        const uint32_t slot = (uint32_t)s_whist[wave * R + d] + rank[i];
+        const uint32_t d = part_mode<MODE>() ? rank[i] >> 16 : key_digit<MODE, RB>(keys[i], shift, lcap);
+        const uint32_t slot = (uint32_t)s_whist[wave * R + d] + (rank[i] & 0xffffu);
         s_stage[slot] = keys[i];
         if (KV) s_vstage[KV ? slot : 0] = vals[KV ? i : 0];
+        if (WIDE) s_wstage[WIDE ? slot : 0] = wv[WIDE ? i : 0];
       }
     }
     if (DEDUP) {
@@ -560,10 +605,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       const int p = i * BLOCK + tid;
       if (p < (int)tile_total) {
         const uint64_t k = s_stage[p];
-        const int64_t pos = s_goff[(uint32_t)(k >> shift) & (R - 1)] + p;
+        const int64_t pos = s_goff[key_digit<MODE, RB>(k, shift, lcap)] + p;
         if ((uint64_t)(pos - H.start) < (uint64_t)H.count) {  // in range by construction
-          G(a.out)[pos] = k;
+          if (!RANKV) G(a.out)[pos] = k;
           if (KV) G(a.vout)[pos] = s_vstage[KV ? p : 0];
+          if (WIDE) G(a.wout)[pos] = s_wstage[WIDE ? p : 0];
         }
       }
     }
@@ -638,6 +684,16 @@ static hipError_t launch_pass_items(const SortLaunch &a, int mode, int parts, hi
     case SORT_IN_FIRST_KV: return launch_pass_t<ITEMS, SORT_IN_FIRST_KV, RB>(a, parts, s);
     case SORT_IN_KV: return launch_pass_t<ITEMS, SORT_IN_KV, RB>(a, parts, s);
     case SORT_IN_FIRST_DEDUP: return launch_pass_t<ITEMS, SORT_IN_FIRST_DEDUP, RB>(a, parts, s);
+    case SORT_PART_ROWS:
+    case SORT_PART_DST:
+    case SORT_PART_RANK:
+      if constexpr (RB == PART_BITS) {
+        if (mode == SORT_PART_ROWS) return launch_pass_t<ITEMS, SORT_PART_ROWS, RB>(a, parts, s);
+        if (mode == SORT_PART_DST) return launch_pass_t<ITEMS, SORT_PART_DST, RB>(a, parts, s);
+        return launch_pass_t<ITEMS, SORT_PART_RANK, RB>(a, parts, s);
+      } else {
+        return hipErrorInvalidValue;  // partition passes have PART_BITS-bit digits
+      }
     default: return launch_pass_t<ITEMS, SORT_PLAIN, RB>(a, parts, s);
   }
 }

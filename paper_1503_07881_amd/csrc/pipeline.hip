@@ -321,11 +321,29 @@ int64_t table_capacity(int64_t est, int64_t rows) {
   return cap;
 }
 
+// Whether a call's node hash tables (slots in all, for rows in all) are
+// filled and read through keys grouped by table part (partitioned
+// numbering).  Grouping costs two passes over the rows and saves on every
+// probe that would miss the caches, so it pays for large tables probed
+// often: measured faster on R-MAT tables from 2^24 slots at 16 or more rows
+// per slot (2^28 rows 34.8 against 35.7 ms, 2^30 rows 151 against 159 ms),
+// slower below 2^24 slots (2^27 rows 16.9 against 16.1 ms) and on uniform
+// tables with fewer rows per slot (2^28 rows over 2^26 slots 55.5 against
+// 51.1 ms).  RINGO_HASH_PARTS=0 or 1 (test support) turns it off or on for
+// every size.
+constexpr int64_t PART_MIN_SLOTS = (int64_t)1 << 24;
+constexpr int64_t PART_MIN_ROWS_PER_SLOT = 16;
+bool parts_for(int64_t slots, int64_t rows) {
+  const char *e = std::getenv("RINGO_HASH_PARTS");
+  if (e && *e) return std::atoi(e) != 0;
+  return slots >= PART_MIN_SLOTS && rows >= PART_MIN_ROWS_PER_SLOT * slots;
+}
+
 // ----------------------------------------------------------- tile maps
 
 enum TileKind {
   TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR,
-  TM_HLL, TM_HCMP, TM_VSORT, TM_KINDS
+  TM_HLL, TM_HCMP, TM_VSORT, TM_PART, TM_KINDS
 };
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -348,6 +366,9 @@ struct Call {
   DirEntry *dir = nullptr;
   void *tab = nullptr;    // node hash tables: keys, then ranks
   uint32_t *hslots = nullptr;  // slot of every node key
+  uint64_t *px = nullptr;  // partitioned numbering: rows grouped by source part (keys, then dst)
+  uint64_t *py = nullptr;  // destination keys grouped by part, then source positions (32-bit)
+  void *pcnt = nullptr;    // tile prefixes and digit bases of the destination keys' grouping
   uint32_t *vals = nullptr;    // multigraph: rows carried through the sorts (2 x N)
   int kind = RINGO_GRAPH_DIRECTED;
   // small tables converted in LDS (one workgroup each)
@@ -418,8 +439,10 @@ struct Call {
 
   void release_workspace() {
     void *bufs[] = {A, B, base, results, meta, dir, tab, hslots, hmeta, counts,
-                    bsum, vals, small_ws, gaps};
+                    bsum, vals, small_ws, gaps, px, py, pcnt};
     for (void *b : bufs) dev_free(hooks, b, stream);
+    px = py = nullptr;
+    pcnt = nullptr;
     small_ws = nullptr;
     gaps = nullptr;
     if (spin) pinned_release(spin, stream);
@@ -506,8 +529,21 @@ struct Call {
     a.vin = nullptr;
     a.vout = nullptr;
     a.seg_total = nullptr;
+    a.wout = nullptr;
+    a.win = nullptr;
+    a.hpairs = nullptr;
     return a;
   }
+  // Grouping of the destination keys by table part (partitioned numbering),
+  // with prefixes and digit bases of its own, which the rank pass reuses.
+  SortLaunch part_dst_args() {
+    SortLaunch a = sort_args(px + plan_rows(), py, TM_PART, RANGE_ROWS, 1, 0, 0);
+    a.counts = (uint32_t *)pcnt;
+    a.digit_base = (int64_t *)((char *)pcnt + align_up(sizeof(uint32_t) * (1 << PART_BITS) *
+                                                        (total(TM_NSORT) + 1)));
+    return a;
+  }
+  int64_t plan_rows() const { return S > 0 ? plan[S - 1].row_off + plan[S - 1].n : 0; }
 };
 
 
@@ -527,7 +563,7 @@ enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
   TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_GRAPH,
-  TK_KINDS
+  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -537,7 +573,8 @@ const char *const kTraceNames[TK_KINDS] = {
     "sort_in_count",     "sort_in_scatter",   "in_csr",          "aux",
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
-    "hash_bucket_sort", "plan_device", "fixed_graph_replay"};
+    "hash_bucket_sort", "plan_device", "fixed_graph_replay", "hash_part_count",
+    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs"};
 
 struct TraceRec {
   int kind;
@@ -803,6 +840,8 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   uint64_t *hkeys = nullptr;
   uint32_t *hrank = nullptr;
   uint32_t *hflags = nullptr;
+  bool parted = false;  // partitioned numbering
+  uint64_t *hpairs = nullptr;
   // one table: its distinct keys are placed by bucket of their top bits, and
   // sorted bucket by bucket in LDS when no bucket exceeds BUCKET_CAP keys
   const bool bucket_place = want_hash && S == 1;
@@ -849,18 +888,53 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       p.tab_cap = p.n > 0 ? table_capacity(est[i], p.n) : 0;
       slots += p.tab_cap;
     }
+    // Partitioned numbering (not for multigraphs, whose edges keep their row
+    // order): the rows are grouped by the table part of their source key,
+    // with the destination keys beside them, and the destination keys again
+    // by theirs; both groupings are inserted, so that the probes of the
+    // blocks of one XCD meet one part of the table at a time.
+    parted = c.kind != RINGO_GRAPH_MULTI && parts_for(slots, N);
     const size_t key_bytes = align_up(sizeof(uint64_t) * std::max<int64_t>(slots, 1));
-    c.tab = dev_alloc(c.hooks, key_bytes + sizeof(uint32_t) * std::max<int64_t>(slots, 1), st);
-    c.hslots = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 2 * std::max<int64_t>(N, 1), st);
-    if (!c.tab || !c.hslots) return RINGO_ERR_OUT_OF_MEMORY;
+    const size_t rank_bytes = align_up(sizeof(uint32_t) * std::max<int64_t>(slots, 1));
+    // partitioned: the (key, position) pairs after the ranks
+    c.tab = dev_alloc(c.hooks, key_bytes + rank_bytes + (parted ? 2 * key_bytes : 0), st);
+    if (parted) {
+      c.px = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * std::max<int64_t>(N, 1), st);
+      c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + sizeof(uint32_t)) *
+                                                std::max<int64_t>(N, 1), st);
+      // the node pass's tile count bounds the grouping's (n keys per table)
+      c.pcnt = dev_alloc(c.hooks, align_up(sizeof(uint32_t) * (1 << PART_BITS) * max_tiles) +
+                                      sizeof(int64_t) * S * (1 << PART_BITS), st);
+      if (!c.tab || !c.px || !c.py || !c.pcnt) return RINGO_ERR_OUT_OF_MEMORY;
+    } else {
+      c.hslots = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 2 * std::max<int64_t>(N, 1), st);
+      if (!c.tab || !c.hslots) return RINGO_ERR_OUT_OF_MEMORY;
+    }
     hkeys = (uint64_t *)c.tab;
     hrank = (uint32_t *)((char *)c.tab + key_bytes);
+    hpairs = parted ? (uint64_t *)((char *)c.tab + key_bytes + rank_bytes) : nullptr;
     c.set_tiles(TM_HCMP, RANGE_SLOTS, SCAN_TILE);
+    if (parted) c.set_tiles(TM_PART, RANGE_ROWS, c.sort_tile);
     HIP_TRY(c.upload());
     HIP_TRY(launch_fill_u64(hkeys, EMPTY_KEY, slots, st));
-    TRACED(TK_HINSERT, 2 * N, 24.0 * N,
-           launch_hash_insert(c.tiles(TM_REMAP, RANGE_ROWS), hkeys, c.hslots, hflags,
-                              grid_for(c.total(TM_REMAP), cus * 8), st));
+    if (parted) {
+      SortLaunch a = c.sort_args(nullptr, c.px, TM_PART, RANGE_ROWS, 1, 0, 0);
+      a.wout = c.px + N;
+      TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 16.0, SORT_PART_ROWS, a, PART_BITS);
+      // its prefixes are kept for the rank pass, which groups the same keys
+      SortLaunch d = c.part_dst_args();
+      TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 0.0, SORT_PART_DST, d, PART_BITS);
+      TRACED(TK_HINSERT, N, 16.0 * N,
+             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, hflags,
+                                     grid_for(c.total(TM_REMAP), cus * 8), st));
+      TRACED(TK_HINSERT, N, 16.0 * N,
+             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.py, hkeys, hflags,
+                                     grid_for(c.total(TM_REMAP), cus * 8), st));
+    } else {
+      TRACED(TK_HINSERT, 2 * N, 24.0 * N,
+             launch_hash_insert(c.tiles(TM_REMAP, RANGE_ROWS), hkeys, c.hslots, hflags,
+                                grid_for(c.total(TM_REMAP), cus * 8), st));
+    }
     {
       TraceMark m = trace_begin(st);
       HIP_TRY(launch_hash_compact(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, c.A, hcount, hflags,
@@ -877,8 +951,12 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       // a table overflowed its probe bound: number the nodes by sorting
       dev_free(c.hooks, c.tab, st);
       dev_free(c.hooks, c.hslots, st);
+      dev_free(c.hooks, c.px, st);
+      dev_free(c.hooks, c.py, st);
       c.tab = nullptr;
       c.hslots = nullptr;
+      c.px = c.py = nullptr;
+      parted = false;
       HIP_TRY(launch_fill_u64((uint64_t *)c.results, 0, 2 * S, st));
     }
   }
@@ -989,10 +1067,6 @@ numbering:
   if (hashed && bucketed) {
     TRACED(TK_HBSORT, sumV, 24.0 * sumV,
            launch_bucket_sort(c.plan_dev(), bkl, c.A, hflags, hrank, st));
-    TRACED(TK_HREMAP, N, 16.0 * N,
-           launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
-                             counts0, c.sort_tile, c.tm_dev(TM_ESORT),
-                             grid_for(c.total(TM_REMAP), cus * 8), st));
   } else if (hashed) {
     const int P_n = lsd_passes(64, c.rb);
     for (int p = 0; p < P_n; ++p) {  // A -> B -> ...; an odd count ends in B
@@ -1003,6 +1077,30 @@ numbering:
     TRACED(TK_HRANK, sumV, 20.0 * sumV,
            launch_hash_rank(c.tiles(TM_DIR, RANGE_NODES), buf[P_n & 1], hkeys, hrank,
                             grid_for(c.total(TM_DIR), cus * 8), st));
+  }
+  if (hashed && parted) {
+    // source positions, grouped as the destination keys are (the same
+    // stable grouping again), then the destination keys' positions beside
+    // them make the edge keys
+    TRACED(TK_HPAIRS, slots, 28.0 * slots,
+           launch_hash_pairs(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, hrank, hpairs,
+                             grid_for(c.total(TM_HCMP), cus * 8), st));
+    uint32_t *spos = (uint32_t *)(c.py + N);
+    SortLaunch a = c.part_dst_args();
+    a.out = nullptr;
+    a.win = c.px;
+    a.vout = spos;
+    a.hpairs = hpairs;
+    TRACED(TK_HPART_RANK, N, 28.0 * N,
+           launch_sort_part(a, SORT_PART_RANK, c.items, PART_BITS, SORT_PART_SCATTER, st));
+    TRACED(TK_HPACK, N, (undirected ? 36.0 : 28.0) * N,
+           launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), c.py, spos, hpairs, c.B,
+                                  undirected, counts0, c.sort_tile, c.tm_dev(TM_ESORT),
+                                  grid_for(c.total(TM_REMAP), cus * 8), st));
+    dev_free(c.hooks, c.px, st);
+    dev_free(c.hooks, c.py, st);
+    c.px = c.py = nullptr;
+  } else if (hashed) {
     TRACED(TK_HREMAP, N, 16.0 * N,
            launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
                              counts0, c.sort_tile, c.tm_dev(TM_ESORT),

@@ -139,6 +139,12 @@ struct SortLaunch {
   uint32_t *vout;
   int64_t *seg_total;         // if set, the count part writes each table's key total
   GapQueue gaps;              // long runs of the out-offsets (first in-pass with dedupe)
+  // partition passes (SORT_PART_*): the destination keys carried beside the
+  // source keys, and the (key, position) pairs of the node hash tables that
+  // the rank pass looks keys up in
+  uint64_t *wout;
+  const uint64_t *win;
+  const uint64_t *hpairs;
 };
 
 // Key source of a pass: the two first passes read their keys from elsewhere
@@ -154,7 +160,16 @@ enum SortMode : int {
   // first in-pass over the sorted edge keys with their repeats: only the
   // first copy of each key is sorted, and the pass also writes out_nbr and
   // out_off at the de-duplicated positions (dedupe folded into the pass)
-  SORT_IN_FIRST_DEDUP = 10
+  SORT_IN_FIRST_DEDUP = 10,
+  // Partition passes of the partitioned hash numbering (PART_BITS-bit
+  // digits: the part of the table a key's home slot lies in).  ROWS: the
+  // rows' source keys (uint64(id) ^ 2^63, grouped by their part) to out,
+  // their destination keys beside them to wout.  DST: the keys of in (the
+  // grouped destination keys) by their part.  RANK: the same grouping as
+  // DST, which it repeats, but what it writes (to vout) is the position of
+  // the source key at the same place in win, looked up in the tables'
+  // pairs hpairs (probes stay inside one part while win is grouped).
+  SORT_PART_ROWS = 11, SORT_PART_DST = 12, SORT_PART_RANK = 13
 };
 enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2, SORT_PART_PREFIX = 4 };
 
@@ -216,6 +231,12 @@ constexpr int HLL_TILE = 256 * 64;           // rows per estimate tile
 constexpr uint64_t EMPTY_KEY = ~0ull;        // free slot (the key ~0 is flagged aside)
 constexpr uint32_t HFLAG_MAX_KEY = 1;        // the table holds the key ~0
 constexpr uint32_t HFLAG_OVERFLOW = 2;       // a probe sequence exceeded its bound
+constexpr int NUM_XCD = 8;                   // accelerator complex dies of the MI355X
+constexpr uint32_t MAX_PROBES = 4096;        // probe bound of the insert (and of lookups)
+// Parts of a node hash table for the partitioned numbering: keys grouped by
+// the part of the table their home slot lies in (top PART_BITS bits of the
+// slot index) meet only that part's slots, a slice small enough for L2.
+constexpr int PART_BITS = 8;
 
 // regs [S][HLL_M] must start at zero; est[S] receives the distinct-count
 // estimate of each table's 2n keys.
@@ -263,6 +284,23 @@ hipError_t launch_hash_rank(const TileLaunch &nodes_t, const uint64_t *sorted,
 hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, const uint32_t *hrank,
                              uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
                              const int64_t *esort_tmap, int grid, hipStream_t s);
+// Partitioned numbering.  Inserts the n keys of each table at keys +
+// row_off (uint64(id) ^ 2^63, grouped by part) into its table; flags as for
+// launch_hash_insert, no slots written.
+hipError_t launch_hash_insert_keys(const TileLaunch &rows, const uint64_t *keys, uint64_t *hkeys,
+                                   uint32_t *flags, int grid, hipStream_t s);
+// (key, position) pairs of every slot (pairs: 2 words per slot, at 2 *
+// tab_off per table) from hkeys and hrank, for lookups by key with one load.
+hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys,
+                             const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s);
+// Packed edge keys from the grouped destination keys (dkeys + row_off) and
+// the source positions at the same places (spos + row_off): each
+// destination key's position is looked up in its table's pairs; sym and
+// counts0 as for launch_hash_remap.
+hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint64_t *dkeys,
+                                  const uint32_t *spos, const uint64_t *hpairs, uint64_t *ekeys, int sym,
+                                  uint32_t *counts0, int sort_tile, const int64_t *esort_tmap,
+                                  int grid, hipStream_t s);
 
 // Multigraph: out-offsets of the sorted keys (every key its own edge) and
 // each table's edge count (its key count) into seg_count.

@@ -29,14 +29,17 @@ def cuda():
     return torch.device("cuda:0")
 
 
-@pytest.fixture(params=["sort", "hash"])
+@pytest.fixture(params=["sort", "hash", "hash_parts"])
 def method(request):
     """Runs the test once per node-numbering method (every size bucket set to
-    it), restoring the library's schedule afterwards."""
+    it), restoring the library's schedule afterwards.  hash_parts is the hash
+    numbering through keys grouped by table part, at every table size."""
     from paper_1503_07881_amd import ringo
     saved = [ringo.tune_get(1 << e) for e in range(63)]
-    ringo.set_node_method(ringo.NODES_HASH if request.param == "hash" else ringo.NODES_SORT)
+    ringo.set_node_method(ringo.NODES_SORT if request.param == "sort" else ringo.NODES_HASH)
+    os.environ["RINGO_HASH_PARTS"] = "1" if request.param == "hash_parts" else "0"
     yield request.param
+    os.environ.pop("RINGO_HASH_PARTS", None)
     for e, (d, it, m) in enumerate(saved):
         ringo.tune_set(1 << e, d, it, m)
 

@@ -71,16 +71,18 @@ KINDS = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
 
 
 @pytest.mark.parametrize("kname", list(KINDS))
-@pytest.mark.parametrize("method", ["sort", "hash", "sync_free"])
+@pytest.mark.parametrize("method", ["sort", "hash", "hash_parts", "sync_free"])
 def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
-    """method: the node numbering of the pass pipeline, or (directed tables
-    numbered by sorting) the sync-free single-table path, whose workspace
-    and outputs are two requests."""
+    """method: the node numbering of the pass pipeline (hash_parts: through
+    keys grouped by table part, whose every request is refused in turn), or
+    (directed tables numbered by sorting) the sync-free single-table path,
+    whose workspace and outputs are two requests."""
     import torch
     if method == "sync_free" and kname != "directed":
         pytest.skip("the sync-free path converts directed tables only")
     if method != "sync_free":
         monkeypatch.setenv("RINGO_FIXED_PATH", "0")
+    monkeypatch.setenv("RINGO_HASH_PARTS", "1" if method == "hash_parts" else "0")
     rng = np.random.default_rng(5)
     n = 300_000  # above the small-table size
     # identifiers from a pool of n / 8, so that hash numbering builds its table
@@ -94,7 +96,7 @@ def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
     saved = [ringo.tune_get(1 << e) for e in range(63)]
     al = CountingAllocator(cuda)
     try:
-        ringo.set_node_method(ringo.NODES_HASH if method == "hash" else ringo.NODES_SORT)
+        ringo.set_node_method(ringo.NODES_HASH if method.startswith("hash") else ringo.NODES_SORT)
         al.install()
         # a full conversion through the hook: how many requests it makes
         rc, g = convert_raw(src, dst, kind)
@@ -104,7 +106,8 @@ def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
         ringo.graph_free(g)
         assert not al.live, "blocks left after graph_free"
         # refuse every request in turn (a sample of them for speed)
-        for k in sorted({1, 2, 3, total // 2, total - 1, total} & set(range(1, total + 1))):
+        ks = range(1, total + 1) if method == "hash_parts" else {1, 2, 3, total // 2, total - 1, total}
+        for k in sorted(set(ks) & set(range(1, total + 1))):
             say("allocator refuses request", k, "of", total, method, kname)
             al.requests, al.fail_at = 0, k
             rc, g = convert_raw(src, dst, kind)

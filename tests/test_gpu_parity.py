@@ -236,14 +236,17 @@ def test_small_tables_batched(cuda, method):
             assert_same(gb[i], oracle.table_to_graph(hs, hd), f"{label} table {i}: ")
 
 
+@pytest.mark.parametrize("parts", ["0", "1"])
 @pytest.mark.parametrize("cap", [1, 64, 4096])
-def test_hash_overflow_falls_back_to_sort(cuda, cap):
+def test_hash_overflow_falls_back_to_sort(cuda, cap, parts):
     """Node hash tables capped far below V (forced from the host): every probe
     sequence stops at its bound, the call numbers the nodes by sorting, and
-    the graph is still the oracle's.  Tables that fit keep the hash path."""
+    the graph is still the oracle's.  Tables that fit keep the hash path.
+    parts: inserts in row order, or of keys grouped by table part."""
     saved = [ringo.tune_get(1 << e) for e in range(63)]
     try:
         os.environ["RINGO_HASH_TEST_CAPACITY"] = str(cap)
+        os.environ["RINGO_HASH_PARTS"] = parts
         ringo.set_node_method(ringo.NODES_HASH)
         for n, pool in ((5, 3), (1000, 40), (20000, 5000), (200_000, 150_000)):
             say("hash capacity", cap, "n", n, "pool", pool)
@@ -251,6 +254,7 @@ def test_hash_overflow_falls_back_to_sort(cuda, cap):
             assert_same(gpu_graph(src, dst, cuda), oracle.table_to_graph(src, dst), f"cap={cap} n={n}: ")
     finally:
         del os.environ["RINGO_HASH_TEST_CAPACITY"]
+        os.environ.pop("RINGO_HASH_PARTS", None)
         for e, (d, it, m) in enumerate(saved):
             ringo.tune_set(1 << e, d, it, m)
 
