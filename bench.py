@@ -34,19 +34,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 KERNEL_DIR = os.path.join(ROOT, "paper_1503_07881_amd", "csrc")
 
-# Trace entry -> kernel name in a rocprofv3 summary ({items}: items per thread).
-# Radix-pass instantiations: <256, items, mode>, mode 1 node (first pass),
-# 3 node, 4 distinct nodes, 5 edge, 2 in (first pass), 6 in.
+# Trace entry -> kernel name in a rocprofv3 summary ({items}: items per thread,
+# {bits}: the schedule's digit width; a|b: either instantiation, one entry
+# covering both).  Radix-pass instantiations: <256, items, mode, digit bits>,
+# mode 1 node (first pass), 3 node, 4 distinct nodes, 5 edge, 2 in (first
+# pass), 6 in, 10 in (first pass, dedupe folded), 11 and 12 the groupings of
+# the partitioned numbering, 13 its rank grouping.  Passes take 8-bit digits
+# where the key width leaves room, so an entry may cover both widths.
 ROCPROF_NAME = {
-    "hash_estimate": "k_hll", "hash_insert": "k_hash_insert", "hash_compact": "k_hash_compact",
+    "hash_estimate": "k_hll", "hash_insert": "k_hash_insert|k_hash_insert_keys",
+    "hash_compact": "k_hash_compact",
     "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
+    "hash_pack_parts": "k_hash_pack_parts", "hash_pairs": "k_hash_pairs",
+    "hash_part_scatter": "k_downsweep<256, {items}, 11|12, 8>",
+    "hash_part_rank": "k_downsweep<256, {items}, 13, 8>",
     "unique": "k_dedupe_write<false>",
     "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe_write<true>", "in_csr": "k_in_csr",
-    "sort_node_scatter": "k_downsweep<256, {items}, 1|3, {bits}>",
-    "sort_vnode_scatter": "k_downsweep<256, {items}, 4, {bits}>",
-    "sort_edge_scatter": "k_downsweep<256, {items}, 5, {bits}>",
-    "sort_in_scatter": "k_downsweep<256, {items}, 2|6, {bits}>",
+    "sort_node_scatter": "k_downsweep<256, {items}, 1|3, 8|{bits}>",
+    "sort_vnode_scatter": "k_downsweep<256, {items}, 4, 8|{bits}>",
+    "sort_edge_scatter": "k_downsweep<256, {items}, 5, 8|{bits}>",
+    "sort_in_scatter": "k_downsweep<256, {items}, 2|6|10, 8|{bits}>",
 }
+
+
+def rocprof_names(entry: str, items: int, bits: int) -> list:
+    """Every kernel name a trace entry may stand for in a rocprofv3 summary."""
+    import itertools
+    pat = ROCPROF_NAME.get(entry, entry).format(items=items, bits=bits)
+    if "<" not in pat:
+        return pat.split("|")
+    head, args = pat[:-1].split("<", 1)
+    alts = [sorted(set(a.strip().split("|")), key=lambda x: (len(x), x)) for a in args.split(",")]
+    return [f"{head}<{', '.join(c)}>" for c in itertools.product(*alts)]
 
 
 def log(*a):
@@ -56,7 +75,7 @@ def log(*a):
 def kernel_source_file(kernel: str) -> str:
     if kernel == "edge_table":
         return "to_table.hip"
-    if kernel.startswith("sort_"):
+    if kernel.startswith("sort_") or ROCPROF_NAME.get(kernel, "").startswith("k_downsweep"):
         return "lsd.h"
     return "hash.hip" if kernel.startswith("hash_") else "kernels.hip"
 
@@ -66,7 +85,7 @@ def kernel_source_sha(kernel: str) -> str:
     helpers it includes: counter summaries taken before a change to them no
     longer describe the kernel."""
     h = hashlib.sha256()
-    for name in (kernel_source_file(kernel), "device_common.h"):
+    for name in (kernel_source_file(kernel), "device_common.h", "ringo_internal.h"):
         with open(os.path.join(KERNEL_DIR, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -95,7 +114,8 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
-CONVERSION_SOURCES = ("kernels.hip", "lsd.h", "hash.hip", "pipeline.hip", "device_common.h")
+CONVERSION_SOURCES = ("kernels.hip", "lsd.h", "hash.hip", "pipeline.hip", "device_common.h",
+                      "ringo_internal.h")
 
 
 def conversion_source_sha() -> str:
@@ -552,7 +572,7 @@ def measure_conversion(spec, args, kind, copy_gbps, steps, warmup):
         "digit_bits": bits, "items_per_thread": items,
         "node_method": "hash" if method == ringo.NODES_HASH else "sort",
         "roofline": {"bound": "hbm", "kernel": dom,
-                     "rocprof_kernel": ROCPROF_NAME.get(dom, dom).format(items=items, bits=bits),
+                     "rocprof_kernel": " | ".join(rocprof_names(dom, items, bits)),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      # the counter-measured bytes over the same launch time (line-granular

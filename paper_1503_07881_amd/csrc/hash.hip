@@ -273,7 +273,8 @@ __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const ui
       uint32_t left[U];
       bool act[U];
 #pragma unroll
-      for (int j = 0; j < U; ++j) u[j] = G(K)[std::min<int64_t>(r0 + j * 256, end - 1)];
+      for (int j = 0; j < U; ++j)
+        u[j] = __builtin_nontemporal_load(&G(K)[std::min<int64_t>(r0 + j * 256, end - 1)]);
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const bool valid = r0 + j * 256 < end;
@@ -380,8 +381,8 @@ __global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uin
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int64_t r = P.row_off + std::min<int64_t>(r0 + j * 256, end - 1);
-        u[j] = G(dkeys)[r];
-        rs[j] = G(spos)[r];
+        u[j] = __builtin_nontemporal_load(&G(dkeys)[r]);
+        rs[j] = __builtin_nontemporal_load(&G(spos)[r]);
       }
       key_ranks<U>(TP, mask, u, last, rd);
 #pragma unroll

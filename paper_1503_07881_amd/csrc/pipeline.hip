@@ -534,16 +534,23 @@ struct Call {
     a.hpairs = nullptr;
     return a;
   }
-  // Grouping of the destination keys by table part (partitioned numbering),
-  // with prefixes and digit bases of its own, which the rank pass reuses.
-  SortLaunch part_dst_args() {
-    SortLaunch a = sort_args(px + plan_rows(), py, TM_PART, RANGE_ROWS, 1, 0, 0);
+  // Passes of the partitioned numbering: PART_BITS-bit digits, whatever
+  // the schedule's width, so their counts, digit bases and run sums live in
+  // a block of their own (pcnt, part_bytes()), which also keeps the
+  // destination keys' prefixes for the rank pass that groups them again.
+  size_t part_count_bytes() { return align_up(sizeof(uint32_t) * (1 << PART_BITS) * (total(TM_NSORT) + 1)); }
+  size_t part_base_bytes() { return align_up(sizeof(int64_t) * S * (1 << PART_BITS)); }
+  size_t part_bytes() {
+    return part_count_bytes() + part_base_bytes() +
+           sizeof(uint32_t) * (1 << PART_BITS) * sort_runs_bound(total(TM_NSORT) + 1);
+  }
+  SortLaunch part_args(const uint64_t *in, uint64_t *out) {
+    SortLaunch a = sort_args(in, out, TM_PART, RANGE_ROWS, 1, 0, 0);
     a.counts = (uint32_t *)pcnt;
-    a.digit_base = (int64_t *)((char *)pcnt + align_up(sizeof(uint32_t) * (1 << PART_BITS) *
-                                                        (total(TM_NSORT) + 1)));
+    a.digit_base = (int64_t *)((char *)pcnt + part_count_bytes());
+    a.bsum = (uint32_t *)((char *)pcnt + part_count_bytes() + part_base_bytes());
     return a;
   }
-  int64_t plan_rows() const { return S > 0 ? plan[S - 1].row_off + plan[S - 1].n : 0; }
 };
 
 
@@ -903,8 +910,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + sizeof(uint32_t)) *
                                                 std::max<int64_t>(N, 1), st);
       // the node pass's tile count bounds the grouping's (n keys per table)
-      c.pcnt = dev_alloc(c.hooks, align_up(sizeof(uint32_t) * (1 << PART_BITS) * max_tiles) +
-                                      sizeof(int64_t) * S * (1 << PART_BITS), st);
+      c.pcnt = dev_alloc(c.hooks, c.part_bytes(), st);
       if (!c.tab || !c.px || !c.py || !c.pcnt) return RINGO_ERR_OUT_OF_MEMORY;
     } else {
       c.hslots = (uint32_t *)dev_alloc(c.hooks, sizeof(uint32_t) * 2 * std::max<int64_t>(N, 1), st);
@@ -918,11 +924,11 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     HIP_TRY(c.upload());
     HIP_TRY(launch_fill_u64(hkeys, EMPTY_KEY, slots, st));
     if (parted) {
-      SortLaunch a = c.sort_args(nullptr, c.px, TM_PART, RANGE_ROWS, 1, 0, 0);
+      SortLaunch a = c.part_args(nullptr, c.px);
       a.wout = c.px + N;
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 16.0, SORT_PART_ROWS, a, PART_BITS);
       // its prefixes are kept for the rank pass, which groups the same keys
-      SortLaunch d = c.part_dst_args();
+      SortLaunch d = c.part_args(c.px + N, c.py);
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 0.0, SORT_PART_DST, d, PART_BITS);
       TRACED(TK_HINSERT, N, 16.0 * N,
              launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, hflags,
@@ -1086,8 +1092,7 @@ numbering:
            launch_hash_pairs(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, hrank, hpairs,
                              grid_for(c.total(TM_HCMP), cus * 8), st));
     uint32_t *spos = (uint32_t *)(c.py + N);
-    SortLaunch a = c.part_dst_args();
-    a.out = nullptr;
+    SortLaunch a = c.part_args(c.px + N, nullptr);
     a.win = c.px;
     a.vout = spos;
     a.hpairs = hpairs;
