@@ -525,13 +525,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     for (int i = 0; i < ITEMS; ++i) {
       const bool valid = (live_bits >> i) & 1u;
       const uint32_t d = key_digit<MODE, RB>(keys[i], shift, lcap);
-      uint64_t m = __ballot(valid);
+      const uint64_t mv = __ballot(valid);
+      // per bit: s = -1 where this lane's bit is set, else 0; the lanes that
+      // agree with it on the bit are the ballot of set bits XNOR s
+      uint32_t mlo = (uint32_t)mv, mhi = (uint32_t)(mv >> 32);
 #pragma unroll
       for (int bit = 0; bit < RB; ++bit) {
-        const bool set = (d >> bit) & 1u;
-        const uint64_t bb = __ballot(set);
-        m &= set ? bb : ~bb;
+        const int32_t sb = (int32_t)(d << (31 - bit)) >> 31;
+        const uint64_t bb = __ballot(sb != 0);
+        mlo &= ~((uint32_t)bb ^ (uint32_t)sb);
+        mhi &= ~((uint32_t)(bb >> 32) ^ (uint32_t)sb);
       }
+      const uint64_t m = ((uint64_t)mhi << 32) | mlo;
       const uint32_t below = lanes_below(m);
       uint32_t rk = 0;
       if (valid) {
