@@ -38,9 +38,10 @@
 //   insert       both groupings, tiles in contiguous ranges per XCD, so the
 //                probes of one XCD meet one part at a time in its L2
 //   (compact, sort, rank as above), then every slot's (key, position) pair
-//   group rank   the grouping of the destination keys again, now carrying
-//                the position of the source key beside each (one 16-byte
+//   rank keys    the position of every grouped source key (one 16-byte
 //                pair load per lookup, inside one part)
+//   group rank   the grouping of the destination keys again, now carrying
+//                the position of the source key beside each
 //   pack         (source position, destination position) edge keys in the
 //                destinations' grouped order; the edge sort does not need
 //                row order
@@ -350,6 +351,41 @@ hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys
                              const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s) {
   if (slot_tiles.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_pairs, dim3(grid), dim3(256), 0, s, slot_tiles, hkeys, hrank, pairs);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_hash_rank_keys(TileLaunch t, const uint64_t *keys,
+                                                        const uint64_t *hpairs, uint32_t *ranks) {
+  const int tid = threadIdx.x;
+  const int64_t t_end = xcd_end_tile(t.total_tiles);
+  for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
+    const int seg = find_seg(t.tmap, t.num_segs, tile);
+    const SegPlan P = t.plan[seg];
+    const uint64_t *TP = hpairs + 2 * P.tab_off;
+    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t last = (uint32_t)(P.V - 1);
+    const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
+    const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
+    constexpr int U = 8;
+    for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
+      uint64_t u[U];
+      uint32_t rk[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        u[j] = __builtin_nontemporal_load(&G(keys)[P.row_off + std::min<int64_t>(r0 + j * 256, end - 1)]);
+      key_ranks<U>(TP, mask, u, last, rk);
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end) G(ranks)[P.row_off + r0 + j * 256] = rk[j];
+    }
+  }
+}
+
+hipError_t launch_hash_rank_keys(const TileLaunch &rows, const uint64_t *keys,
+                                 const uint64_t *hpairs, uint32_t *ranks, int grid, hipStream_t s) {
+  if (rows.total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_rank_keys, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, keys, hpairs,
+                     ranks);
   return hipGetLastError();
 }
 

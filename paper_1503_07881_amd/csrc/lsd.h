@@ -353,8 +353,9 @@ __global__ __launch_bounds__(256) void k_seg_base(SortLaunch a) {
 constexpr int ds_waves(int items, int mode, int rb) {
   return mode == SORT_IN_FIRST_DEDUP
              ? (items <= 8 ? (rb <= 9 ? 3 : 2) : items <= 12 ? 2 : (rb <= 9 ? 2 : 1))
-         : (mode == SORT_PART_ROWS || mode == SORT_PART_RANK) ? (items <= 8 ? 3 : 2)
-         : (mode == SORT_EDGE_KV || mode == SORT_IN_FIRST_KV || mode == SORT_IN_KV)
+         : mode == SORT_PART_ROWS ? (items <= 8 ? 3 : 2)
+         : (mode == SORT_EDGE_KV || mode == SORT_IN_FIRST_KV || mode == SORT_IN_KV ||
+            mode == SORT_PART_RANK)
              ? (items <= 8 ? (rb <= 9 ? 4 : 3) : items <= 12 ? (rb <= 9 ? 3 : 2) : 2)
              : (items <= 8 ? (rb <= 10 ? 4 : 3) : items <= 12 || rb == 8 ? 3 : 2);
 }
@@ -366,8 +367,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   static_assert(R % BLOCK == 0, "whole digits per thread");
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * ITEMS;
-  // RANKV: the staged values are the looked-up source positions, and only
-  // they are written; WIDE: 64-bit destination keys carried with the keys
+  // RANKV: only the carried values (source positions) are written; WIDE:
+  // 64-bit destination keys carried with the keys
   constexpr bool RANKV = MODE == SORT_PART_RANK;
   constexpr bool WIDE = MODE == SORT_PART_ROWS;
   constexpr bool KV = MODE == SORT_EDGE_KV || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_KV || RANKV;
@@ -431,15 +432,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
     uint64_t keys[ITEMS];
     uint32_t vals[KV ? ITEMS : 1];
     uint64_t wv[WIDE ? ITEMS : 1];
-    uint64_t xs[RANKV ? ITEMS : 1];  // RANKV: the source keys at the same places
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
       const int64_t e = base + (idx < cnt ? idx : 0);
       keys[i] = pass_key<MODE>(a, H.P, H.start, e);
-      if (KV && !RANKV) vals[KV ? i : 0] = G(a.vin)[H.start + e];
+      if (KV) vals[KV ? i : 0] = G(a.vin)[H.start + e];
       if (WIDE) wv[WIDE ? i : 0] = (uint64_t)G(H.P.dst)[e] ^ SIGN_FLIP;
-      if (RANKV) xs[RANKV ? i : 0] = G(a.win)[H.start + e];
     }
     // This tile's digit counts are the differences of its prefixes and the
     // next tile's (the last tile's next row is the scan's sentinel row).
@@ -470,9 +469,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
         ls += dcnt[j];
       }
     }
-    if constexpr (RANKV)
-      key_ranks<ITEMS>(a.hpairs + 2 * H.P.tab_off, (uint64_t)H.P.tab_cap - 1, xs,
-                       (uint32_t)(H.P.V - 1), vals);
     uint32_t dpos = 0;  // DEDUP: de-duplicated position of this wave's first live key
     if (DEDUP) {
       // the table's live keys in earlier tiles (the digit prefixes summed)

@@ -530,8 +530,6 @@ struct Call {
     a.vout = nullptr;
     a.seg_total = nullptr;
     a.wout = nullptr;
-    a.win = nullptr;
-    a.hpairs = nullptr;
     return a;
   }
   // Passes of the partitioned numbering: PART_BITS-bit digits, whatever
@@ -570,7 +568,7 @@ enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
   TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_GRAPH,
-  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_KINDS
+  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_HRANK_KEYS, TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -581,7 +579,7 @@ const char *const kTraceNames[TK_KINDS] = {
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
     "hash_bucket_sort", "plan_device", "fixed_graph_replay", "hash_part_count",
-    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs"};
+    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs", "hash_rank_keys"};
 
 struct TraceRec {
   int kind;
@@ -907,7 +905,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     c.tab = dev_alloc(c.hooks, key_bytes + rank_bytes + (parted ? 2 * key_bytes : 0), st);
     if (parted) {
       c.px = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * std::max<int64_t>(N, 1), st);
-      c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + sizeof(uint32_t)) *
+      c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + 2 * sizeof(uint32_t)) *
                                                 std::max<int64_t>(N, 1), st);
       // the node pass's tile count bounds the grouping's (n keys per table)
       c.pcnt = dev_alloc(c.hooks, c.part_bytes(), st);
@@ -1091,12 +1089,15 @@ numbering:
     TRACED(TK_HPAIRS, slots, 28.0 * slots,
            launch_hash_pairs(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, hrank, hpairs,
                              grid_for(c.total(TM_HCMP), cus * 8), st));
-    uint32_t *spos = (uint32_t *)(c.py + N);
+    uint32_t *spos = (uint32_t *)(c.py + N);  // source positions, grouped as dst keys
+    uint32_t *xpos = spos + N;                 // source positions, grouped as rows
+    TRACED(TK_HRANK_KEYS, N, 24.0 * N,
+           launch_hash_rank_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hpairs, xpos,
+                                 grid_for(c.total(TM_REMAP), cus * 8), st));
     SortLaunch a = c.part_args(c.px + N, nullptr);
-    a.win = c.px;
+    a.vin = xpos;
     a.vout = spos;
-    a.hpairs = hpairs;
-    TRACED(TK_HPART_RANK, N, 28.0 * N,
+    TRACED(TK_HPART_RANK, N, 20.0 * N,
            launch_sort_part(a, SORT_PART_RANK, c.items, PART_BITS, SORT_PART_SCATTER, st));
     TRACED(TK_HPACK, N, (undirected ? 36.0 : 28.0) * N,
            launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), c.py, spos, hpairs, c.B,

@@ -139,12 +139,9 @@ struct SortLaunch {
   uint32_t *vout;
   int64_t *seg_total;         // if set, the count part writes each table's key total
   GapQueue gaps;              // long runs of the out-offsets (first in-pass with dedupe)
-  // partition passes (SORT_PART_*): the destination keys carried beside the
-  // source keys, and the (key, position) pairs of the node hash tables that
-  // the rank pass looks keys up in
+  // partition passes (SORT_PART_ROWS): the destination keys carried beside
+  // the source keys
   uint64_t *wout;
-  const uint64_t *win;
-  const uint64_t *hpairs;
 };
 
 // Key source of a pass: the two first passes read their keys from elsewhere
@@ -166,9 +163,8 @@ enum SortMode : int {
   // rows' source keys (uint64(id) ^ 2^63, grouped by their part) to out,
   // their destination keys beside them to wout.  DST: the keys of in (the
   // grouped destination keys) by their part.  RANK: the same grouping as
-  // DST, which it repeats, but what it writes (to vout) is the position of
-  // the source key at the same place in win, looked up in the tables'
-  // pairs hpairs (probes stay inside one part while win is grouped).
+  // DST, which it repeats, carrying the 32-bit values of vin (the source
+  // keys' positions), and writes only those (to vout).
   SORT_PART_ROWS = 11, SORT_PART_DST = 12, SORT_PART_RANK = 13
 };
 enum SortPart : int { SORT_PART_COUNT = 1, SORT_PART_SCATTER = 2, SORT_PART_PREFIX = 4 };
@@ -293,6 +289,10 @@ hipError_t launch_hash_insert_keys(const TileLaunch &rows, const uint64_t *keys,
 // tab_off per table) from hkeys and hrank, for lookups by key with one load.
 hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys,
                              const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s);
+// Position of each of the n keys at keys + row_off (grouped by part) among
+// its table's distinct keys, from the tables' pairs, into ranks + row_off.
+hipError_t launch_hash_rank_keys(const TileLaunch &rows, const uint64_t *keys,
+                                 const uint64_t *hpairs, uint32_t *ranks, int grid, hipStream_t s);
 // Packed edge keys from the grouped destination keys (dkeys + row_off) and
 // the source positions at the same places (spos + row_off): each
 // destination key's position is looked up in its table's pairs; sym and
