@@ -54,37 +54,6 @@ __device__ __forceinline__ uint32_t slot_part(uint64_t u, int lcap) {
                            : (uint32_t)(home << (PART_BITS - lcap));
 }
 
-// Positions among the table's distinct keys of U keys that the table holds,
-// from the table's (key, position) pairs (16 bytes per slot): each key's
-// probe sequence is walked from its home slot to the pair holding it, one
-// 16-byte load per slot.  The first probes of all U keys are in flight
-// together; the key ~0, kept aside by the table, is always the last
-// (position V - 1).  A walk stops after MAX_PROBES slots, which no inserted
-// key's sequence exceeds.
-template <int U>
-__device__ __forceinline__ void key_ranks(const uint64_t *pairs, uint64_t mask,
-                                          const uint64_t (&u)[U], uint32_t last,
-                                          uint32_t (&rk)[U]) {
-  const __attribute__((address_space(1))) u64x2 *TP =
-      (const __attribute__((address_space(1))) u64x2 *)G(pairs);
-  uint64_t pos[U];
-  u64x2 e[U];
-#pragma unroll
-  for (int j = 0; j < U; ++j) pos[j] = fmix64(u[j]) & mask;
-#pragma unroll
-  for (int j = 0; j < U; ++j) e[j] = TP[pos[j]];
-#pragma unroll
-  for (int j = 0; j < U; ++j) {
-    if (u[j] == EMPTY_KEY) continue;
-    for (uint32_t i = 0; e[j].x != u[j] && i < MAX_PROBES; ++i) {
-      pos[j] = (pos[j] + 1) & mask;
-      e[j] = TP[pos[j]];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < U; ++j) rk[j] = u[j] == EMPTY_KEY ? last : (uint32_t)e[j].y;
-}
-
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {

@@ -253,6 +253,17 @@ __device__ __forceinline__ int64_t xcd_end_tile(int64_t total) {
 }
 inline int xcd_grid(int grid) { return std::max(NUM_XCD, grid / NUM_XCD * NUM_XCD); }
 
+// The lookups keep a block cache of the (key, position) pairs they met last
+// (grouped keys: the hubs of a part recur often): KC entries in LDS,
+// indexed by the low bits of the key's home slot (which vary inside a
+// part).  Entries belong to the table whose tiles the block walks, and are
+// cleared when it moves to the next table.  (The insert walks its keys
+// without one: checking the cache before each probe made it slower.)
+constexpr int KC_BITS = 11;
+constexpr int KC = 1 << KC_BITS;
+constexpr uint64_t KC_MASK = KC - 1;
+typedef __attribute__((address_space(3))) u64x2 lds_pair;
+
 // The insert of k_hash_insert over grouped keys, with no slots written.
 __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const uint64_t *keys,
                                                           uint64_t *hkeys, uint32_t *flags) {
@@ -354,26 +365,86 @@ hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_hash_rank_keys(TileLaunch t, const uint64_t *keys,
+// Positions among the table's distinct keys of U keys that the table holds,
+// through the block's cache of (key, position) pairs: keys found there need
+// no probe; the others walk their probe sequence in the table's pairs (one
+// 16-byte load per slot) from the home slot to the pair holding the key, and
+// are entered.  An entry is one 16-byte LDS access, written and read whole.
+// The key ~0, kept aside by the table, is always the last (position V - 1).
+// A walk stops after MAX_PROBES slots, which no inserted key's sequence
+// exceeds.
+template <int U>
+__device__ __forceinline__ void cached_ranks(lds_pair *kc, const uint64_t *pairs, uint64_t mask,
+                                             const uint64_t (&u)[U], uint32_t last,
+                                             uint32_t (&rk)[U]) {
+  const __attribute__((address_space(1))) u64x2 *TP =
+      (const __attribute__((address_space(1))) u64x2 *)G(pairs);
+  uint64_t pos[U];
+  uint32_t ci[U];  // cache entry: the home slot's low bits
+  u64x2 e[U];
+  bool miss[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    pos[j] = fmix64(u[j]) & mask;
+    ci[j] = (uint32_t)(pos[j] & KC_MASK);
+    e[j] = kc[ci[j]];
+    miss[j] = u[j] != EMPTY_KEY && e[j].x != u[j];
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j)
+    if (miss[j]) e[j] = TP[pos[j]];
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    if (!miss[j]) continue;
+    for (uint32_t i = 0; e[j].x != u[j] && i < MAX_PROBES; ++i) {
+      pos[j] = (pos[j] + 1) & mask;
+      e[j] = TP[pos[j]];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < U; ++j) {
+    rk[j] = u[j] == EMPTY_KEY ? last : (uint32_t)e[j].y;
+    if (miss[j]) kc[ci[j]] = e[j];
+  }
+}
+
+// Clears the block's pair cache when the block moves to table seg.
+__device__ __forceinline__ void pair_cache_for(lds_pair *kc, int seg, int &cur) {
+  if (seg == cur) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < KC; i += blockDim.x) {
+    u64x2 z;
+    z.x = EMPTY_KEY;
+    z.y = 0;
+    kc[i] = z;
+  }
+  __syncthreads();
+  cur = seg;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_hash_rank_keys(TileLaunch t, const uint64_t *keys,
                                                         const uint64_t *hpairs, uint32_t *ranks) {
+  __shared__ u64x2 s_kc[KC];
   const int tid = threadIdx.x;
+  int cur = -1;
   const int64_t t_end = xcd_end_tile(t.total_tiles);
   for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
+    pair_cache_for((lds_pair *)s_kc, seg, cur);
     const SegPlan P = t.plan[seg];
     const uint64_t *TP = hpairs + 2 * P.tab_off;
     const uint64_t mask = (uint64_t)P.tab_cap - 1;
     const uint32_t last = (uint32_t)(P.V - 1);
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
-    constexpr int U = 8;
+    constexpr int U = 4;  // more keys per thread spill the cache state
     for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
       uint64_t u[U];
       uint32_t rk[U];
 #pragma unroll
       for (int j = 0; j < U; ++j)
         u[j] = __builtin_nontemporal_load(&G(keys)[P.row_off + std::min<int64_t>(r0 + j * 256, end - 1)]);
-      key_ranks<U>(TP, mask, u, last, rk);
+      cached_ranks<U>((lds_pair *)s_kc, TP, mask, u, last, rk);
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end) G(ranks)[P.row_off + r0 + j * 256] = rk[j];
@@ -389,20 +460,23 @@ hipError_t launch_hash_rank_keys(const TileLaunch &rows, const uint64_t *keys,
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uint64_t *dkeys,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_hash_pack_parts(TileLaunch t, const uint64_t *dkeys,
                                                          const uint32_t *spos,
                                                          const uint64_t *hpairs, uint64_t *ekeys,
                                                          int sym, uint32_t *counts0, int sort_tile,
                                                          const int64_t *esort_tmap) {
   constexpr int MAX_SUB = REMAP_TILE / 2048;  // sort tiles of at least 2048 keys
   __shared__ uint32_t s_c[MAX_SUB * FUSED_RADIX];
+  __shared__ u64x2 s_kc[KC];
   const int tid = threadIdx.x;
+  int cur = -1;
   const int nsub = counts0 ? REMAP_TILE / sort_tile : 0;
   for (int i = tid; i < nsub * FUSED_RADIX; i += 256) s_c[i] = 0;
   __syncthreads();
   const int64_t t_end = xcd_end_tile(t.total_tiles);
   for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
+    pair_cache_for((lds_pair *)s_kc, seg, cur);
     const SegPlan P = t.plan[seg];
     const uint64_t *TP = hpairs + 2 * P.tab_off;
     const uint64_t mask = (uint64_t)P.tab_cap - 1;
@@ -410,7 +484,7 @@ __global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uin
     const int b = P.b;
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
-    constexpr int U = 8;
+    constexpr int U = 4;  // more keys per thread spill the cache state
     for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
       uint64_t u[U];
       uint32_t rs[U], rd[U];
@@ -420,7 +494,7 @@ __global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uin
         u[j] = __builtin_nontemporal_load(&G(dkeys)[r]);
         rs[j] = __builtin_nontemporal_load(&G(spos)[r]);
       }
-      key_ranks<U>(TP, mask, u, last, rd);
+      cached_ranks<U>((lds_pair *)s_kc, TP, mask, u, last, rd);
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end) {

@@ -1097,9 +1097,9 @@ numbering:
     SortLaunch a = c.part_args(c.px + N, nullptr);
     a.vin = xpos;
     a.vout = spos;
-    TRACED(TK_HPART_RANK, N, 20.0 * N,
+    TRACED(TK_HPART_RANK, N, 16.0 * N,
            launch_sort_part(a, SORT_PART_RANK, c.items, PART_BITS, SORT_PART_SCATTER, st));
-    TRACED(TK_HPACK, N, (undirected ? 36.0 : 28.0) * N,
+    TRACED(TK_HPACK, N, (undirected ? 40.0 : 32.0) * N,
            launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), c.py, spos, hpairs, c.B,
                                   undirected, counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                                   grid_for(c.total(TM_REMAP), cus * 8), st));
