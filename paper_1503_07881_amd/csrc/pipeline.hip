@@ -323,14 +323,15 @@ int64_t table_capacity(int64_t est, int64_t rows) {
 
 // Whether a call's node hash tables (slots in all, for rows in all) are
 // filled and read through keys grouped by table part (partitioned
-// numbering).  Grouping costs two passes over the rows and saves on every
-// probe that would miss the caches, so it pays for large tables probed
-// often: measured faster on R-MAT tables from 2^24 slots at 16 or more rows
-// per slot (2^28 rows 34.8 against 35.7 ms, 2^30 rows 151 against 159 ms),
-// slower below 2^24 slots (2^27 rows 16.9 against 16.1 ms) and on uniform
-// tables with fewer rows per slot (2^28 rows over 2^26 slots 55.5 against
-// 51.1 ms).  RINGO_HASH_PARTS=0 or 1 (test support) turns it off or on for
-// every size.
+// numbering).  Grouping costs passes over the rows and saves on every probe
+// that would miss the caches, so it pays for large tables probed often:
+// measured faster on R-MAT tables from 2^24 slots at 16 or more rows per
+// slot (2^28 rows 34.6 against 35.9 ms, 2^30 rows 141.8 against 157.0 ms)
+// and on uniform ones at 16 rows per slot (2^28 rows over 2^24 slots 41.9
+// against 44.0 ms), slower below 2^24 slots (2^27 R-MAT rows 16.8 against
+// 16.4 ms) and with fewer rows per slot (2^28 uniform rows over 2^26 slots
+// 54.0 against 52.3 ms).  RINGO_HASH_PARTS=0 or 1 (test support) turns it
+// off or on for every size.
 constexpr int64_t PART_MIN_SLOTS = (int64_t)1 << 24;
 constexpr int64_t PART_MIN_ROWS_PER_SLOT = 16;
 bool parts_for(int64_t slots, int64_t rows) {
