@@ -46,7 +46,8 @@ ROCPROF_NAME = {
     "hash_compact": "k_hash_compact",
     "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
     "hash_pack_parts": "k_hash_pack_parts", "hash_pairs": "k_hash_pairs", "hash_rank_keys": "k_hash_rank_keys",
-    "hash_part_scatter": "k_downsweep<256, {items}, 11|12, 8>",
+    "hash_part_scatter": "k_downsweep<256, {items}, 11, 8>",
+    "hash_part_dst_scatter": "k_downsweep<256, {items}, 12, 8>",
     "hash_part_rank": "k_downsweep<256, {items}, 13, 8>",
     "unique": "k_dedupe_write<false>",
     "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe_write<true>", "in_csr": "k_in_csr",

@@ -569,7 +569,8 @@ enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
   TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_GRAPH,
-  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_HRANK_KEYS, TK_KINDS
+  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_HRANK_KEYS,
+  TK_HPART_DST, TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -580,7 +581,8 @@ const char *const kTraceNames[TK_KINDS] = {
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
     "hash_bucket_sort", "plan_device", "fixed_graph_replay", "hash_part_count",
-    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs", "hash_rank_keys"};
+    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs", "hash_rank_keys",
+    "hash_part_dst_scatter"};
 
 struct TraceRec {
   int kind;
@@ -928,7 +930,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 16.0, SORT_PART_ROWS, a, PART_BITS);
       // its prefixes are kept for the rank pass, which groups the same keys
       SortLaunch d = c.part_args(c.px + N, c.py);
-      TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 0.0, SORT_PART_DST, d, PART_BITS);
+      TRACED_PASS(TK_HPART_COUNT, TK_HPART_DST, N, 0.0, SORT_PART_DST, d, PART_BITS);
       TRACED(TK_HINSERT, N, 16.0 * N,
              launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, hflags,
                                      grid_for(c.total(TM_REMAP), cus * 8), st));
