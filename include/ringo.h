@@ -275,6 +275,18 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t bytes, hipStream_t stre
                                    void *ctx);
 
 /*
+ * Returns the built-in allocator's idle cached blocks on the current device
+ * to the device (hipFree, once the work before each block's release has
+ * completed; it may wait for that work).  Blocks in use (resident graphs,
+ * calls in flight) are not touched, and later calls cache blocks again.
+ * For callers that share the device with another allocator (a framework's
+ * caching allocator) and need the memory back.  *bytes_released (may be
+ * NULL) receives the bytes returned.  RINGO_ERR_HIP if there is no current
+ * device.
+ */
+ringo_status_t ringo_release_cached(int64_t *bytes_released);
+
+/*
  * Tuning schedule: digit width (bits per radix pass), items per thread of
  * the scatter tile, and the node-numbering method.  ringo_tune_get returns
  * the schedule the library will use for a table of num_rows rows (for a

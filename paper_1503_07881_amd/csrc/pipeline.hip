@@ -2059,6 +2059,21 @@ ringo_status_t ringo_set_allocator(void *(*alloc)(size_t, hipStream_t, void *),
   return RINGO_OK;
 }
 
+ringo_status_t ringo_release_cached(int64_t *bytes_released) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return RINGO_ERR_HIP;
+  }
+  DeviceCache &C = g_cache[dev];
+  std::lock_guard<std::mutex> lk(C.mu);
+  int64_t total = 0;
+  for (const auto &kv : C.idle) total += (int64_t)kv.second.size;
+  release_idle(C);
+  if (bytes_released) *bytes_released = total;
+  return RINGO_OK;
+}
+
 ringo_status_t ringo_tune_get(int64_t num_rows, ringo_schedule_t *out) {
   if (!out || num_rows < 0) return RINGO_ERR_INVALID_ARG;
   out->digit_bits = digit_bits_for(num_rows);

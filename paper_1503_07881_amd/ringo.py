@@ -39,6 +39,7 @@ EXPORTED_SYMBOLS = (
     "ringo_graph_to_edge_table", "ringo_graph_to_node_table", "ringo_pagerank",
     "ringo_table_to_graph_ex", "ringo_table_to_graph_batched_ex", "ringo_sort_keys",
     "ringo_table_to_graph_noalloc", "ringo_server_pin", "ringo_server_unpin", "ringo_server_batches",
+    "ringo_release_cached",
 )
 
 NOALLOC_MAX_ROWS = 1 << 20
@@ -113,6 +114,8 @@ def lib() -> ctypes.CDLL:
         L.ringo_status_string.restype = ctypes.c_char_p
         L.ringo_set_allocator.argtypes = [p, p, p]
         L.ringo_set_allocator.restype = ctypes.c_int
+        L.ringo_release_cached.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+        L.ringo_release_cached.restype = ctypes.c_int
         L.ringo_tune_get.argtypes = [i64, ctypes.POINTER(Schedule)]
         L.ringo_tune_get.restype = ctypes.c_int
         L.ringo_tune_set.argtypes = [i64, ctypes.POINTER(Schedule)]
@@ -230,6 +233,16 @@ def sort_keys(keys: torch.Tensor, bits: int = 64, stream=None) -> torch.Tensor:
 
 def graph_free(g: RawGraph) -> None:
     lib().ringo_graph_free(ctypes.byref(g))
+
+
+def release_cached() -> int:
+    """Returns the built-in allocator's idle cached blocks on the current
+    device to the device; the bytes returned."""
+    n = ctypes.c_int64(0)
+    rc = lib().ringo_release_cached(ctypes.byref(n))
+    if rc != 0:
+        raise RingoError(rc, "ringo_release_cached")
+    return n.value
 
 
 def status_string(status: int) -> str:

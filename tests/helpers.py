@@ -117,8 +117,12 @@ def check_invariants(g, src, dst):
 def check_invariants_torch(g, src, dst):
     """Same invariants as check_invariants, with torch on the device (for
     tables too large for the host checks).  Uses only torch's own sort,
-    unique and searchsorted."""
+    unique and searchsorted.  The library's idle cached blocks go back to
+    the device first, for torch's temporaries."""
     import torch
+    from paper_1503_07881_amd import ringo
+    torch.cuda.synchronize()
+    ringo.release_cached()
     nodes = g.node_ids
     V = nodes.numel()
     oo, io = g.out_offsets, g.in_offsets

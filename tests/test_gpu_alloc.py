@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from helpers import assert_same
-from paper_1503_07881_amd import ringo
+from paper_1503_07881_amd import ringo, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -128,3 +128,27 @@ def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
     g2 = ringo.to_graph(src, dst, kind=kind)
     torch.cuda.synchronize()
     assert_same(g2, want, "built-in allocator: ")
+
+
+@pytest.mark.gpu
+def test_release_cached_returns_idle_blocks(cuda):
+    """After a conversion whose graph is freed, the built-in allocator holds
+    idle blocks; ringo_release_cached returns them (a second call finds
+    none), and a later conversion allocates again and gives the same graph."""
+    import torch
+    spec = workloads.TableSpec("rmat", 1 << 22, seed=71, scale=18)
+    src = torch.empty(spec.n, dtype=torch.int64, device=cuda)
+    dst = torch.empty_like(src)
+    workloads.generate_device(spec, src.data_ptr(), dst.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    first = ringo.to_graph(src, dst)
+    keep = {f: getattr(first, f).clone() for f in ("node_ids", "out_offsets", "out_nbrs", "in_offsets", "in_nbrs")}
+    del first
+    torch.cuda.synchronize()
+    freed = ringo.release_cached()
+    say("released", freed, "bytes")
+    assert freed > 16 * spec.n  # at least the two key buffers of the call
+    assert ringo.release_cached() == 0
+    again = ringo.to_graph(src, dst)
+    torch.cuda.synchronize()
+    for f, t in keep.items():
+        assert torch.equal(getattr(again, f), t), f
