@@ -45,7 +45,7 @@ ROCPROF_NAME = {
     "hash_estimate": "k_hll", "hash_insert": "k_hash_insert|k_hash_insert_keys",
     "hash_compact": "k_hash_compact",
     "hash_rank": "k_hash_rank", "hash_remap_pack": "k_hash_remap", "hash_bucket_sort": "k_bucket_sort",
-    "hash_pack_parts": "k_hash_pack_parts", "hash_pairs": "k_hash_pairs", "hash_rank_keys": "k_hash_rank_keys",
+    "hash_pack_parts": "k_hash_pack_parts", "hash_rank_slots": "k_hash_rank_slots",
     "hash_part_scatter": "k_downsweep<256, {items}, 11, 8>",
     "hash_part_dst_scatter": "k_downsweep<256, {items}, 12, 8>",
     "hash_part_rank": "k_downsweep<256, {items}, 13, 8>",

@@ -51,7 +51,9 @@ def build(verbose: bool = False) -> list[str]:
         parts = [objs[p] for p in parts if p in objs]
         target = os.path.join(HERE, lib)
         tmp = target + ".tmp"
-        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *parts, "-lpthread"]
+        # -z defs: a symbol left undefined fails the link, not the first load
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp, *parts,
+               "-lpthread"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed for {lib}:\n{r.stdout}\n{r.stderr}")

@@ -36,14 +36,16 @@
 //                carried beside them (grouped sources, then destinations)
 //   group dst    the carried destination keys by their own part
 //   insert       both groupings, tiles in contiguous ranges per XCD, so the
-//                probes of one XCD meet one part at a time in its L2
-//   (compact, sort, rank as above), then every slot's (key, position) pair
-//   rank keys    the position of every grouped source key (one 16-byte
-//                pair load per lookup, inside one part)
+//                probes of one XCD meet one part at a time in its L2; the
+//                slot of every key is written beside it (grouped order)
+//   (compact, sort, rank as above)
+//   rank slots   the grouped source keys' slots become their positions (a
+//                gather from the part's slice of the rank array)
 //   group rank   the grouping of the destination keys again, now carrying
 //                the position of the source key beside each
 //   pack         (source position, destination position) edge keys in the
-//                destinations' grouped order; the edge sort does not need
+//                destinations' grouped order, the destination positions
+//                gathered through their slots; the edge sort does not need
 //                row order
 // Multigraph edges keep their rows through the sorts, so they stay in row
 // order and take the remap.
@@ -253,20 +255,11 @@ __device__ __forceinline__ int64_t xcd_end_tile(int64_t total) {
 }
 inline int xcd_grid(int grid) { return std::max(NUM_XCD, grid / NUM_XCD * NUM_XCD); }
 
-// The lookups keep a block cache of the (key, position) pairs they met last
-// (grouped keys: the hubs of a part recur often): KC entries in LDS,
-// indexed by the low bits of the key's home slot (which vary inside a
-// part).  Entries belong to the table whose tiles the block walks, and are
-// cleared when it moves to the next table.  (The insert walks its keys
-// without one: checking the cache before each probe made it slower.)
-constexpr int KC_BITS = 11;
-constexpr int KC = 1 << KC_BITS;
-constexpr uint64_t KC_MASK = KC - 1;
-typedef __attribute__((address_space(3))) u64x2 lds_pair;
-
-// The insert of k_hash_insert over grouped keys, with no slots written.
+// The insert of k_hash_insert over grouped keys; the slot of every key
+// goes to slots + row_off (sequential in the grouped order).
 __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const uint64_t *keys,
-                                                          uint64_t *hkeys, uint32_t *flags) {
+                                                          uint64_t *hkeys, uint32_t *slots,
+                                                          uint32_t *flags) {
   const int tid = threadIdx.x;
   const int64_t t_end = xcd_end_tile(t.total_tiles);
   for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
@@ -326,175 +319,96 @@ __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const ui
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (r0 + j * 256 < end)
+          G(slots)[P.row_off + r0 + j * 256] = u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j];
     }
     if (flag) atomicOr(&flags[seg], flag);
   }
 }
 
 hipError_t launch_hash_insert_keys(const TileLaunch &rows, const uint64_t *keys, uint64_t *hkeys,
-                                   uint32_t *flags, int grid, hipStream_t s) {
+                                   uint32_t *slots, uint32_t *flags, int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hash_insert_keys, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, keys, hkeys,
-                     flags);
+                     slots, flags);
   return hipGetLastError();
 }
 
-// Edge keys from the grouped destination keys and the source positions
-// beside them; the counts of the first edge pass as in k_hash_remap.
-__global__ __launch_bounds__(256) void k_hash_pairs(TileLaunch t, const uint64_t *hkeys,
-                                                    const uint32_t *hrank, uint64_t *pairs) {
-  for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
-    const int seg = find_seg(t.tmap, t.num_segs, tile);
-    const SegPlan P = t.plan[seg];
-    const int64_t base = P.tab_off + (tile - t.tmap[seg]) * (int64_t)SCAN_TILE;
-    const int64_t end = std::min<int64_t>(base + SCAN_TILE, P.tab_off + P.tab_cap);
-    __attribute__((address_space(1))) u64x2 *out = (__attribute__((address_space(1))) u64x2 *)G(pairs);
-    for (int64_t j = base + threadIdx.x; j < end; j += 256) {
-      u64x2 e;
-      e.x = G(hkeys)[j];
-      e.y = G(hrank)[j];
-      out[j] = e;
-    }
-  }
-}
-
-hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys,
-                             const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s) {
-  if (slot_tiles.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_pairs, dim3(grid), dim3(256), 0, s, slot_tiles, hkeys, hrank, pairs);
-  return hipGetLastError();
-}
-
-// Positions among the table's distinct keys of U keys that the table holds,
-// through the block's cache of (key, position) pairs: keys found there need
-// no probe; the others walk their probe sequence in the table's pairs (one
-// 16-byte load per slot) from the home slot to the pair holding the key, and
-// are entered.  An entry is one 16-byte LDS access, written and read whole.
-// The key ~0, kept aside by the table, is always the last (position V - 1).
-// A walk stops after MAX_PROBES slots, which no inserted key's sequence
-// exceeds.
-template <int U>
-__device__ __forceinline__ void cached_ranks(lds_pair *kc, const uint64_t *pairs, uint64_t mask,
-                                             const uint64_t (&u)[U], uint32_t last,
-                                             uint32_t (&rk)[U]) {
-  const __attribute__((address_space(1))) u64x2 *TP =
-      (const __attribute__((address_space(1))) u64x2 *)G(pairs);
-  uint64_t pos[U];
-  uint32_t ci[U];  // cache entry: the home slot's low bits
-  u64x2 e[U];
-  bool miss[U];
-#pragma unroll
-  for (int j = 0; j < U; ++j) {
-    pos[j] = fmix64(u[j]) & mask;
-    ci[j] = (uint32_t)(pos[j] & KC_MASK);
-    e[j] = kc[ci[j]];
-    miss[j] = u[j] != EMPTY_KEY && e[j].x != u[j];
-  }
-#pragma unroll
-  for (int j = 0; j < U; ++j)
-    if (miss[j]) e[j] = TP[pos[j]];
-#pragma unroll
-  for (int j = 0; j < U; ++j) {
-    if (!miss[j]) continue;
-    for (uint32_t i = 0; e[j].x != u[j] && i < MAX_PROBES; ++i) {
-      pos[j] = (pos[j] + 1) & mask;
-      e[j] = TP[pos[j]];
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < U; ++j) {
-    rk[j] = u[j] == EMPTY_KEY ? last : (uint32_t)e[j].y;
-    if (miss[j]) kc[ci[j]] = e[j];
-  }
-}
-
-// Clears the block's pair cache when the block moves to table seg.
-__device__ __forceinline__ void pair_cache_for(lds_pair *kc, int seg, int &cur) {
-  if (seg == cur) return;
-  __syncthreads();
-  for (int i = threadIdx.x; i < KC; i += blockDim.x) {
-    u64x2 z;
-    z.x = EMPTY_KEY;
-    z.y = 0;
-    kc[i] = z;
-  }
-  __syncthreads();
-  cur = seg;
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_hash_rank_keys(TileLaunch t, const uint64_t *keys,
-                                                        const uint64_t *hpairs, uint32_t *ranks) {
-  __shared__ u64x2 s_kc[KC];
+// Positions of grouped keys from their recorded slots, in place: the
+// slots of one part lie in one slice of the rank array, which stays in the
+// L2 of the XCD walking that part.
+__global__ __launch_bounds__(256) void k_hash_rank_slots(TileLaunch t, uint32_t *slot_rank,
+                                                         const uint32_t *hrank) {
   const int tid = threadIdx.x;
-  int cur = -1;
   const int64_t t_end = xcd_end_tile(t.total_tiles);
   for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
-    pair_cache_for((lds_pair *)s_kc, seg, cur);
     const SegPlan P = t.plan[seg];
-    const uint64_t *TP = hpairs + 2 * P.tab_off;
-    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t *R = hrank + P.tab_off;
+    uint32_t *SR = slot_rank + P.row_off;
     const uint32_t last = (uint32_t)(P.V - 1);
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
-    constexpr int U = 4;  // more keys per thread spill the cache state
+    constexpr int U = 8;
     for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
-      uint64_t u[U];
-      uint32_t rk[U];
+      uint32_t q[U], rk[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) q[j] = G(SR)[std::min<int64_t>(r0 + j * 256, end - 1)];
+#pragma unroll
+      for (int j = 0; j < U; ++j) rk[j] = G(R)[q[j] == NO_SLOT ? 0u : q[j]];
 #pragma unroll
       for (int j = 0; j < U; ++j)
-        u[j] = __builtin_nontemporal_load(&G(keys)[P.row_off + std::min<int64_t>(r0 + j * 256, end - 1)]);
-      cached_ranks<U>((lds_pair *)s_kc, TP, mask, u, last, rk);
-#pragma unroll
-      for (int j = 0; j < U; ++j)
-        if (r0 + j * 256 < end) G(ranks)[P.row_off + r0 + j * 256] = rk[j];
+        if (r0 + j * 256 < end) G(SR)[r0 + j * 256] = q[j] == NO_SLOT ? last : rk[j];
     }
   }
 }
 
-hipError_t launch_hash_rank_keys(const TileLaunch &rows, const uint64_t *keys,
-                                 const uint64_t *hpairs, uint32_t *ranks, int grid, hipStream_t s) {
+hipError_t launch_hash_rank_slots(const TileLaunch &rows, uint32_t *slot_rank,
+                                  const uint32_t *hrank, int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_rank_keys, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, keys, hpairs,
-                     ranks);
+  hipLaunchKernelGGL(k_hash_rank_slots, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, slot_rank,
+                     hrank);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_hash_pack_parts(TileLaunch t, const uint64_t *dkeys,
+// Edge keys from the destination keys' recorded slots (grouped order) and
+// the source positions beside them; the counts of the first edge pass as in
+// k_hash_remap.
+__global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uint32_t *dslots,
                                                          const uint32_t *spos,
-                                                         const uint64_t *hpairs, uint64_t *ekeys,
+                                                         const uint32_t *hrank, uint64_t *ekeys,
                                                          int sym, uint32_t *counts0, int sort_tile,
                                                          const int64_t *esort_tmap) {
   constexpr int MAX_SUB = REMAP_TILE / 2048;  // sort tiles of at least 2048 keys
   __shared__ uint32_t s_c[MAX_SUB * FUSED_RADIX];
-  __shared__ u64x2 s_kc[KC];
   const int tid = threadIdx.x;
-  int cur = -1;
   const int nsub = counts0 ? REMAP_TILE / sort_tile : 0;
   for (int i = tid; i < nsub * FUSED_RADIX; i += 256) s_c[i] = 0;
   __syncthreads();
   const int64_t t_end = xcd_end_tile(t.total_tiles);
   for (int64_t tile = xcd_first_tile(t.total_tiles); tile < t_end; tile += gridDim.x / NUM_XCD) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
-    pair_cache_for((lds_pair *)s_kc, seg, cur);
     const SegPlan P = t.plan[seg];
-    const uint64_t *TP = hpairs + 2 * P.tab_off;
-    const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const uint32_t *R = hrank + P.tab_off;
     const uint32_t last = (uint32_t)(P.V - 1);
     const int b = P.b;
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
-    constexpr int U = 4;  // more keys per thread spill the cache state
+    constexpr int U = 8;
     for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
-      uint64_t u[U];
-      uint32_t rs[U], rd[U];
+      uint32_t q[U], rs[U], rd[U];
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int64_t r = P.row_off + std::min<int64_t>(r0 + j * 256, end - 1);
-        u[j] = __builtin_nontemporal_load(&G(dkeys)[r]);
+        q[j] = __builtin_nontemporal_load(&G(dslots)[r]);
         rs[j] = __builtin_nontemporal_load(&G(spos)[r]);
       }
-      cached_ranks<U>((lds_pair *)s_kc, TP, mask, u, last, rd);
+#pragma unroll
+      for (int j = 0; j < U; ++j) rd[j] = G(R)[q[j] == NO_SLOT ? 0u : q[j]];
+#pragma unroll
+      for (int j = 0; j < U; ++j) rd[j] = q[j] == NO_SLOT ? last : rd[j];
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end) {
@@ -524,15 +438,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 }
 
-hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint64_t *dkeys,
-                                  const uint32_t *spos, const uint64_t *hpairs, uint64_t *ekeys, int sym,
+hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint32_t *dslots,
+                                  const uint32_t *spos, const uint32_t *hrank, uint64_t *ekeys, int sym,
                                   uint32_t *counts0, int sort_tile, const int64_t *esort_tmap,
                                   int grid, hipStream_t s) {
   if (rows.total_tiles == 0) return hipSuccess;
   if (counts0 && (sym || sort_tile < 2048 || REMAP_TILE % sort_tile != 0))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_hash_pack_parts, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, dkeys, spos,
-                     hpairs, ekeys, sym, counts0, sort_tile, esort_tmap);
+  hipLaunchKernelGGL(k_hash_pack_parts, dim3(xcd_grid(grid)), dim3(256), 0, s, rows, dslots, spos,
+                     hrank, ekeys, sym, counts0, sort_tile, esort_tmap);
   return hipGetLastError();
 }
 

@@ -569,8 +569,8 @@ enum TraceKind {
   TK_NODE_COUNT, TK_NODE_SCATTER, TK_UNIQUE, TK_DIR, TK_REMAP, TK_EDGE_COUNT, TK_EDGE_SCATTER,
   TK_DEDUPE, TK_IN_COUNT, TK_IN_SCATTER, TK_IN_CSR, TK_AUX, TK_HLL, TK_HINSERT, TK_HCOMPACT,
   TK_VNODE_COUNT, TK_VNODE_SCATTER, TK_HRANK, TK_HREMAP, TK_SMALL, TK_HBSORT, TK_PLAN, TK_GRAPH,
-  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HPAIRS, TK_HRANK_KEYS,
-  TK_HPART_DST, TK_KINDS
+  TK_HPART_COUNT, TK_HPART_SCATTER, TK_HPART_RANK, TK_HPACK, TK_HRANK_KEYS, TK_HPART_DST,
+  TK_KINDS
 };
 // "count" entries are the small kernels of a pass's digit counting and
 // prefixes (three or four); every other entry is a single kernel.
@@ -581,7 +581,7 @@ const char *const kTraceNames[TK_KINDS] = {
     "hash_estimate",     "hash_insert",       "hash_compact",    "sort_vnode_count",
     "sort_vnode_scatter", "hash_rank",        "hash_remap_pack", "small_tables",
     "hash_bucket_sort", "plan_device", "fixed_graph_replay", "hash_part_count",
-    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_pairs", "hash_rank_keys",
+    "hash_part_scatter", "hash_part_rank", "hash_pack_parts", "hash_rank_slots",
     "hash_part_dst_scatter"};
 
 struct TraceRec {
@@ -849,7 +849,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   uint32_t *hrank = nullptr;
   uint32_t *hflags = nullptr;
   bool parted = false;  // partitioned numbering
-  uint64_t *hpairs = nullptr;
   // one table: its distinct keys are placed by bucket of their top bits, and
   // sorted bucket by bucket in LDS when no bucket exceeds BUCKET_CAP keys
   const bool bucket_place = want_hash && S == 1;
@@ -904,11 +903,13 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     parted = c.kind != RINGO_GRAPH_MULTI && parts_for(slots, N);
     const size_t key_bytes = align_up(sizeof(uint64_t) * std::max<int64_t>(slots, 1));
     const size_t rank_bytes = align_up(sizeof(uint32_t) * std::max<int64_t>(slots, 1));
-    // partitioned: the (key, position) pairs after the ranks
-    c.tab = dev_alloc(c.hooks, key_bytes + rank_bytes + (parted ? 2 * key_bytes : 0), st);
+    c.tab = dev_alloc(c.hooks, key_bytes + rank_bytes, st);
     if (parted) {
       c.px = (uint64_t *)dev_alloc(c.hooks, sizeof(uint64_t) * 2 * std::max<int64_t>(N, 1), st);
-      c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + 2 * sizeof(uint32_t)) *
+      // destination keys, then three 32-bit arrays: source positions grouped
+      // as destinations, source slots (then positions) grouped as rows,
+      // destination slots
+      c.py = (uint64_t *)dev_alloc(c.hooks, (sizeof(uint64_t) + 3 * sizeof(uint32_t)) *
                                                 std::max<int64_t>(N, 1), st);
       // the node pass's tile count bounds the grouping's (n keys per table)
       c.pcnt = dev_alloc(c.hooks, c.part_bytes(), st);
@@ -919,7 +920,6 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     }
     hkeys = (uint64_t *)c.tab;
     hrank = (uint32_t *)((char *)c.tab + key_bytes);
-    hpairs = parted ? (uint64_t *)((char *)c.tab + key_bytes + rank_bytes) : nullptr;
     c.set_tiles(TM_HCMP, RANGE_SLOTS, SCAN_TILE);
     if (parted) c.set_tiles(TM_PART, RANGE_ROWS, c.sort_tile);
     HIP_TRY(c.upload());
@@ -931,11 +931,12 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       // its prefixes are kept for the rank pass, which groups the same keys
       SortLaunch d = c.part_args(c.px + N, c.py);
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_DST, N, 0.0, SORT_PART_DST, d, PART_BITS);
-      TRACED(TK_HINSERT, N, 16.0 * N,
-             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, hflags,
+      uint32_t *xslot = (uint32_t *)(c.py + N) + N, *yslot = xslot + N;
+      TRACED(TK_HINSERT, N, 20.0 * N,
+             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, xslot, hflags,
                                      grid_for(c.total(TM_REMAP), cus * 8), st));
-      TRACED(TK_HINSERT, N, 16.0 * N,
-             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.py, hkeys, hflags,
+      TRACED(TK_HINSERT, N, 20.0 * N,
+             launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.py, hkeys, yslot, hflags,
                                      grid_for(c.total(TM_REMAP), cus * 8), st));
     } else {
       TRACED(TK_HINSERT, 2 * N, 24.0 * N,
@@ -1089,21 +1090,19 @@ numbering:
     // source positions, grouped as the destination keys are (the same
     // stable grouping again), then the destination keys' positions beside
     // them make the edge keys
-    TRACED(TK_HPAIRS, slots, 28.0 * slots,
-           launch_hash_pairs(c.tiles(TM_HCMP, RANGE_SLOTS), hkeys, hrank, hpairs,
-                             grid_for(c.total(TM_HCMP), cus * 8), st));
     uint32_t *spos = (uint32_t *)(c.py + N);  // source positions, grouped as dst keys
-    uint32_t *xpos = spos + N;                 // source positions, grouped as rows
-    TRACED(TK_HRANK_KEYS, N, 24.0 * N,
-           launch_hash_rank_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hpairs, xpos,
-                                 grid_for(c.total(TM_REMAP), cus * 8), st));
+    uint32_t *xpos = spos + N;                 // source slots, then positions, grouped as rows
+    uint32_t *yslot = xpos + N;                // destination slots, grouped
+    TRACED(TK_HRANK_KEYS, N, 12.0 * N,
+           launch_hash_rank_slots(c.tiles(TM_REMAP, RANGE_ROWS), xpos, hrank,
+                                  grid_for(c.total(TM_REMAP), cus * 8), st));
     SortLaunch a = c.part_args(c.px + N, nullptr);
     a.vin = xpos;
     a.vout = spos;
     TRACED(TK_HPART_RANK, N, 16.0 * N,
            launch_sort_part(a, SORT_PART_RANK, c.items, PART_BITS, SORT_PART_SCATTER, st));
-    TRACED(TK_HPACK, N, (undirected ? 40.0 : 32.0) * N,
-           launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), c.py, spos, hpairs, c.B,
+    TRACED(TK_HPACK, N, (undirected ? 28.0 : 20.0) * N,
+           launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), yslot, spos, hrank, c.B,
                                   undirected, counts0, c.sort_tile, c.tm_dev(TM_ESORT),
                                   grid_for(c.total(TM_REMAP), cus * 8), st));
     dev_free(c.hooks, c.px, st);

@@ -281,24 +281,22 @@ hipError_t launch_hash_remap(const TileLaunch &rows, const uint32_t *slots, cons
                              uint64_t *ekeys, int sym, uint32_t *counts0, int sort_tile,
                              const int64_t *esort_tmap, int grid, hipStream_t s);
 // Partitioned numbering.  Inserts the n keys of each table at keys +
-// row_off (uint64(id) ^ 2^63, grouped by part) into its table; flags as for
-// launch_hash_insert, no slots written.
+// row_off (uint64(id) ^ 2^63, grouped by part) into its table and writes
+// each key's slot to slots + row_off (NO_SLOT for the key ~0); flags as for
+// launch_hash_insert.
 hipError_t launch_hash_insert_keys(const TileLaunch &rows, const uint64_t *keys, uint64_t *hkeys,
-                                   uint32_t *flags, int grid, hipStream_t s);
-// (key, position) pairs of every slot (pairs: 2 words per slot, at 2 *
-// tab_off per table) from hkeys and hrank, for lookups by key with one load.
-hipError_t launch_hash_pairs(const TileLaunch &slot_tiles, const uint64_t *hkeys,
-                             const uint32_t *hrank, uint64_t *pairs, int grid, hipStream_t s);
-// Position of each of the n keys at keys + row_off (grouped by part) among
-// its table's distinct keys, from the tables' pairs, into ranks + row_off.
-hipError_t launch_hash_rank_keys(const TileLaunch &rows, const uint64_t *keys,
-                                 const uint64_t *hpairs, uint32_t *ranks, int grid, hipStream_t s);
-// Packed edge keys from the grouped destination keys (dkeys + row_off) and
-// the source positions at the same places (spos + row_off): each
-// destination key's position is looked up in its table's pairs; sym and
-// counts0 as for launch_hash_remap.
-hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint64_t *dkeys,
-                                  const uint32_t *spos, const uint64_t *hpairs, uint64_t *ekeys, int sym,
+                                   uint32_t *slots, uint32_t *flags, int grid, hipStream_t s);
+// The slots at slot_rank + row_off become the keys' positions among their
+// table's distinct keys (gathered from hrank at each table's tab_off), in
+// place.
+hipError_t launch_hash_rank_slots(const TileLaunch &rows, uint32_t *slot_rank,
+                                  const uint32_t *hrank, int grid, hipStream_t s);
+// Packed edge keys from the grouped destination keys' slots (dslots +
+// row_off) and the source positions at the same places (spos + row_off):
+// each destination's position is gathered from hrank; sym and counts0 as
+// for launch_hash_remap.
+hipError_t launch_hash_pack_parts(const TileLaunch &rows, const uint32_t *dslots,
+                                  const uint32_t *spos, const uint32_t *hrank, uint64_t *ekeys, int sym,
                                   uint32_t *counts0, int sort_tile, const int64_t *esort_tmap,
                                   int grid, hipStream_t s);
 
