@@ -45,13 +45,18 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   return k;
 }
 
-// Part of a node hash table of 2^lcap slots that holds key u's home slot:
-// the slots split into 2^PART_BITS equal contiguous parts (a table with
-// fewer slots than parts spreads its slots over them).
-__device__ __forceinline__ uint32_t slot_part(uint64_t u, int lcap) {
-  const uint64_t home = fmix64(u) & ((1ull << lcap) - 1);
-  return lcap >= PART_BITS ? (uint32_t)(home >> (lcap - PART_BITS))
-                           : (uint32_t)(home << (PART_BITS - lcap));
+// Home slot of a key with hash h in a node hash table of 2^lcap slots: the
+// top lcap bits of the hash.
+__device__ __forceinline__ uint64_t home_slot(uint64_t h, int lcap) {
+  return lcap > 0 ? h >> (64 - lcap) : 0;
+}
+
+// Part of key u: the top PART_BITS bits of its hash.  The home slots of a
+// part's keys form one contiguous range of every table of at least
+// 2^PART_BITS slots (the table's 2^PART_BITS equal parts, in order), and
+// the part does not depend on the table's size.
+__device__ __forceinline__ uint32_t slot_part(uint64_t u) {
+  return (uint32_t)(fmix64(u) >> (64 - PART_BITS));
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {

@@ -66,21 +66,30 @@ constexpr uint32_t NO_SLOT = 0xffffffffu;
 
 // ------------------------------------------------------------- estimate
 
-__device__ __forceinline__ void hll_add(uint32_t *R, uint64_t key) {
-  const uint64_t h = fmix64(key);
+__device__ __forceinline__ void hll_add(uint32_t *R, uint64_t h) {
   const uint32_t idx = (uint32_t)(h >> (64 - HLL_BITS));
   const uint64_t w = h << HLL_BITS;
   const uint32_t rho = w == 0 ? 64 - HLL_BITS + 1 : (uint32_t)__clzll((long long)w) + 1;
   if (R[idx] < rho) atomicMax(&R[idx], rho);  // the read only skips redundant atomics
 }
 
-__global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs) {
+// With pcounts, the estimate also counts the source keys' parts for the
+// rows' grouping pass: per grouping tile of ptile rows (tile map ptmap,
+// ptile dividing HLL_TILE), pcounts [tile][2^PART_BITS].  Each bin is split
+// over four sub-counters (lane mod 4), as in the radix passes' counting, so
+// the lanes of a hub's rows do not all meet at one counter.
+__global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs, uint32_t *pcounts,
+                                             const int64_t *ptmap, int ptile) {
+  constexpr int PR = 1 << PART_BITS, PSUB = 4, MAX_PSUB = HLL_TILE / 2048;
   __shared__ uint32_t R[HLL_M];
+  __shared__ uint32_t s_pc[MAX_PSUB * PR * PSUB];
   const int tid = threadIdx.x;
+  const int nsub = pcounts ? HLL_TILE / ptile : 0;
   for (int64_t tile = blockIdx.x; tile < t.total_tiles; tile += gridDim.x) {
     const int seg = find_seg(t.tmap, t.num_segs, tile);
     const SegPlan P = t.plan[seg];
     for (int i = tid; i < HLL_M; i += 256) R[i] = 0;
+    for (int i = tid; i < nsub * PR * PSUB; i += 256) s_pc[i] = 0;
     __syncthreads();
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)HLL_TILE;
     const int64_t end = std::min<int64_t>(base + HLL_TILE, P.n);
@@ -96,8 +105,12 @@ __global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs) {
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end) {
-          hll_add(R, s[j]);
-          hll_add(R, d[j]);
+          const uint64_t hs = fmix64(s[j]);
+          hll_add(R, hs);
+          hll_add(R, fmix64(d[j]));
+          if (pcounts)
+            atomicAdd(&s_pc[((int)((r0 + j * 256 - base) / ptile) * PR +
+                             (int)(hs >> (64 - PART_BITS))) * PSUB + (tid & (PSUB - 1))], 1u);
         }
     }
     __syncthreads();
@@ -105,6 +118,17 @@ __global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs) {
     for (int i = tid; i < HLL_M; i += 256) {
       const uint32_t v = R[i];
       if (v > G(g)[i]) atomicMax(&g[i], v);
+    }
+    if (pcounts) {
+      // the grouping tiles of this estimate tile that hold rows of the table
+      const int64_t first = base / ptile;
+      for (int i = tid; i < nsub * PR; i += 256) {
+        const int st = i / PR;
+        if ((first + st) * ptile < P.n) {
+          const uint32_t *c = s_pc + i * PSUB;
+          G(pcounts)[(ptmap[seg] + first + st) * PR + i % PR] = c[0] + c[1] + c[2] + c[3];
+        }
+      }
     }
     __syncthreads();
   }
@@ -147,9 +171,11 @@ __global__ __launch_bounds__(256) void k_hll_estimate(const SegPlan *plan, int S
   }
 }
 
-hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, int grid,
-                      hipStream_t s) {
-  if (rows.total_tiles > 0) hipLaunchKernelGGL(k_hll, dim3(grid), dim3(256), 0, s, rows, regs);
+hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, uint32_t *pcounts,
+                      const int64_t *ptmap, int ptile, int grid, hipStream_t s) {
+  if (pcounts && (ptile < 2048 || HLL_TILE % ptile != 0)) return hipErrorInvalidValue;
+  if (rows.total_tiles > 0)
+    hipLaunchKernelGGL(k_hll, dim3(grid), dim3(256), 0, s, rows, regs, pcounts, ptmap, ptile);
   hipLaunchKernelGGL(k_hll_estimate, dim3(rows.num_segs), dim3(256), 0, s, rows.plan,
                      rows.num_segs, regs, est);
   return hipGetLastError();
@@ -171,6 +197,7 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
     uint64_t *T = hkeys + P.tab_off;
     uint32_t *sl = slots + 2 * P.row_off;
     const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const int lcap = __builtin_ctzll((uint64_t)P.tab_cap);  // tables with rows have slots
     const uint32_t max_probes = (uint32_t)std::min<int64_t>(P.tab_cap, MAX_PROBES);
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
@@ -191,7 +218,7 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
         const bool valid = r0 + (j % U) * 256 < end;
         if (valid && u[j] == EMPTY_KEY) flag |= HFLAG_MAX_KEY;
         act[j] = valid && u[j] != EMPTY_KEY;
-        pos[j] = fmix64(u[j]) & mask;
+        pos[j] = home_slot(fmix64(u[j]), lcap);
         left[j] = max_probes;
       }
       // First probe of every key unconditionally (all loads in flight at
@@ -268,6 +295,7 @@ __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const ui
     uint64_t *T = hkeys + P.tab_off;
     const uint64_t *K = keys + P.row_off;
     const uint64_t mask = (uint64_t)P.tab_cap - 1;
+    const int lcap = __builtin_ctzll((uint64_t)P.tab_cap);  // tables with rows have slots
     const uint32_t max_probes = (uint32_t)std::min<int64_t>(P.tab_cap, MAX_PROBES);
     const int64_t base = (tile - t.tmap[seg]) * (int64_t)REMAP_TILE;
     const int64_t end = std::min<int64_t>(base + REMAP_TILE, P.n);
@@ -285,7 +313,7 @@ __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const ui
         const bool valid = r0 + j * 256 < end;
         if (valid && u[j] == EMPTY_KEY) flag |= HFLAG_MAX_KEY;
         act[j] = valid && u[j] != EMPTY_KEY;
-        pos[j] = fmix64(u[j]) & mask;
+        pos[j] = home_slot(fmix64(u[j]), lcap);
         left[j] = max_probes;
       }
       bool more = true;
@@ -676,7 +704,7 @@ __global__ __launch_bounds__(256) void k_hash_rank(TileLaunch t, const uint64_t 
       const uint64_t u = G(nd)[j];
       G(P.node_ids)[j] = (int64_t)(u ^ SIGN_FLIP);
       if (u == EMPTY_KEY) continue;
-      uint64_t pos = fmix64(u) & mask;
+      uint64_t pos = home_slot(fmix64(u), __builtin_ctzll((uint64_t)P.tab_cap));
       // the key is in the table (no overflow): the walk ends within tab_cap slots
       for (int64_t left = P.tab_cap; left > 0 && G(T)[pos] != u; --left) pos = (pos + 1) & mask;
       G(hrank)[P.tab_off + pos] = (uint32_t)j;

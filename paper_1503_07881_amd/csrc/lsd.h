@@ -43,21 +43,15 @@ constexpr bool part_mode() {
 }
 
 // Digit of key k in the pass: bits [shift, shift + RB) of the key, or
-// (partition passes) the part of its table of 2^lcap slots that holds the
-// key's home slot.
+// (partition passes) the key's part of the node hash tables.
 template <int MODE, int RB>
-__device__ __forceinline__ uint32_t key_digit(uint64_t k, int shift, int lcap) {
+__device__ __forceinline__ uint32_t key_digit(uint64_t k, int shift) {
   if constexpr (part_mode<MODE>()) {
     static_assert(RB == PART_BITS, "partition passes have PART_BITS-bit digits");
-    return slot_part(k, lcap);
+    return slot_part(k);
   } else {
     return (uint32_t)(k >> shift) & ((1u << RB) - 1);
   }
-}
-
-// log2 of a table's node hash table slots (partition passes).
-__device__ __forceinline__ int table_lcap(const SegPlan &P) {
-  return __builtin_ctzll((uint64_t)P.tab_cap | (1ull << 62));
 }
 
 // The key of element e of a table's range, as the pass sorts it.
@@ -152,7 +146,6 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
     __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
     __builtin_amdgcn_wave_barrier();
     H.at(a, t);
-    const int lcap = part_mode<MODE>() ? table_lcap(H.P) : 0;
     const int64_t k0 = (t - H.first) * tile_keys;
     // a tile past the table's key count (tile maps sized for the worst case,
     // the count set on the device) is empty
@@ -171,12 +164,12 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
 #pragma unroll
         for (int j = 0; j < U2; ++j)
           if (q0 + j * 64 < np) {
-            atomicAdd(&h[key_digit<MODE, RB>(k[j].x, shift, lcap) * SUB], 1u);
-            atomicAdd(&h[key_digit<MODE, RB>(k[j].y, shift, lcap) * SUB], 1u);
+            atomicAdd(&h[key_digit<MODE, RB>(k[j].x, shift) * SUB], 1u);
+            atomicAdd(&h[key_digit<MODE, RB>(k[j].y, shift) * SUB], 1u);
           }
       }
       if ((cnt & 1) && lane == 0)
-        atomicAdd(&h[key_digit<MODE, RB>(G(a.in)[H.start + k1 - 1], shift, lcap) * SUB], 1u);
+        atomicAdd(&h[key_digit<MODE, RB>(G(a.in)[H.start + k1 - 1], shift) * SUB], 1u);
     } else {
       for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
         uint64_t k[U];
@@ -194,7 +187,7 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
             if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
             valid = valid && (e == 0 || k[j] != prev);
           }
-          if (valid) atomicAdd(&h[key_digit<MODE, RB>(k[j], shift, lcap) * SUB], 1u);
+          if (valid) atomicAdd(&h[key_digit<MODE, RB>(k[j], shift) * SUB], 1u);
         }
       }
     }
@@ -389,7 +382,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int shift = a.shift;
   TileHeader H;
-  int lcap = 0;          // partition passes: log2 of the table's slots
   int64_t dbase[DPT];    // this thread's digits: first output position in the table
   uint32_t pfirst[DPT];  // prefix of the table's first tile
 #pragma unroll
@@ -411,7 +403,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
        tile += per) {
     if (tile >= H.end) {
       H.at(a, tile);
-      if (part_mode<MODE>()) lcap = table_lcap(H.P);
 #pragma unroll
       for (int j = 0; j < DPT; ++j) {
         const int d = tid * DPT + j;
@@ -520,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const bool valid = (live_bits >> i) & 1u;
-      const uint32_t d = key_digit<MODE, RB>(keys[i], shift, lcap);
+      const uint32_t d = key_digit<MODE, RB>(keys[i], shift);
       const uint64_t mv = __ballot(valid);
       // per bit: s = -1 where this lane's bit is set, else 0; the lanes that
       // agree with it on the bit are the ballot of set bits XNOR s
@@ -567,7 +558,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       if ((live_bits >> i) & 1u) {
-        const uint32_t d = part_mode<MODE>() ? rank[i] >> 16 : key_digit<MODE, RB>(keys[i], shift, lcap);
+        const uint32_t d = part_mode<MODE>() ? rank[i] >> 16 : key_digit<MODE, RB>(keys[i], shift);
         const uint32_t slot = (uint32_t)s_whist[wave * R + d] + (rank[i] & 0xffffu);
         s_stage[slot] = keys[i];
         if (KV) s_vstage[KV ? slot : 0] = vals[KV ? i : 0];
@@ -606,7 +597,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       const int p = i * BLOCK + tid;
       if (p < (int)tile_total) {
         const uint64_t k = s_stage[p];
-        const int64_t pos = s_goff[key_digit<MODE, RB>(k, shift, lcap)] + p;
+        const int64_t pos = s_goff[key_digit<MODE, RB>(k, shift)] + p;
         if ((uint64_t)(pos - H.start) < (uint64_t)H.count) {  // in range by construction
           if (!RANKV) G(a.out)[pos] = k;
           if (KV) G(a.vout)[pos] = s_vstage[KV ? p : 0];

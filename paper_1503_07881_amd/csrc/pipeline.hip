@@ -334,10 +334,21 @@ int64_t table_capacity(int64_t est, int64_t rows) {
 // off or on for every size.
 constexpr int64_t PART_MIN_SLOTS = (int64_t)1 << 24;
 constexpr int64_t PART_MIN_ROWS_PER_SLOT = 16;
-bool parts_for(int64_t slots, int64_t rows) {
+int parts_env() {  // 0 or 1 when RINGO_HASH_PARTS is set, else -1
   const char *e = std::getenv("RINGO_HASH_PARTS");
-  if (e && *e) return std::atoi(e) != 0;
+  return e && *e ? (std::atoi(e) != 0 ? 1 : 0) : -1;
+}
+bool parts_for(int64_t slots, int64_t rows) {
+  const int e = parts_env();
+  if (e >= 0) return e == 1;
   return slots >= PART_MIN_SLOTS && rows >= PART_MIN_ROWS_PER_SLOT * slots;
+}
+// Whether a call of this many rows may take the partitioned numbering: its
+// distinct-count estimate then also counts the rows' parts.
+bool parts_possible(int64_t rows) {
+  const int e = parts_env();
+  if (e >= 0) return e == 1;
+  return rows >= PART_MIN_ROWS_PER_SLOT * PART_MIN_SLOTS;
 }
 
 // ----------------------------------------------------------- tile maps
@@ -815,6 +826,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
   c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
   c.set_tiles(TM_HLL, RANGE_ROWS, HLL_TILE);
+  c.set_tiles(TM_PART, RANGE_ROWS, c.sort_tile);
   c.set_tiles(TM_REMAP, RANGE_ROWS, REMAP_TILE);
 
   // the node pass has the most tiles: 2n keys per table
@@ -849,6 +861,7 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   uint32_t *hrank = nullptr;
   uint32_t *hflags = nullptr;
   bool parted = false;  // partitioned numbering
+  bool hll_counts = false;  // the estimate counted the rows' parts
   // one table: its distinct keys are placed by bucket of their top bits, and
   // sorted bucket by bucket in LDS when no bucket exceeds BUCKET_CAP keys
   const bool bucket_place = want_hash && S == 1;
@@ -875,9 +888,12 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       bkl.max_bucket = c.results + S;
     }
     HIP_TRY(launch_fill_u64((uint64_t *)c.hmeta, 0, (int64_t)(hm_bytes / 8), st));
+    // where the rows may be grouped, the estimate also counts their parts
+    // (into the counts array, free until the grouping's prefixes)
+    hll_counts = c.kind != RINGO_GRAPH_MULTI && HLL_TILE % c.sort_tile == 0 && parts_possible(N);
     TRACED(TK_HLL, 2 * N, 16.0 * N,
-           launch_hll(c.tiles(TM_HLL, RANGE_ROWS), regs, c.results,
-                      grid_for(c.total(TM_HLL), cus * 4), st));
+           launch_hll(c.tiles(TM_HLL, RANGE_ROWS), regs, c.results, hll_counts ? c.counts : nullptr,
+                      c.tm_dev(TM_PART), c.sort_tile, grid_for(c.total(TM_HLL), cus * 4), st));
     // sync #0: size every table's node hash table from its estimate
     std::vector<int64_t> est;
     HIP_TRY(c.readback(0, est));
@@ -921,13 +937,20 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
     hkeys = (uint64_t *)c.tab;
     hrank = (uint32_t *)((char *)c.tab + key_bytes);
     c.set_tiles(TM_HCMP, RANGE_SLOTS, SCAN_TILE);
-    if (parted) c.set_tiles(TM_PART, RANGE_ROWS, c.sort_tile);
     HIP_TRY(c.upload());
     HIP_TRY(launch_fill_u64(hkeys, EMPTY_KEY, slots, st));
     if (parted) {
       SortLaunch a = c.part_args(nullptr, c.px);
       a.wout = c.px + N;
-      TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 16.0, SORT_PART_ROWS, a, PART_BITS);
+      if (hll_counts) {  // tile counts written by the estimate
+        a.counts = c.counts;
+        TRACED(TK_HPART_COUNT, N, 0.0,
+               launch_sort_part(a, SORT_PART_ROWS, c.items, PART_BITS, SORT_PART_PREFIX, st));
+        TRACED(TK_HPART_SCATTER, N, 32.0 * N,
+               launch_sort_part(a, SORT_PART_ROWS, c.items, PART_BITS, SORT_PART_SCATTER, st));
+      } else {
+        TRACED_PASS(TK_HPART_COUNT, TK_HPART_SCATTER, N, 16.0, SORT_PART_ROWS, a, PART_BITS);
+      }
       // its prefixes are kept for the rank pass, which groups the same keys
       SortLaunch d = c.part_args(c.px + N, c.py);
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_DST, N, 0.0, SORT_PART_DST, d, PART_BITS);

@@ -235,9 +235,12 @@ constexpr uint32_t MAX_PROBES = 4096;        // probe bound of the insert (and o
 constexpr int PART_BITS = 8;
 
 // regs [S][HLL_M] must start at zero; est[S] receives the distinct-count
-// estimate of each table's 2n keys.
-hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, int grid,
-                      hipStream_t s);
+// estimate of each table's 2n keys.  pcounts (or null): the source keys'
+// part counts per grouping tile of ptile rows (a divisor of HLL_TILE, at
+// least 2048; tile map ptmap), pcounts [tile][2^PART_BITS], for the rows'
+// grouping pass of the partitioned numbering.
+hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, uint32_t *pcounts,
+                      const int64_t *ptmap, int ptile, int grid, hipStream_t s);
 // hkeys (tab_cap slots per table at tab_off) must hold EMPTY_KEY; flags [S]
 // and count [S] start at zero.  The insert writes the slot of every key to
 // slots [2 * row_off + r] (source) and [2 * row_off + n + r] (destination).
