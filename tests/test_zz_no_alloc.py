@@ -147,3 +147,38 @@ def test_argument_checks(cuda):
         assert L.ringo_table_to_graph_noalloc(s.data_ptr(), s.data_ptr(), 4, *q, sh) == 1, k
     torch.cuda.synchronize()
     assert o.counts.cpu().tolist() == [SENTINEL, SENTINEL], "nothing enqueued by a rejected call"
+
+
+def test_captured_in_a_caller_graph(cuda):
+    """Captured into the caller's graph (what a caller that cannot allocate
+    usually does) and replayed three times, with eager conversions between the
+    replays that leave other contents in the shared workspace: every replay
+    equals the eager call's graph, which equals the oracle's."""
+    import torch
+    hs, hd, s, d = table(7, 300_001, 90_000, cuda)
+    n = s.numel()
+    eager = Outputs(n, cuda)
+    # the first eager call also resolves the workspace's address, outside any capture
+    eager.call(s, d, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    want = eager.graph()
+    assert_same(want, oracle.table_to_graph(hs, hd), "eager call against the oracle: ")
+
+    o = Outputs(n, cuda)
+    g = torch.cuda.CUDAGraph()
+    say("no-alloc: capture, n", n)
+    with torch.cuda.graph(g):
+        o.call(s, d, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    other = [table(20 + k, 5_000 + 777 * k, 1_000, cuda) for k in range(3)]
+    for k, (_, _, s2, d2) in enumerate(other):
+        for t in (o.node_ids, o.out_off, o.out_nbr, o.in_off, o.in_nbr, o.counts):
+            t.fill_(SENTINEL)
+        between = Outputs(s2.numel(), cuda)
+        between.call(s2, d2, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        say("no-alloc: replay", k)
+        g.replay()
+        torch.cuda.synchronize()
+        assert_same(o.graph(), want, f"replay {k}: ")
+        assert_same(between.graph(), entry_point_graph(s2, d2, pipeline=True), f"eager call {k}: ")
