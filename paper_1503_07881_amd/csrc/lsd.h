@@ -513,17 +513,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       const bool valid = (live_bits >> i) & 1u;
       const uint32_t d = key_digit<MODE, RB>(keys[i], shift);
       const uint64_t mv = __ballot(valid);
-      // per bit: s = -1 where this lane's bit is set, else 0; the lanes that
-      // agree with it on the bit are the ballot of set bits XNOR s
-      uint32_t mlo = (uint32_t)mv, mhi = (uint32_t)(mv >> 32);
+      // Per bit: s = -1 where this lane's bit is set, else 0 (one v_bfe_i32);
+      // the lanes that disagree with it on the bit are the ballot of set bits
+      // XOR s.  Their union over the bits, starting from the lanes without a
+      // key, takes one v_bitop3_b32 per half and bit: table 0xDE with the
+      // union as the middle operand is union | (s ^ ballot) whichever outer
+      // operand indexes the table's high bit.  Builtins, not inline
+      // assembly: the compiler then keeps the wait states that a VALU read
+      // of the ballot's SGPRs needs after the compare that wrote them.
+      uint32_t alo = ~(uint32_t)mv, ahi = ~(uint32_t)(mv >> 32);
 #pragma unroll
       for (int bit = 0; bit < RB; ++bit) {
-        const int32_t sb = (int32_t)(d << (31 - bit)) >> 31;
-        const uint64_t bb = __ballot(sb != 0);
-        mlo &= ~((uint32_t)bb ^ (uint32_t)sb);
-        mhi &= ~((uint32_t)(bb >> 32) ^ (uint32_t)sb);
+        const int32_t sb = __builtin_amdgcn_sbfe((int32_t)d, bit, 1);
+        const uint64_t bb = __ballot(sb < 0);
+        alo = __builtin_amdgcn_bitop3_b32((uint32_t)sb, alo, (uint32_t)bb, 0xDE);
+        ahi = __builtin_amdgcn_bitop3_b32((uint32_t)sb, ahi, (uint32_t)(bb >> 32), 0xDE);
       }
-      const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+      const uint64_t m = ~(((uint64_t)ahi << 32) | alo);
       const uint32_t below = lanes_below(m);
       uint32_t rk = 0;
       if (valid) {
