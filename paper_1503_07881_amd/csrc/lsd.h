@@ -54,7 +54,10 @@ __device__ __forceinline__ uint32_t key_digit(uint64_t k, int shift) {
   }
 }
 
-// The key of element e of a table's range, as the pass sorts it.
+// The key of element e of a table's range, as the pass sorts it.  A pass
+// reads each key twice (count, then scatter) and never again, so the reads
+// are non-temporal: they leave the caches to the scatter's partial lines,
+// which meet there with their neighbours' before going to memory.
 template <int MODE>
 __device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan &P, int64_t start,
                                              int64_t e) {
@@ -65,11 +68,11 @@ __device__ __forceinline__ uint64_t pass_key(const SortLaunch &a, const SegPlan 
     const __attribute__((address_space(1))) int64_t *ptr = e < P.n ? G(P.src) + e : G(P.dst) + (e - P.n);
     return (uint64_t)*ptr ^ SIGN_FLIP;
   } else if (MODE == SORT_IN_FIRST || MODE == SORT_IN_FIRST_KV || MODE == SORT_IN_FIRST_DEDUP) {
-    const uint64_t x = G(a.in)[start + e];
+    const uint64_t x = __builtin_nontemporal_load(&G(a.in)[start + e]);
     const uint64_t d = x & ((1ull << P.b) - 1);
     return (d << 32) | (x >> P.b);
   }
-  return G(a.in)[start + e];
+  return __builtin_nontemporal_load(&G(a.in)[start + e]);
 }
 
 // Header of the table holding a tile; tiles only move forward in a block.
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
       for (int q0 = lane; q0 < np; q0 += U2 * 64) {
         u64x2 k[U2];
 #pragma unroll
-        for (int j = 0; j < U2; ++j) k[j] = p2[std::min(q0 + j * 64, np - 1)];
+        for (int j = 0; j < U2; ++j) k[j] = __builtin_nontemporal_load(&p2[std::min(q0 + j * 64, np - 1)]);
 #pragma unroll
         for (int j = 0; j < U2; ++j)
           if (q0 + j * 64 < np) {
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
       const int idx = wave * (ITEMS * 64) + i * 64 + lane;
       const int64_t e = base + (idx < cnt ? idx : 0);
       keys[i] = pass_key<MODE>(a, H.P, H.start, e);
-      if (KV) vals[KV ? i : 0] = G(a.vin)[H.start + e];
+      if (KV) vals[KV ? i : 0] = __builtin_nontemporal_load(&G(a.vin)[H.start + e]);
       if (WIDE) wv[WIDE ? i : 0] = (uint64_t)G(H.P.dst)[e] ^ SIGN_FLIP;
     }
     // This tile's digit counts are the differences of its prefixes and the
