@@ -99,8 +99,8 @@ __global__ __launch_bounds__(256) void k_hll(TileLaunch t, uint32_t *regs, uint3
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
-        s[j] = (uint64_t)G(P.src)[r] ^ SIGN_FLIP;
-        d[j] = (uint64_t)G(P.dst)[r] ^ SIGN_FLIP;
+        s[j] = (uint64_t)__builtin_nontemporal_load(&G(P.src)[r]) ^ SIGN_FLIP;
+        d[j] = (uint64_t)__builtin_nontemporal_load(&G(P.dst)[r]) ^ SIGN_FLIP;
       }
 #pragma unroll
       for (int j = 0; j < U; ++j)
@@ -183,6 +183,10 @@ hipError_t launch_hll(const TileLaunch &rows, uint32_t *regs, int64_t *est, uint
 
 // --------------------------------------------------------------- insert
 //
+// The row columns, the slots and the edge keys are each read or written once
+// per kernel, in order, so those accesses are non-temporal: the caches stay
+// with the table and rank gathers, which are reused.
+//
 // Each thread carries the keys of U rows through their probe sequences at
 // once so that their loads overlap.  A slot goes from free to its key exactly
 // once, so a plain load that still sees it free is corrected by the
@@ -210,8 +214,8 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
-        u[j] = (uint64_t)G(P.src)[r] ^ SIGN_FLIP;
-        u[U + j] = (uint64_t)G(P.dst)[r] ^ SIGN_FLIP;
+        u[j] = (uint64_t)__builtin_nontemporal_load(&G(P.src)[r]) ^ SIGN_FLIP;
+        u[U + j] = (uint64_t)__builtin_nontemporal_load(&G(P.dst)[r]) ^ SIGN_FLIP;
       }
 #pragma unroll
       for (int j = 0; j < 2 * U; ++j) {
@@ -258,8 +262,8 @@ __global__ __launch_bounds__(256) void k_hash_insert(TileLaunch t, uint64_t *hke
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end) {
-          G(sl)[r0 + j * 256] = u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j];
-          G(sl)[P.n + r0 + j * 256] = u[U + j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[U + j];
+          __builtin_nontemporal_store(u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j], &G(sl)[r0 + j * 256]);
+          __builtin_nontemporal_store(u[U + j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[U + j], &G(sl)[P.n + r0 + j * 256]);
         }
     }
     if (flag) atomicOr(&flags[seg], flag);
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(256) void k_hash_pack_parts(TileLaunch t, const uin
             G(ekeys)[2 * P.row_off + r0 + j * 256] = key;
             G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rd[j] << b) | rs[j];
           } else {
-            G(ekeys)[P.row_off + r0 + j * 256] = key;
+            __builtin_nontemporal_store(key, &G(ekeys)[P.row_off + r0 + j * 256]);
             if (counts0)
               atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * FUSED_RADIX +
                              (uint32_t)(key & (FUSED_RADIX - 1))], 1u);
@@ -829,8 +833,8 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         const int64_t r = std::min<int64_t>(r0 + j * 256, end - 1);
-        q[j] = G(sl)[r];
-        q[U + j] = G(sl)[P.n + r];
+        q[j] = __builtin_nontemporal_load(&G(sl)[r]);
+        q[U + j] = __builtin_nontemporal_load(&G(sl)[P.n + r]);
       }
 #pragma unroll
       for (int j = 0; j < 2 * U; ++j) rk[j] = G(R)[q[j] == NO_SLOT ? 0u : q[j]];
@@ -844,7 +848,7 @@ __global__ __launch_bounds__(256) void k_hash_remap(TileLaunch t, const uint32_t
             G(ekeys)[2 * P.row_off + r0 + j * 256] = key;
             G(ekeys)[2 * P.row_off + P.n + r0 + j * 256] = ((uint64_t)rd << b) | rs;
           } else {
-            G(ekeys)[P.row_off + r0 + j * 256] = key;
+            __builtin_nontemporal_store(key, &G(ekeys)[P.row_off + r0 + j * 256]);
             if (counts0)
               atomicAdd(&s_c[(int)((r0 + j * 256 - base) / sort_tile) * FUSED_RADIX +
                              (uint32_t)(key & (FUSED_RADIX - 1))], 1u);
