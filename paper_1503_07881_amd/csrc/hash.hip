@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_hash_insert_keys(TileLaunch t, const ui
 #pragma unroll
       for (int j = 0; j < U; ++j)
         if (r0 + j * 256 < end)
-          G(slots)[P.row_off + r0 + j * 256] = u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j];
+          __builtin_nontemporal_store(u[j] == EMPTY_KEY ? NO_SLOT : (uint32_t)pos[j], &G(slots)[P.row_off + r0 + j * 256]);
     }
     if (flag) atomicOr(&flags[seg], flag);
   }
@@ -387,12 +387,12 @@ __global__ __launch_bounds__(256) void k_hash_rank_slots(TileLaunch t, uint32_t 
     for (int64_t r0 = base + tid; r0 < end; r0 += U * 256) {
       uint32_t q[U], rk[U];
 #pragma unroll
-      for (int j = 0; j < U; ++j) q[j] = G(SR)[std::min<int64_t>(r0 + j * 256, end - 1)];
+      for (int j = 0; j < U; ++j) q[j] = __builtin_nontemporal_load(&G(SR)[std::min<int64_t>(r0 + j * 256, end - 1)]);
 #pragma unroll
       for (int j = 0; j < U; ++j) rk[j] = G(R)[q[j] == NO_SLOT ? 0u : q[j]];
 #pragma unroll
       for (int j = 0; j < U; ++j)
-        if (r0 + j * 256 < end) G(SR)[r0 + j * 256] = q[j] == NO_SLOT ? last : rk[j];
+        if (r0 + j * 256 < end) __builtin_nontemporal_store(q[j] == NO_SLOT ? last : rk[j], &G(SR)[r0 + j * 256]);
     }
   }
 }
