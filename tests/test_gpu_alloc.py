@@ -70,16 +70,18 @@ KINDS = {"directed": ringo.GRAPH_DIRECTED, "undirected": ringo.GRAPH_UNDIRECTED,
          "multi": ringo.GRAPH_MULTI}
 
 
-@pytest.mark.parametrize("kname", list(KINDS))
-@pytest.mark.parametrize("method", ["sort", "hash", "hash_parts", "sync_free"])
+# the sync-free path converts directed tables only
+ALLOC_CASES = [(m, k) for m in ("sort", "hash", "hash_parts", "sync_free") for k in KINDS
+               if m != "sync_free" or k == "directed"]
+
+
+@pytest.mark.parametrize("method,kname", ALLOC_CASES)
 def test_allocator_hook_and_out_of_memory(cuda, method, kname, monkeypatch):
     """method: the node numbering of the pass pipeline (hash_parts: through
     keys grouped by table part, whose every request is refused in turn), or
     (directed tables numbered by sorting) the sync-free single-table path,
     whose workspace and outputs are two requests."""
     import torch
-    if method == "sync_free" and kname != "directed":
-        pytest.skip("the sync-free path converts directed tables only")
     if method != "sync_free":
         monkeypatch.setenv("RINGO_FIXED_PATH", "0")
     monkeypatch.setenv("RINGO_HASH_PARTS", "1" if method == "hash_parts" else "0")
