@@ -53,20 +53,27 @@ ROCPROF_NAME = {
     "directory": "k_dir", "remap_pack": "k_remap", "dedupe_out_csr": "k_dedupe_write<true>", "in_csr": "k_in_csr",
     "sort_node_scatter": "k_downsweep<256, {items}, 1|3, 8|{bits}>",
     "sort_vnode_scatter": "k_downsweep<256, {items}, 4, 8|{bits}>",
-    "sort_edge_scatter": "k_downsweep<256, {items}, 5, 8|{bits}>",
-    "sort_in_scatter": "k_downsweep<256, {items}, 2|6|10, 8|{bits}>",
+    # plain edge and in-passes of 16-key schedules with digits of at most
+    # 9 bits run on two-half tiles (k_downsweep_pair<16, mode, digit bits>)
+    "sort_edge_scatter": ("k_downsweep<256, {items}, 5, 8|{bits}>", "k_downsweep_pair<16, 5, 8|{bits}>"),
+    "sort_in_scatter": ("k_downsweep<256, {items}, 2|6|10, 8|{bits}>", "k_downsweep_pair<16, 6, 8|{bits}>"),
 }
 
 
 def rocprof_names(entry: str, items: int, bits: int) -> list:
     """Every kernel name a trace entry may stand for in a rocprofv3 summary."""
     import itertools
-    pat = ROCPROF_NAME.get(entry, entry).format(items=items, bits=bits)
-    if "<" not in pat:
-        return pat.split("|")
-    head, args = pat[:-1].split("<", 1)
-    alts = [sorted(set(a.strip().split("|")), key=lambda x: (len(x), x)) for a in args.split(",")]
-    return [f"{head}<{', '.join(c)}>" for c in itertools.product(*alts)]
+    pats = ROCPROF_NAME.get(entry, entry)
+    names = []
+    for pat in (pats,) if isinstance(pats, str) else pats:
+        pat = pat.format(items=items, bits=bits)
+        if "<" not in pat:
+            names += pat.split("|")
+            continue
+        head, args = pat[:-1].split("<", 1)
+        alts = [sorted(set(a.strip().split("|")), key=lambda x: (len(x), x)) for a in args.split(",")]
+        names += [f"{head}<{', '.join(c)}>" for c in itertools.product(*alts)]
+    return names
 
 
 def log(*a):
@@ -76,7 +83,9 @@ def log(*a):
 def kernel_source_file(kernel: str) -> str:
     if kernel == "edge_table":
         return "to_table.hip"
-    if kernel.startswith("sort_") or ROCPROF_NAME.get(kernel, "").startswith("k_downsweep"):
+    pats = ROCPROF_NAME.get(kernel, "")
+    if kernel.startswith("sort_") or any(p.startswith("k_downsweep") for p in
+                                         ((pats,) if isinstance(pats, str) else pats)):
         return "lsd.h"
     return "hash.hip" if kernel.startswith("hash_") else "kernels.hip"
 

@@ -619,6 +619,170 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ds_waves(
   }
 }
 
+// The plain passes over tiles of two halves (2 x 256 x ITEMS keys): each
+// half is loaded, ranked and staged in turn with the registers of one (in
+// every digit the second half's slots follow the first's), then the whole
+// tile is written out.  A tile's digit runs are twice as long as those of
+// the one-half tile at the same registers and blocks per CU, so fewer of
+// the lines they write are shared with a neighbouring tile.
+// (The staging buffer holds two blocks per CU, so the kernel is compiled
+// for two waves per SIMD.)
+template <int ITEMS, int MODE, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_downsweep_pair(SortLaunch a) {
+  static_assert(MODE == SORT_PLAIN || MODE == SORT_EDGE || MODE == SORT_IN, "plain passes only");
+  constexpr int BLOCK = 256;
+  constexpr int R = 1 << RB;
+  constexpr int DPT = R / BLOCK;
+  static_assert(R % BLOCK == 0, "whole digits per thread");
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int HALF = BLOCK * ITEMS;
+  constexpr int TILE = 2 * HALF;
+  static_assert(ITEMS <= 32, "one live bit per item");
+  typedef typename std::conditional<(RB > 8), uint16_t, uint32_t>::type hist_t;
+  static_assert(TILE < 65536, "16-bit slot bases");
+  __shared__ uint64_t s_stage[TILE];
+  __shared__ hist_t s_whist[WAVES * R];
+  __shared__ int64_t s_goff[R];
+  __shared__ uint32_t s_w[WAVES];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int shift = a.shift;
+  TileHeader H;
+  int64_t dbase[DPT];
+  uint32_t pfirst[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    dbase[j] = 0;
+    pfirst[j] = 0;
+  }
+  for (int i = tid; i < WAVES * R; i += BLOCK) s_whist[i] = 0;
+  __syncthreads();
+
+  // tiles in contiguous ranges per XCD, as in k_downsweep
+  const int xcd = blockIdx.x % NUM_XCD;
+  const int64_t per = gridDim.x / NUM_XCD;
+  const int64_t t_hi = a.total_tiles * (xcd + 1) / NUM_XCD;
+  for (int64_t tile = a.total_tiles * xcd / NUM_XCD + blockIdx.x / NUM_XCD; tile < t_hi;
+       tile += per) {
+    if (tile >= H.end) {
+      H.at(a, tile);
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+        dbase[j] = a.digit_base[(int64_t)H.seg * R + d];
+        pfirst[j] = a.counts[H.first * R + d];
+      }
+    }
+    const int64_t base = (tile - H.first) * (int64_t)TILE;
+    const int cnt = (int)std::max<int64_t>(0, std::min<int64_t>(TILE, H.count - base));
+
+    // the first half's keys are in flight while the digit bases are found
+    uint64_t keys[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int idx = wave * (ITEMS * 64) + i * 64 + lane;
+      keys[i] = pass_key<MODE>(a, H.P, H.start, base + (idx < cnt ? idx : 0));
+    }
+    uint32_t tdig = 0;
+    uint32_t dcnt[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = tid * DPT + j;
+      const uint32_t tp = a.counts[tile * R + d];
+      dcnt[j] = a.counts[(tile + 1) * R + d] - tp;
+      tdig += dcnt[j];
+      s_goff[d] = dbase[j] + (int64_t)(tp - pfirst[j]);
+    }
+    uint32_t tile_total;
+    const uint32_t lstart = block_excl_scan<BLOCK>(tdig, s_w, tile_total);
+    uint32_t next[DPT];  // next free slot of each of this thread's digits
+    {
+      uint32_t ls = lstart;
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        s_goff[tid * DPT + j] -= (int64_t)ls;
+        next[j] = ls;
+        ls += dcnt[j];
+      }
+    }
+
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int h0 = h * HALF + wave * (ITEMS * 64);  // this wave's first key of the half
+      if (h == 1) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+          const int idx = h0 + i * 64 + lane;
+          keys[i] = pass_key<MODE>(a, H.P, H.start, base + (idx < cnt ? idx : 0));
+        }
+      }
+      // stable rank inside the wave, as in k_downsweep
+      uint32_t rank[ITEMS];
+      uint32_t live_bits = 0;
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = h0 + i * 64 + lane < cnt;
+        live_bits |= (uint32_t)valid << i;
+        const uint32_t d = key_digit<MODE, RB>(keys[i], shift);
+        const uint64_t mv = __ballot(valid);
+        uint32_t alo = ~(uint32_t)mv, ahi = ~(uint32_t)(mv >> 32);
+#pragma unroll
+        for (int bit = 0; bit < RB; ++bit) {
+          const int32_t sb = __builtin_amdgcn_sbfe((int32_t)d, bit, 1);
+          const uint64_t bb = __ballot(sb < 0);
+          alo = __builtin_amdgcn_bitop3_b32((uint32_t)sb, alo, (uint32_t)bb, 0xDE);
+          ahi = __builtin_amdgcn_bitop3_b32((uint32_t)sb, ahi, (uint32_t)(bb >> 32), 0xDE);
+        }
+        const uint64_t m = ~(((uint64_t)ahi << 32) | alo);
+        const uint32_t below = lanes_below(m);
+        uint32_t rk = 0;
+        if (valid) {
+          const uint32_t old = s_whist[wave * R + d];
+          if (below == 0) s_whist[wave * R + d] = (hist_t)(old + (uint32_t)__popcll(m));
+          rk = old + below;
+        }
+        rank[i] = rk;
+      }
+      __syncthreads();
+      // this half's per-wave digit counts become slot bases
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const int d = tid * DPT + j;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+          const uint32_t c = s_whist[w * R + d];
+          s_whist[w * R + d] = (hist_t)next[j];
+          next[j] += c;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        if ((live_bits >> i) & 1u) {
+          const uint32_t d = key_digit<MODE, RB>(keys[i], shift);
+          s_stage[(uint32_t)s_whist[wave * R + d] + rank[i]] = keys[i];
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < WAVES * R; i += BLOCK) s_whist[i] = 0;
+      __syncthreads();
+    }
+
+    // write out the whole tile: consecutive threads take consecutive staged
+    // keys, so every digit run is stored contiguously
+#pragma unroll
+    for (int i = 0; i < 2 * ITEMS; ++i) {
+      const int p = i * BLOCK + tid;
+      if (p < (int)tile_total) {
+        const uint64_t k = s_stage[p];
+        const int64_t pos = s_goff[key_digit<MODE, RB>(k, shift)] + p;
+        if ((uint64_t)(pos - H.start) < (uint64_t)H.count) G(a.out)[pos] = k;  // in range by construction
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Blocks of the downsweep that fit on the device at once.  The occupancy
 // query is host work on the launch path of small tables, so its answer is
 // kept (per instantiation; the blocks per CU do not depend on the device
@@ -639,15 +803,33 @@ static int resident_t() {
   return nb * device_cu_count();
 }
 
-template <int ITEMS, int MODE, int RB>
-static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
+template <int RB>
+static int resident_pair() {
+  static std::atomic<int> per_cu{0};
+  int nb = per_cu.load(std::memory_order_relaxed);
+  if (nb == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_downsweep_pair<16, SORT_PLAIN, RB>,
+                                                     256, 0) != hipSuccess ||
+        nb < 1) {
+      (void)hipGetLastError();
+      nb = 1;
+    }
+    per_cu.store(nb, std::memory_order_relaxed);
+  }
+  return nb * device_cu_count();
+}
+
+// Counting parts of a pass over tiles of tile_keys keys: upsweep (or the
+// run sums of counts written elsewhere), scans and digit bases.
+template <int MODE, int RB>
+static void launch_counts(const SortLaunch &a, int tile_keys, int parts, hipStream_t s) {
   constexpr int R = 1 << RB;
   if (parts & (SORT_PART_COUNT | SORT_PART_PREFIX)) {
     const int rt = run_tiles_for(a.total_tiles);
     const int64_t runs = (a.total_tiles + rt - 1) / rt;
     if (parts & SORT_PART_COUNT)
       hipLaunchKernelGGL((k_upsweep<MODE, RB>), dim3((unsigned)runs), dim3(256), 0, s, a,
-                         256 * ITEMS, rt);
+                         tile_keys, rt);
     else if (a.total_tiles > SMALL_SCAN_TILES)
       hipLaunchKernelGGL(k_run_sums<RB>, dim3((unsigned)runs, R / 256), dim3(256), 0, s, a, rt);
     if (a.total_tiles <= SMALL_SCAN_TILES) {
@@ -659,6 +841,11 @@ static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
     }
     hipLaunchKernelGGL(k_seg_base<RB>, dim3(a.num_segs), dim3(256), 0, s, a);
   }
+}
+
+template <int ITEMS, int MODE, int RB>
+static hipError_t launch_pass_t(const SortLaunch &a, int parts, hipStream_t s) {
+  launch_counts<MODE, RB>(a, 256 * ITEMS, parts, s);
   if (parts & SORT_PART_SCATTER) {
     // four blocks per resident slot: blocks that finish early make room for
     // the next ones (measured faster than one persistent block per slot)
@@ -699,10 +886,38 @@ static hipError_t launch_pass_items(const SortLaunch &a, int mode, int parts, hi
   }
 }
 
+// Plain passes over two-half tiles (items code PAIR_ITEMS: 2 x 16 keys per
+// thread); the two halves' staging fits two blocks per CU up to 9-bit digits.
+template <int MODE, int RB>
+static hipError_t launch_pair_t(const SortLaunch &a, int parts, hipStream_t s) {
+  launch_counts<MODE, RB>(a, 2 * 256 * 16, parts, s);
+  if (parts & SORT_PART_SCATTER) {
+    const int64_t g = std::max<int64_t>(
+        NUM_XCD, std::min<int64_t>(a.total_tiles, 4 * resident_pair<RB>()) / NUM_XCD * NUM_XCD);
+    hipLaunchKernelGGL((k_downsweep_pair<16, MODE, RB>), dim3((unsigned)g), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int RB>
+static hipError_t launch_pair_items(const SortLaunch &a, int mode, int parts, hipStream_t s) {
+  if constexpr (RB <= 9) {
+    switch (mode) {
+      case SORT_PLAIN: return launch_pair_t<SORT_PLAIN, RB>(a, parts, s);
+      case SORT_EDGE: return launch_pair_t<SORT_EDGE, RB>(a, parts, s);
+      case SORT_IN: return launch_pair_t<SORT_IN, RB>(a, parts, s);
+      default: return hipErrorInvalidValue;  // the other modes use one-half tiles
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int RB>
 hipError_t launch_sort_part_rb(const SortLaunch &a, int mode, int items, int parts,
                                hipStream_t s) {
   switch (items) {
+    case PAIR_ITEMS: return launch_pair_items<RB>(a, mode, parts, s);
     case 8: return launch_pass_items<8, RB>(a, mode, parts, s);
     case 12: return launch_pass_items<12, RB>(a, mode, parts, s);
     default: return launch_pass_items<16, RB>(a, mode, parts, s);

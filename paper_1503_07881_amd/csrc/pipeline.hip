@@ -343,6 +343,19 @@ bool parts_for(int64_t slots, int64_t rows) {
   if (e >= 0) return e == 1;
   return slots >= PART_MIN_SLOTS && rows >= PART_MIN_ROWS_PER_SLOT * slots;
 }
+// The items code of the plain edge and in-passes: two-half tiles of 8192
+// keys where the schedule has 16 items and digits of at most 9 bits (whose
+// two halves' staging leaves room for two blocks per CU).  A 9-bit digit's
+// run per tile doubles from 8 to 16 keys, so fewer of the lines it writes
+// are shared with a neighbouring tile; 8192 divides the remap tile, so the
+// first edge pass still takes its counts from the remap.
+// RINGO_TILE_PAIRS=0 (test support) keeps one-half tiles.
+int pair_items(int items, int rb) {
+  const char *e = std::getenv("RINGO_TILE_PAIRS");
+  const bool on = !(e && *e && std::atoi(e) == 0);
+  return on && items == 16 && rb <= 9 ? PAIR_ITEMS : items;
+}
+
 // Whether a call of this many rows may take the partitioned numbering: its
 // distinct-count estimate then also counts the rows' parts.
 bool parts_possible(int64_t rows) {
@@ -355,7 +368,7 @@ bool parts_possible(int64_t rows) {
 
 enum TileKind {
   TM_NSORT, TM_UNIQ, TM_DIR, TM_REMAP, TM_ESORT, TM_DEDUP, TM_ISORT, TM_ICSR,
-  TM_HLL, TM_HCMP, TM_VSORT, TM_PART, TM_KINDS
+  TM_HLL, TM_HCMP, TM_VSORT, TM_PART, TM_IN0, TM_KINDS
 };
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -366,6 +379,8 @@ struct Call {
   AllocHooks hooks;
   int items = 16;
   int sort_tile = 4096;
+  int eitems = 16;      // items code of the plain edge and in-passes (PAIR_ITEMS: two-half tiles)
+  int esort_tile = 4096;
   int rb = DEFAULT_DIGIT_BITS;  // digit bits of the radix passes
   std::vector<SegPlan> plan;
   std::vector<int64_t> tmap;  // TM_KINDS x (S + 1)
@@ -660,13 +675,15 @@ void trace_set_bytes(long idx, double bytes) {
 // One radix pass of w-bit digits as two traced entries: counting (reads
 // every key) and scatter (reads and writes every key, plus extra bytes per
 // key).
-#define TRACED_PASS(kcount, kscatter, keys, extra, mode, a, w)                                  \
+#define TRACED_PASS_N(kcount, kscatter, keys, extra, mode, a, w, items)                         \
   do {                                                                                        \
     TRACED(kcount, keys, 8.0 * (keys),                                                        \
-           launch_sort_part(a, mode, c.items, (w), SORT_PART_COUNT, st));                     \
+           launch_sort_part(a, mode, (items), (w), SORT_PART_COUNT, st));                     \
     TRACED(kscatter, keys, (16.0 + (extra)) * (keys),                                         \
-           launch_sort_part(a, mode, c.items, (w), SORT_PART_SCATTER, st));                   \
+           launch_sort_part(a, mode, (items), (w), SORT_PART_SCATTER, st));                   \
   } while (0)
+#define TRACED_PASS(kcount, kscatter, keys, extra, mode, a, w) \
+  TRACED_PASS_N(kcount, kscatter, keys, extra, mode, a, w, c.items)
 
 int grid_for(int64_t tiles, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
@@ -823,6 +840,9 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
   const int R = 1 << c.rb;
   const bool want_hash = method_for(S == 1 ? max_rows : N) == RINGO_NODES_HASH;
   c.sort_tile = sort_tile(c.items);
+  // the plain edge and in-passes (not the multigraph's key-value passes)
+  c.eitems = c.kind == RINGO_GRAPH_MULTI ? c.items : pair_items(c.items, c.rb);
+  c.esort_tile = sort_tile(c.eitems);
   c.set_tiles(TM_NSORT, RANGE_NODE_KEYS, c.sort_tile);
   c.set_tiles(TM_UNIQ, RANGE_NODE_KEYS, SCAN_TILE);
   c.set_tiles(TM_HLL, RANGE_ROWS, HLL_TILE);
@@ -1080,7 +1100,8 @@ numbering:
   const bool undirected = c.kind == RINGO_GRAPH_UNDIRECTED, multi = c.kind == RINGO_GRAPH_MULTI;
   const int erange = undirected ? RANGE_NODE_KEYS : RANGE_ROWS;
   const int64_t NE = undirected ? 2 * N : N;
-  c.set_tiles(TM_ESORT, erange, c.sort_tile);
+  c.set_tiles(TM_ESORT, erange, c.esort_tile);
+  c.set_tiles(TM_IN0, erange, c.sort_tile);
   c.set_tiles(TM_DEDUP, erange, SCAN_TILE);
   HIP_TRY(c.upload());
 
@@ -1088,7 +1109,7 @@ numbering:
   // tile (directed and multigraph keys, sort tiles that divide its tiles);
   // that pass then starts from its prefixes.
   uint32_t *counts0 = hashed && !undirected && lsd_width(2 * b_max, c.rb, 0) == FUSED_RADIX_BITS &&
-                              REMAP_TILE % c.sort_tile == 0
+                              REMAP_TILE % c.esort_tile == 0
                           ? c.counts
                           : nullptr;
 
@@ -1126,7 +1147,7 @@ numbering:
            launch_sort_part(a, SORT_PART_RANK, c.items, PART_BITS, SORT_PART_SCATTER, st));
     TRACED(TK_HPACK, N, (undirected ? 28.0 : 20.0) * N,
            launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), yslot, spos, hrank, c.B,
-                                  undirected, counts0, c.sort_tile, c.tm_dev(TM_ESORT),
+                                  undirected, counts0, c.esort_tile, c.tm_dev(TM_ESORT),
                                   grid_for(c.total(TM_REMAP), cus * 8), st));
     dev_free(c.hooks, c.px, st);
     dev_free(c.hooks, c.py, st);
@@ -1134,7 +1155,7 @@ numbering:
   } else if (hashed) {
     TRACED(TK_HREMAP, N, 16.0 * N,
            launch_hash_remap(c.tiles(TM_REMAP, RANGE_ROWS), c.hslots, hrank, c.B, undirected,
-                             counts0, c.sort_tile, c.tm_dev(TM_ESORT),
+                             counts0, c.esort_tile, c.tm_dev(TM_ESORT),
                              grid_for(c.total(TM_REMAP), cus * 8), st));
   } else {
     TileLaunch dt = c.tiles(TM_DIR, RANGE_NODES);
@@ -1169,11 +1190,11 @@ numbering:
       const int mode = multi ? SORT_EDGE_KV : SORT_EDGE;
       if (p == 0 && counts0) {  // tile counts written by the remap
         TRACED(TK_EDGE_COUNT, NE, 0.0,
-               launch_sort_part(a, mode, c.items, w, SORT_PART_PREFIX, st));
+               launch_sort_part(a, mode, c.eitems, w, SORT_PART_PREFIX, st));
         TRACED(TK_EDGE_SCATTER, NE, (16.0 + (multi ? 8.0 : 0.0)) * NE,
-               launch_sort_part(a, mode, c.items, w, SORT_PART_SCATTER, st));
+               launch_sort_part(a, mode, c.eitems, w, SORT_PART_SCATTER, st));
       } else {
-        TRACED_PASS(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a, w);
+        TRACED_PASS_N(TK_EDGE_COUNT, TK_EDGE_SCATTER, NE, multi ? 8.0 : 0.0, mode, a, w, c.eitems);
       }
     }
   }
@@ -1185,7 +1206,7 @@ numbering:
   if (folded) {
     // Directed graphs: dedupe is folded into the first in-pass, which counts
     // only the first copy of every key; its per-table totals are E.
-    in0 = c.sort_args(sorted_edges, ukeys, TM_ESORT, RANGE_ROWS, P_in, 0, 32);
+    in0 = c.sort_args(sorted_edges, ukeys, TM_IN0, RANGE_ROWS, P_in, 0, 32);
     in0.seg_total = c.results + S;
     TRACED(TK_IN_COUNT, N, 8.0 * N,
            launch_sort_part(in0, SORT_IN_FIRST_DEDUP, c.items, lsd_width(b_max, c.rb, 0),
@@ -1251,7 +1272,7 @@ numbering:
     p.in_eid = multi ? (int32_t *)(a2 + off2[(size_t)narr * i + 3]) : nullptr;
     if (undirected) p.in_off = p.out_off;  // the adjacency is its own transpose
   }
-  c.set_tiles(TM_ISORT, RANGE_EDGES, c.sort_tile);
+  c.set_tiles(TM_ISORT, RANGE_EDGES, c.esort_tile);
   c.set_tiles(TM_ICSR, undirected ? RANGE_EDGES2 : RANGE_EDGES, SCAN_TILE);
   HIP_TRY(c.upload());
 
@@ -1272,7 +1293,8 @@ numbering:
     for (int p = 1; p < P_in; ++p) {
       SortLaunch a = c.sort_args(ib[(p - 1) & 1], ib[p & 1], TM_ISORT, RANGE_EDGES, P_in, p,
                                  32 + lsd_shift(b_max, c.rb, p));
-      TRACED_PASS(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a, lsd_width(b_max, c.rb, p));
+      TRACED_PASS_N(TK_IN_COUNT, TK_IN_SCATTER, sumE, 0.0, SORT_IN, a, lsd_width(b_max, c.rb, p),
+                    c.eitems);
     }
     TileLaunch it = c.tiles(TM_ICSR, RANGE_EDGES);
     it.gaps = c.gapq(2);
@@ -1898,8 +1920,8 @@ ringo_status_t sort_keys(const uint64_t *in, uint64_t *out, int64_t n, int bits,
   c.plan.assign(1, SegPlan{});
   c.plan[0].n = n;
   c.tmap.assign((size_t)TM_KINDS * 2, 0);
-  c.items = items_for(n);
   c.rb = digit_bits_for(n);
+  c.items = pair_items(items_for(n), c.rb);
   const int R = 1 << c.rb;
   c.sort_tile = sort_tile(c.items);
   c.set_tiles(TM_ESORT, RANGE_ROWS, c.sort_tile);

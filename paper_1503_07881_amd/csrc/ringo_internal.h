@@ -201,6 +201,9 @@ inline int run_tiles_for(int64_t tiles) {
   return rt;
 }
 int sort_tile(int items);
+// Items code of the plain passes' two-half tiles: 2 x 16 keys per thread,
+// sort_tile(PAIR_ITEMS) = 8192 keys per tile.
+constexpr int PAIR_ITEMS = 32;
 int64_t sort_runs(int64_t tiles);
 int64_t sort_runs_bound(int64_t max_tiles);  // >= sort_runs(t) for every t <= max_tiles
 // Distinct sorted node keys of every table into out, their count into

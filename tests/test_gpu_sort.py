@@ -161,3 +161,48 @@ def test_digit_widths_scan_paths(cuda, n):
         say("sort_keys 11-bit digits, scan boundary n", n)
         keys = keys_of("few", n, 30, rng)
         assert np.array_equal(run(keys, 30, cuda), expected(keys, 30, 11))
+
+
+@contextlib.contextmanager
+def schedule(digit, items):
+    """Every size bucket on `digit`-bit digits and `items` keys per thread,
+    restored after."""
+    saved = [ringo.tune_get(1 << e) for e in range(63)]
+    try:
+        for e, (_, _, m) in enumerate(saved):
+            ringo.tune_set(1 << e, digit, items, m)
+        yield
+    finally:
+        for e, (d, it, m) in enumerate(saved):
+            ringo.tune_set(1 << e, d, it, m)
+
+
+PAIR_TILE = 2 * 256 * 16  # two halves of 256 threads x 16 keys
+
+
+@pytest.mark.parametrize("digit", [8, 9])
+def test_two_half_tiles(cuda, digit):
+    """16 keys per thread with digits of at most 9 bits: the plain passes
+    stage each 8192-key tile as two halves, ranked one after the other.
+    Sizes around both tile sizes and a half, key widths, distributions."""
+    rng = np.random.default_rng(8000 + digit)
+    with schedule(digit, 16):
+        for n in (1, 2, 4095, 4096, 4097, PAIR_TILE - 1, PAIR_TILE, PAIR_TILE + 1, 3 * PAIR_TILE + 17,
+                  300_007):
+            for bits in (1, digit, digit + 1, 17, 44, 64):
+                for kind in ("uniform", "few"):
+                    say("sort_keys two-half tiles digit", digit, "n", n, "bits", bits, kind)
+                    keys = keys_of(kind, n, bits, rng)
+                    assert np.array_equal(run(keys, bits, cuda), expected(keys, bits, digit)), (n, bits, kind)
+        keys = keys_of("equal", 100_003, 3 * digit, rng)
+        assert np.array_equal(run(keys, 3 * digit, cuda), keys)
+
+
+@pytest.mark.parametrize("n", [4096 * PAIR_TILE - 1, 4096 * PAIR_TILE + 1])
+def test_two_half_tiles_scan_paths(cuda, n):
+    """Both scan kernels over 8192-key tiles."""
+    rng = np.random.default_rng(9000 + n % 7)
+    with schedule(9, 16):
+        say("sort_keys two-half tiles, scan boundary n", n)
+        keys = keys_of("few", n, 27, rng)
+        assert np.array_equal(run(keys, 27, cuda), expected(keys, 27, 9))
