@@ -174,6 +174,9 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
       if ((cnt & 1) && lane == 0)
         atomicAdd(&h[key_digit<MODE, RB>(G(a.in)[H.start + k1 - 1], shift) * SUB], 1u);
     } else {
+      // DEDUP: lane 63's key of the previous group of rows, the predecessor
+      // of lane 0's first key in the next group
+      uint64_t carry = 0;
       for (int64_t e0 = k0 + lane; e0 < k1; e0 += U * 64) {
         uint64_t k[U];
 #pragma unroll
@@ -184,14 +187,21 @@ __global__ __launch_bounds__(256) void k_upsweep(SortLaunch a, int tile_keys, in
           const int64_t e = e0 + j * 64;
           bool valid = e < k1;
           if (MODE == SORT_IN_FIRST_DEDUP) {
-            // only the first copy of every key counts
+            // only the first copy of every key counts; lane 0's predecessor
+            // is lane 63's key of the row above (a shuffle, or the carry of
+            // the previous group), read from memory only for the tile's
+            // first row (the keys are read non-temporally, so a second read
+            // of a line goes to memory again)
             uint64_t prev = __shfl_up(k[j], 1, 64);
-            // lane 0 reads its predecessor, only for elements inside the tile
-            if (lane == 0) prev = (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
+            const uint64_t above = j > 0 ? __shfl(k[j > 0 ? j - 1 : 0], 63, 64) : carry;
+            if (lane == 0)
+              prev = e != k0 ? above
+                             : (e > 0 && e < k1) ? pass_key<MODE>(a, H.P, H.start, e - 1) : ~k[j];
             valid = valid && (e == 0 || k[j] != prev);
           }
           if (valid) atomicAdd(&h[key_digit<MODE, RB>(k[j], shift) * SUB], 1u);
         }
+        if (MODE == SORT_IN_FIRST_DEDUP) carry = __shfl(k[U - 1], 63, 64);
       }
     }
     __builtin_amdgcn_s_waitcnt(LGKMCNT_0);
