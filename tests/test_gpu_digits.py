@@ -143,3 +143,34 @@ def test_rmat_large(cuda, bits):
         with numbering(method) as m, schedule(bits, method=m):
             g = ringo.to_graph(to_dev(src, cuda), to_dev(dst, cuda))
         assert_same_kind(g, want, ringo.GRAPH_DIRECTED, f"bits {bits} method {method}: ")
+
+
+@contextlib.contextmanager
+def tile_pairs(on):
+    """RINGO_TILE_PAIRS: the plain edge and in-passes of 16-key schedules on
+    two-half 8192-key tiles (on, the default) or one-half 4096-key tiles."""
+    import os
+    os.environ["RINGO_TILE_PAIRS"] = "1" if on else "0"
+    try:
+        yield
+    finally:
+        os.environ.pop("RINGO_TILE_PAIRS", None)
+
+
+@pytest.mark.parametrize("bits", [8, 9])
+def test_tile_halves(cuda, bits):
+    """16 keys per thread with 8- or 9-bit digits: the plain passes on
+    two-half tiles and on one-half tiles give the oracle's graph, for the
+    directed and undirected kinds (the multigraph's key-value passes keep
+    one-half tiles) and every numbering; a ragged last tile."""
+    spec = workloads.TableSpec("rmat", (1 << 19) + 4097, seed=73, scale=16)
+    src, dst = workloads.generate_host(spec)
+    for kname in ("directed", "undirected"):
+        kind, okind = KINDS[kname]
+        want = oracle.table_to_graph_kind(src, dst, okind)
+        for method in (ringo.NODES_SORT, ringo.NODES_HASH, "parts"):
+            for on in (True, False):
+                say("R-MAT 2^19 + 4097 rows, digit bits", bits, "16 items", kname, "method", method, "pairs", on)
+                with tile_pairs(on), numbering(method) as m, schedule(bits, items=16, method=m):
+                    g = ringo.to_graph(to_dev(src, cuda), to_dev(dst, cuda), kind=kind)
+                    assert_same_kind(g, want, kind, f"bits {bits} {kname} method {method} pairs {on}: ")
