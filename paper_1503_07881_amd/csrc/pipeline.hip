@@ -975,12 +975,17 @@ ringo_status_t run(Call &c, const int64_t *const *src, const int64_t *const *dst
       SortLaunch d = c.part_args(c.px + N, c.py);
       TRACED_PASS(TK_HPART_COUNT, TK_HPART_DST, N, 0.0, SORT_PART_DST, d, PART_BITS);
       uint32_t *xslot = (uint32_t *)(c.py + N) + N, *yslot = xslot + N;
+      // The grouped kernels' grids set how many keys an XCD has in flight,
+      // hence how many parts' table or rank slices share its L2 at once:
+      // at 1.5e9 rows 4 blocks per CU suit the inserts (12.7 against 13.2 ms
+      // at 8, 15.0 at 2) and the pack (10.35 against 10.6), 2 the position
+      // gather (7.3 against 8.3 at 4 and 8.85 at 8).
       TRACED(TK_HINSERT, N, 20.0 * N,
              launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.px, hkeys, xslot, hflags,
-                                     grid_for(c.total(TM_REMAP), cus * 8), st));
+                                     grid_for(c.total(TM_REMAP), cus * 4), st));
       TRACED(TK_HINSERT, N, 20.0 * N,
              launch_hash_insert_keys(c.tiles(TM_REMAP, RANGE_ROWS), c.py, hkeys, yslot, hflags,
-                                     grid_for(c.total(TM_REMAP), cus * 8), st));
+                                     grid_for(c.total(TM_REMAP), cus * 4), st));
     } else {
       TRACED(TK_HINSERT, 2 * N, 24.0 * N,
              launch_hash_insert(c.tiles(TM_REMAP, RANGE_ROWS), hkeys, c.hslots, hflags,
@@ -1139,7 +1144,7 @@ numbering:
     uint32_t *yslot = xpos + N;                // destination slots, grouped
     TRACED(TK_HRANK_KEYS, N, 12.0 * N,
            launch_hash_rank_slots(c.tiles(TM_REMAP, RANGE_ROWS), xpos, hrank,
-                                  grid_for(c.total(TM_REMAP), cus * 8), st));
+                                  grid_for(c.total(TM_REMAP), cus * 2), st));
     SortLaunch a = c.part_args(c.px + N, nullptr);
     a.vin = xpos;
     a.vout = spos;
@@ -1148,7 +1153,7 @@ numbering:
     TRACED(TK_HPACK, N, (undirected ? 28.0 : 20.0) * N,
            launch_hash_pack_parts(c.tiles(TM_REMAP, RANGE_ROWS), yslot, spos, hrank, c.B,
                                   undirected, counts0, c.esort_tile, c.tm_dev(TM_ESORT),
-                                  grid_for(c.total(TM_REMAP), cus * 8), st));
+                                  grid_for(c.total(TM_REMAP), cus * 4), st));
     dev_free(c.hooks, c.px, st);
     dev_free(c.hooks, c.py, st);
     c.px = c.py = nullptr;
