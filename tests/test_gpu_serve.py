@@ -110,22 +110,30 @@ def test_batched_budget_frees_what_it_counts(cuda):
     as resident are exactly the live blocks a caller's allocator handed out;
     evictions happened; a graph pinned all along was never evicted, and its
     view, read on the client's stream while other graphs were evicted,
-    equals the oracle's graph."""
+    equals the oracle's graph.  The budget (32 MB) lies just above the
+    largest request's admission footprint (28.5 MB for 143,444 rows), and
+    that request comes last: the graphs resident by then (about 15 MB) and
+    its footprint exceed the budget, so the server must evict however its
+    batches overlapped, while the pinned graph and it still fit."""
     import torch
     from test_gpu_alloc import CountingAllocator
     specs = [workloads.mixed_table(60, i, 3_000, 150_000) for i in range(40)]
     tables = pinned_tables(specs)
+    big = max(range(1, len(specs)), key=lambda i: specs[i].n)
+    budget = 32 << 20
     al = CountingAllocator(cuda)
     al.install()
     try:
-        with serve.Server(budget_bytes=80 << 20, num_streams=2, max_batch_tables=6,
+        with serve.Server(budget_bytes=budget, num_streams=2, max_batch_tables=6,
                           max_batch_rows=400_000) as srv:
             first = srv.submit(*tables[0])
             assert srv.wait(first)[0] == 0
             rc, view = srv.pin(first)
             assert rc == 0
-            say("serve: 39 more requests under an 80 MB budget, first graph pinned")
-            ids = [first] + [srv.submit(s, d) for s, d in tables[1:]]
+            say("serve: 39 more requests under a 32 MB budget, first graph pinned, the largest last")
+            ids = [first] + [None] * (len(tables) - 1)
+            for i in [i for i in range(1, len(tables)) if i != big] + [big]:
+                ids[i] = srv.submit(*tables[i])
             for rid in ids:
                 rc, _, _ = srv.wait(rid)
                 assert rc in (0, ringo.STATUS_EVICTED), rc
@@ -141,7 +149,7 @@ def test_batched_budget_frees_what_it_counts(cuda):
             say("serve: stats", st, "evicted", states.count(ringo.STATUS_EVICTED))
             assert st["completed"] == 40 and st["failed"] == 0
             assert st["evicted"] >= 1 and states.count(ringo.STATUS_EVICTED) == st["evicted"]
-            assert st["resident_bytes"] <= 80 << 20
+            assert st["resident_bytes"] <= budget
             torch.cuda.synchronize()
             live = sum(al.live.values())
             assert st["resident_bytes"] == live, (st["resident_bytes"], live)
