@@ -15,8 +15,6 @@
 //   seg base     every table's digit bases
 //   downsweep    wave-ballot stable rank inside the tile, LDS staging in
 //                digit order, contiguous write-out of every digit run
-//                (the plain passes of 16-key schedules: k_downsweep_pair,
-//                tiles of two halves ranked and staged one after the other)
 // No block waits on another.  Tiles in flight are always neighbours in
 // the input, so the runs they write land next to each other in every
 // digit's output range.  Prefixes are 32-bit and wrap: only differences
